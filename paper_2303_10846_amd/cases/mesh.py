@@ -1,0 +1,359 @@
+"""Seeded tetrahedral meshes for the synthetic workloads.
+
+This module only builds inputs: node coordinates, tetrahedra, tagged boundary
+triangles and a colour-major cell order.  It holds none of the scheme's
+arithmetic (no face geometry, no fluxes); the solver library and the CPU
+oracle each derive their own geometry from these arrays.
+
+Boundary tags used by the case definitions:
+    1  solid wall (diffuse reflection)
+    2  second wall group (cavity lid) or far field (external flows)
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+__all__ = [
+    "kuhn_box_mesh",
+    "shell_mesh",
+    "sphere_body",
+    "capsule_body",
+    "color_major",
+    "boundary_triangles",
+    "tet_volumes",
+]
+
+
+def tet_volumes(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
+    """Signed volumes (positive for right-handed vertex order)."""
+    a = xyz[tets[:, 0]]
+    d1 = xyz[tets[:, 1]] - a
+    d2 = xyz[tets[:, 2]] - a
+    d3 = xyz[tets[:, 3]] - a
+    return np.einsum("ij,ij->i", d1, np.cross(d2, d3)) / 6.0
+
+
+def _orient(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
+    v = tet_volumes(xyz, tets)
+    tets = tets.copy()
+    neg = v < 0
+    tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    return tets
+
+
+def _face_keys(tets: np.ndarray) -> np.ndarray:
+    """The 4 faces of every tet as sorted vertex triples, shape [4*nt, 3]."""
+    loc = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]])
+    f = tets[:, loc].reshape(-1, 3)
+    return np.sort(f, axis=1)
+
+
+def _match_faces(tets: np.ndarray):
+    """Returns (pairs [n_int,2] of tet ids sharing a face, boundary keys [n_b,3])."""
+    keys = _face_keys(tets)
+    owner = np.repeat(np.arange(len(tets)), 4)
+    order = np.lexsort((keys[:, 2], keys[:, 1], keys[:, 0]))
+    ks = keys[order]
+    same = np.all(ks[1:] == ks[:-1], axis=1)
+    if np.any(same[1:] & same[:-1]):
+        raise ValueError("non-manifold mesh: a face is shared by more than two tets")
+    first = np.nonzero(same)[0]
+    pairs = np.stack([owner[order[first]], owner[order[first + 1]]], axis=1)
+    in_pair = np.zeros(len(ks), dtype=bool)
+    in_pair[first] = True
+    in_pair[first + 1] = True
+    bkeys = ks[~in_pair]
+    return pairs, bkeys
+
+
+def boundary_triangles(tets: np.ndarray) -> np.ndarray:
+    return _match_faces(tets)[1]
+
+
+def color_major(xyz: np.ndarray, tets: np.ndarray):
+    """Greedy first-fit colouring of the face-adjacency graph and colour-major renumbering.
+
+    Cells are first put in Morton order of their centroids (locality), coloured
+    greedily in that order, then stably sorted by colour.  Returns
+    (tets_reordered, color_offsets) with color_offsets[c]..color_offsets[c+1]
+    the cells of colour c.  No two cells of one colour share a face.
+    """
+    nt = len(tets)
+    cen = xyz[tets].mean(axis=1)
+    lo = cen.min(axis=0)
+    span = np.maximum(cen.max(axis=0) - lo, 1e-300)
+    q = np.minimum(((cen - lo) / span * 1023.0).astype(np.int64), 1023)
+    code = np.zeros(nt, dtype=np.int64)
+    for b in range(10):
+        for ax in range(3):
+            code |= ((q[:, ax] >> b) & 1) << (3 * b + ax)
+    morton = np.argsort(code, kind="stable")
+    tets = tets[morton]
+
+    pairs, _ = _match_faces(tets)
+    nbr = [[] for _ in range(nt)]
+    for a, b in pairs.tolist():
+        nbr[a].append(b)
+        nbr[b].append(a)
+    color = np.full(nt, -1, dtype=np.int64)
+    for i in range(nt):
+        used = {color[j] for j in nbr[i] if color[j] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        color[i] = c
+    order = np.argsort(color, kind="stable")
+    ncol = int(color.max()) + 1
+    offsets = np.zeros(ncol + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(np.bincount(color, minlength=ncol))
+    return np.ascontiguousarray(tets[order]), offsets
+
+
+# --------------------------------------------------------------------------
+# Box meshes (Kuhn split of a structured hexahedral grid)
+# --------------------------------------------------------------------------
+
+_KUHN = [p for p in itertools.permutations(range(3))]
+
+
+def kuhn_box_mesh(n: int = 6, seed: int = 0, jitter: float = 0.15, length: float = 1.0,
+                  tag_of_plane=None):
+    """n^3 hexahedra on [0,L]^3, each split into 6 tets along the main diagonal.
+
+    The split follows a coordinate permutation per tet (Kuhn/Freudenthal), so
+    it is conforming across hexahedra.  Interior nodes are jittered by
+    U(-jitter*h, jitter*h)^3 drawn from ``numpy.random.default_rng(seed)``; a
+    draw that makes any tet volume non-positive is rejected and redrawn.
+
+    ``tag_of_plane(axis, side) -> tag`` gives each of the six box faces a tag;
+    the default tags the z = L plane 2 and the five others 1.
+    """
+    if tag_of_plane is None:
+        def tag_of_plane(axis, side):
+            return 2 if (axis == 2 and side == 1) else 1
+    h = length / n
+    m = n + 1
+    g = np.arange(m) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    xyz0 = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+    def nid(i, j, k):
+        return (i * m + j) * m + k
+
+    tets = []
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                base = np.array([i, j, k])
+                for perm in _KUHN:
+                    v = [base.copy()]
+                    cur = base.copy()
+                    for ax in perm:
+                        cur = cur.copy()
+                        cur[ax] += 1
+                        v.append(cur)
+                    tets.append([nid(*p) for p in v])
+    tets = np.array(tets, dtype=np.int64)
+
+    ijk = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"), -1).reshape(-1, 3)
+    interior = np.all((ijk > 0) & (ijk < n), axis=1)
+    rng = np.random.default_rng(seed)
+    for _ in range(100):
+        xyz = xyz0.copy()
+        d = rng.uniform(-jitter * h, jitter * h, size=(int(interior.sum()), 3))
+        xyz[interior] += d
+        tets_o = _orient(xyz, tets)
+        if np.all(tet_volumes(xyz, tets_o) > 0):
+            break
+    else:
+        raise RuntimeError("could not draw a valid jitter")
+
+    tets_c, offsets = color_major(xyz, tets_o)
+    bkeys = boundary_triangles(tets_c)
+    tags = np.zeros(len(bkeys), dtype=np.int64)
+    fc = xyz[bkeys].mean(axis=1)
+    for ax in range(3):
+        for side in (0, 1):
+            on = np.abs(fc[:, ax] - side * length) < 1e-12 * max(length, 1.0)
+            tags[on] = tag_of_plane(ax, side)
+    if np.any(tags == 0):
+        raise RuntimeError("unclassified boundary triangle")
+    return dict(xyz=xyz, tets=tets_c, btri=bkeys, btag=tags, color_offsets=offsets)
+
+
+# --------------------------------------------------------------------------
+# Shell meshes around star-shaped bodies (cubed-sphere O-grid)
+# --------------------------------------------------------------------------
+
+def sphere_body(radius: float = 0.5):
+    def inside(p):
+        return np.einsum("ij,ij->i", p, p) <= radius * radius
+    return inside, np.zeros(3)
+
+
+def capsule_body(diameter: float = 1.0, nose_radius: float = 1.2, cone_half_angle_deg: float = 33.0,
+                 base_radius_frac: float = 0.4):
+    """Spherical-cap forebody facing -x plus a conical aftbody, cut by a flat base.
+
+    Convex, hence star-shaped about an interior point; returns (inside(p), centre).
+    """
+    rmax = 0.5 * diameter
+    depth = nose_radius - math.sqrt(nose_radius ** 2 - rmax ** 2)
+    x_s = depth
+    t = math.tan(math.radians(cone_half_angle_deg))
+    x_back = x_s + (rmax - base_radius_frac * rmax) / t
+    cball = np.array([nose_radius, 0.0, 0.0])
+
+    def inside(p):
+        r = np.hypot(p[:, 1], p[:, 2])
+        in_ball = np.einsum("ij,ij->i", p - cball, p - cball) <= nose_radius ** 2
+        in_cone = r <= rmax - (p[:, 0] - x_s) * t
+        return in_ball & in_cone & (p[:, 0] <= x_back) & (p[:, 0] >= 0.0)
+
+    centre = np.array([0.5 * (x_s + x_back) * 0.6, 0.0, 0.0])
+    return inside, centre
+
+
+def _ray_hit(inside, centre, dirs, rmax=10.0, iters=60):
+    lo = np.zeros(len(dirs))
+    hi = np.full(len(dirs), rmax)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        ins = inside(centre + dirs * mid[:, None])
+        lo = np.where(ins, mid, lo)
+        hi = np.where(ins, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+def _cubed_sphere_dirs(n: int):
+    """Unique directions of an equiangular cubed sphere and the 6 patch index grids."""
+    a = np.tan(0.25 * np.pi * np.linspace(-1.0, 1.0, n + 1))
+    A, B = np.meshgrid(a, a, indexing="ij")
+    patches = []
+    for ax in range(3):
+        for sgn in (1.0, -1.0):
+            v = np.zeros((n + 1, n + 1, 3))
+            o = [x for x in range(3) if x != ax]
+            v[..., ax] = sgn
+            # keep each patch right-handed when viewed from outside
+            if sgn > 0:
+                v[..., o[0]] = A
+                v[..., o[1]] = B
+            else:
+                v[..., o[0]] = B
+                v[..., o[1]] = A
+            v /= np.linalg.norm(v, axis=-1, keepdims=True)
+            patches.append(v)
+    allv = np.concatenate([p.reshape(-1, 3) for p in patches])
+    key = np.round(allv * 1e9).astype(np.int64)
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    dirs = allv[first]
+    idx = inv.reshape(6, n + 1, n + 1)
+    return dirs, idx
+
+
+def shell_mesh(body, n_ang: int, n_rad: int, r_far: float, first_layer: float, seed: int = 0,
+               jitter: float = 0.1):
+    """Graded tetrahedral shell between a star-shaped body and a far-field sphere.
+
+    Nodes sit on rays of an equiangular cubed sphere; along each ray the layers
+    grow geometrically from ``first_layer`` at the wall to the far-field radius.
+    Each hexahedron is split into 6 pyramids on its centre, and every pyramid
+    base is cut along the diagonal through its lowest-numbered node, so the
+    12-tet split is conforming.  Interior layer nodes get an isotropic
+    U(-j, j)^3 jitter scaled by the local radial spacing.
+    Tags: 1 = wall, 2 = far field.
+    """
+    inside, centre = body
+    dirs, pidx = _cubed_sphere_dirs(n_ang)
+    rb = _ray_hit(inside, centre, dirs, rmax=r_far)
+    # geometric grading on the unit interval with a first step first_layer/(r_far-mean rb)
+    span = r_far - rb.mean()
+    f = first_layer / span
+    if f * n_rad >= 1.0:
+        q = 1.0
+    else:
+        lo_q, hi_q = 1.0 + 1e-12, 10.0
+        for _ in range(200):
+            mq = 0.5 * (lo_q + hi_q)
+            if f * (mq ** n_rad - 1.0) / (mq - 1.0) > 1.0:
+                hi_q = mq
+            else:
+                lo_q = mq
+        q = 0.5 * (lo_q + hi_q)
+    if q == 1.0:
+        xi = np.linspace(0.0, 1.0, n_rad + 1)
+    else:
+        xi = (q ** np.arange(n_rad + 1) - 1.0) / (q ** n_rad - 1.0)
+    nd = len(dirs)
+    rad = rb[:, None] + (r_far - rb)[:, None] * xi[None, :]
+    xyz = (centre[None, None, :] + dirs[:, None, :] * rad[:, :, None]).reshape(-1, 3)
+
+    def nid(d, k):
+        return d * (n_rad + 1) + k
+
+    rng = np.random.default_rng(seed)
+    layer = np.tile(np.arange(n_rad + 1), nd)
+    interior = (layer > 0) & (layer < n_rad)
+    dr = np.zeros(len(xyz))
+    rr = rad.reshape(-1)
+    kk = layer
+    # local radial spacing = min of adjacent layer gaps
+    radm = rad
+    gaps = np.diff(radm, axis=1)
+    loc = np.full(rad.shape, np.inf)
+    loc[:, 1:] = np.minimum(loc[:, 1:], gaps)
+    loc[:, :-1] = np.minimum(loc[:, :-1], gaps)
+    dr = loc.reshape(-1)
+    del rr, kk
+
+    hexes = []
+    for p in range(6):
+        P = pidx[p]
+        for i in range(n_ang):
+            for j in range(n_ang):
+                d00, d10, d11, d01 = P[i, j], P[i + 1, j], P[i + 1, j + 1], P[i, j + 1]
+                for k in range(n_rad):
+                    hexes.append([nid(d00, k), nid(d10, k), nid(d11, k), nid(d01, k),
+                                  nid(d00, k + 1), nid(d10, k + 1), nid(d11, k + 1), nid(d01, k + 1)])
+    hexes = np.array(hexes, dtype=np.int64)
+    quads = np.array([[0, 1, 2, 3], [4, 5, 6, 7], [0, 1, 5, 4], [1, 2, 6, 5], [2, 3, 7, 6], [3, 0, 4, 7]])
+
+    for _attempt in range(50):
+        xj = xyz.copy()
+        d = rng.uniform(-jitter, jitter, size=(int(interior.sum()), 3)) * dr[interior, None]
+        xj[interior] += d
+        nn = len(xj)
+        centres = xj[hexes].mean(axis=1)
+        allxyz = np.concatenate([xj, centres])
+        cid = nn + np.arange(len(hexes))
+        tets = []
+        for qd in quads:
+            v = hexes[:, qd]  # [nh,4] quad in cyclic order
+            m = np.argmin(v, axis=1)
+            r = (np.arange(4)[None, :] + m[:, None]) % 4
+            vr = np.take_along_axis(v, r, axis=1)  # rotated so vr[:,0] is the lowest id
+            tets.append(np.stack([vr[:, 0], vr[:, 1], vr[:, 2], cid], axis=1))
+            tets.append(np.stack([vr[:, 0], vr[:, 2], vr[:, 3], cid], axis=1))
+        tets = np.concatenate(tets)
+        tets = _orient(allxyz, tets)
+        vol = tet_volumes(allxyz, tets)
+        if np.all(vol > 1e-14):
+            break
+    else:
+        raise RuntimeError("shell mesh: non-positive tet volume after 50 jitter draws")
+
+    tets_c, offsets = color_major(allxyz, tets)
+    bkeys = boundary_triangles(tets_c)
+    lay = np.concatenate([layer, np.full(len(hexes), -1)])
+    bl = lay[bkeys]
+    tags = np.zeros(len(bkeys), dtype=np.int64)
+    tags[np.all(bl == 0, axis=1)] = 1
+    tags[np.all(bl == n_rad, axis=1)] = 2
+    if np.any(tags == 0):
+        raise RuntimeError("shell mesh: unclassified boundary triangle")
+    return dict(xyz=allxyz, tets=tets_c, btri=bkeys, btag=tags, color_offsets=offsets,
+                wall_radius=rb, centre=centre)
