@@ -1,0 +1,151 @@
+"""Throughput of one implicit iteration (Steps 2-6) on one MI355X.
+
+Workload: Ma 5 flow over a sphere (Kn 0.1, Tw/T_inf = 3) on a ~50k-tet graded mesh with a ~4k-point
+unstructured DVS, started from rest.  Metric: cell-velocity updates per second per implicit iteration,
+for the mixed-precision path (FP32 distributions and flux kernels, FP64 compensated moments, macro update and
+implicit diagonal) and the FP64 path.  Inputs are generated on the host, copied to HBM before the timed
+region; the timed region is K calls' worth of iterations on the GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(nc, nf, nv, es, n_micro):
+    """Algorithmic HBM bytes of one iteration per stage (each value moved once)."""
+    return {
+        "recon": (2 * nc + 2 * nf) * nv * es,          # read phi (G, R); write phi_bar for every (face, velocity)
+        "face": 4 * nf * nv * es,                      # read phi_bar; write A (u.n) phi_f
+        "residual": (2 * nf + 4 * nc) * nv * es,       # read face fluxes and phi; write Res
+        "micro": 2 * n_micro * 6 * nc * nv * es,       # per half-sweep: read Res, neighbour dphi; write dphi
+        "update": 6 * nc * nv * es,                    # read phi, dphi; write phi
+    }
+
+
+def run_path(case, precision, steps, warmup):
+    import torch
+
+    from paper_2303_10846_amd.binding import Solver
+    s = Solver(case, precision=precision, device="cuda:0")
+    s.init_equilibrium(case["W0"])
+    if warmup:
+        s.iterate(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = s.iterate(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # stage times with hipEvents on the solver's stream, over a second timed region of the same length
+    s.profile(True)
+    s.iterate(steps)
+    prof = s.profile_read()
+    s.profile(False)
+    W, q = s.moments()
+    Qw = s.wall_heat_flux(1)
+    pairs = s.nc * s.nv
+    es = 8 if precision == "fp64" else 4
+    sb = stage_bytes(s.nc, s.nf, s.nv, es, case["num"]["n_micro"])
+    stages = {}
+    for k, (ms, nl) in prof.items():
+        e = dict(ms_per_iter=ms / steps, launches_per_iter=nl / steps)
+        if k in sb:
+            e["algorithmic_GB_per_iter"] = sb[k] / 1e9
+            e["achieved_GBs"] = sb[k] * steps / (ms * 1e-3) / 1e9 if ms > 0 else None
+        stages[k] = e
+    hbm = {k: v for k, v in stages.items() if k in sb}
+    dom = max(hbm, key=lambda k: hbm[k]["ms_per_iter"])
+    ach = hbm[dom]["achieved_GBs"]
+    roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    out = dict(value=pairs * steps / t, ms_per_step=1e3 * t / steps, pairs=pairs, n_cells=s.nc, n_faces=s.nf,
+               n_vel=s.nv, residual_last=float(hist[-1].max()), stages=stages, roofline=roof, Qw=Qw, W=W)
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(case, stride=8, iters=2):
+    """The oracle on the sphere mesh with every `stride`-th velocity (a bounded sample), timed per iteration."""
+    import oracle
+    c = dict(case, u=case["u"][::stride], w=case["w"][::stride] * stride)
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    t0 = time.perf_counter()
+    o.iterate(iters)
+    t = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    pairs = o.nc * o.nv
+    return {"value": pairs * iters / t, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"sphere mesh {o.nc} tets x every {stride}th DVS point ({o.nv} of {len(case['u'])}), "
+                      f"{iters} FP64 iterations from rest, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the DVS-sharded multi-GPU path is a design, not code); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    from paper_2303_10846_amd.cases import configs
+    case = configs.sphere_case(seed=0)
+    print(f"bench: {case['name']} tets={len(case['mesh']['tets'])} nv={len(case['u'])}", file=sys.stderr, flush=True)
+    res = {}
+    for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+        print(f"bench: timing {prec}", file=sys.stderr, flush=True)
+        res[prec] = run_path(case, prec, args.steps, args.warmup)
+        print(f"bench: {prec} {res[prec]['ms_per_step']:.2f} ms/iter", file=sys.stderr, flush=True)
+    main_key = "mixed" if "mixed" in res else "fp64"
+    r = res[main_key]
+    line = {
+        "metric": "cell-velocity updates/s per implicit iteration",
+        "value": r["value"], "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if main_key == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "sphere Ma 5 Kn 0.1 Tw/Tinf 3, graded tets x unstructured DVS, from rest",
+                   "n_cells": r["n_cells"], "n_faces": r["n_faces"], "n_vel": r["n_vel"], "pairs": r["pairs"],
+                   "precision": main_key, "n_macro_sweeps": case["num"]["n_macro"],
+                   "n_micro_sweeps": case["num"]["n_micro"]},
+        "roofline": r["roofline"],
+        "stages": r["stages"],
+    }
+    if "fp64" in res and main_key != "fp64":
+        f = res["fp64"]
+        line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "roofline": f["roofline"],
+                        "stages": f["stages"]}
+        Wm, Wd = r["W"], f["W"]
+
+        def rho_T(W):
+            rho = W[:, 0]
+            ke = 0.5 * np.sum(W[:, 1:4] ** 2, axis=1) / rho
+            return rho, 0.4 * (W[:, 4] - ke) / (rho * 0.5)
+
+        rm, Tm = rho_T(Wm)
+        rd, Td = rho_T(Wd)
+        line["mixed_vs_fp64_after_same_iterations"] = {
+            "rho": float(np.max(np.abs(rm - rd)) / np.max(np.abs(rd))),
+            "T": float(np.max(np.abs(Tm - Td)) / np.max(np.abs(Td))),
+            "Qw": abs(r["Qw"] - f["Qw"]) / abs(f["Qw"]),
+            "iterations": args.warmup + 2 * args.steps}
+    if not args.no_cpu:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

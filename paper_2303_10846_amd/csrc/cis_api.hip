@@ -1,0 +1,757 @@
+// Host side of the cis library: mesh/DVS preprocessing, validation, device
+// state and the C ABI declared in include/cis.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/cis.h"
+#include "cis_internal.h"
+
+using namespace cis;
+
+namespace {
+
+thread_local std::string g_err;
+
+cis_status fail(cis_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(CIS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct TriKey {
+  int32_t a, b, c;
+  bool operator==(const TriKey& o) const { return a == o.a && b == o.b && c == o.c; }
+};
+struct TriHash {
+  size_t operator()(const TriKey& k) const {
+    uint64_t h = (uint64_t)(uint32_t)k.a * 0x9E3779B97F4A7C15ull;
+    h ^= (uint64_t)(uint32_t)k.b + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)(uint32_t)k.c + 0x94D049BB133111EBull + (h << 6) + (h >> 2);
+    return (size_t)h;
+  }
+};
+TriKey make_key(int32_t x, int32_t y, int32_t z) {
+  int32_t v[3] = {x, y, z};
+  std::sort(v, v + 3);
+  return {v[0], v[1], v[2]};
+}
+
+template <class T> cis_status dmalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  HIP_TRY(hipMalloc((void**)p, n * sizeof(T)));
+  return CIS_OK;
+}
+
+template <class T> cis_status upload(T** p, const std::vector<T>& v, hipStream_t st) {
+  cis_status s = dmalloc(p, v.size());
+  if (s != CIS_OK) return s;
+  HIP_TRY(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return CIS_OK;
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+  int i = threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+struct cis_mesh {
+  int64_t nc = 0, nf = 0, n_int = 0, n_b = 0, n_colors = 0;
+  std::vector<int64_t> color_off;
+  std::vector<int32_t> cell_nb, cell_face, face_cell, face_tag;
+  std::vector<double> V, h, xc, xf, fA, fn;  // cells: V, h, centroid; faces: centroid, area, unit normal
+};
+
+struct cis_dvs {
+  int64_t n = 0;
+  std::vector<double> u, w;
+  double umax = 0.0;
+};
+
+struct cis_state {
+  const cis_mesh* mesh = nullptr;
+  const cis_dvs* dvs = nullptr;
+  cis_gas gas{};
+  cis_numerics num{};
+  std::vector<cis_bc> bcs;
+  int32_t precision = CIS_FP64;
+  hipStream_t stream = nullptr;
+  Dev dev{};
+  Bufs buf{};
+  Work work{};
+  // library-owned device arrays
+  int32_t *d_cell_nb = nullptr, *d_cell_face = nullptr, *d_face_cell = nullptr, *d_face_bc = nullptr;
+  double *d_cell_geo = nullptr, *d_face_geo = nullptr, *d_dvs = nullptr, *d_bc = nullptr;
+  float* d_dvs_f = nullptr;
+  int64_t res_cap = 0;
+  bool profile = false;
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_launch[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<void*> owned;
+  ~cis_state() {
+    for (void* p : owned)
+      if (p) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+template <class T> cis_status own_alloc(cis_state* s, T** p, size_t n) {
+  cis_status st = dmalloc(p, n);
+  if (st == CIS_OK) s->owned.push_back((void*)*p);
+  return st;
+}
+template <class T> cis_status own_upload(cis_state* s, T** p, const std::vector<T>& v) {
+  cis_status st = upload(p, v, s->stream);
+  if (st == CIS_OK) s->owned.push_back((void*)*p);
+  return st;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+cis_status check_numerics(const cis_numerics* n) {
+  if (!n) return fail(CIS_E_INVALID_ARG, "numerics is NULL");
+  if (!(n->cfl > 0.0) || !(n->inv_dt >= 0.0) || !(n->cfl_imp >= 0.0) || !(n->lim_K >= 0.0) || !(n->snap >= 0.0) ||
+      n->n_macro < 0 || n->n_micro < 0 || n->n_macro > 100000 || n->n_micro > 100000)
+    return fail(CIS_E_INVALID_ARG, "numerics out of range");
+  return CIS_OK;
+}
+
+void fill_dev_numerics(cis_state* s) {
+  s->dev.snap = s->num.snap;
+  s->dev.lim_K = s->num.lim_K;
+  s->dev.inv_dt = s->num.inv_dt;
+  s->dev.cfl_imp = s->num.cfl_imp;
+  s->dev.limiter = s->num.limiter;
+}
+
+template <class F> cis_status dispatch(cis_state* s, F&& f) {
+  if (s->precision == CIS_FP64) return f((double*)nullptr);
+  return f((float*)nullptr);
+}
+
+cis_status device_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CIS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return CIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cis_last_error(void) { return g_err.c_str(); }
+
+cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* tet, int64_t n_cells,
+                           const int32_t* btri, const int32_t* btag, int64_t n_b, const int64_t* color_offsets,
+                           int64_t n_colors, cis_mesh** out) {
+  if (!out) return fail(CIS_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!xyz || !tet || n_nodes <= 0 || n_cells <= 0 || n_cells > INT32_MAX || n_b < 0 || (n_b > 0 && (!btri || !btag)))
+    return fail(CIS_E_INVALID_ARG, "bad mesh arrays");
+  if (!color_offsets || n_colors <= 0) return fail(CIS_E_INVALID_ARG, "colour offsets are required");
+  if (color_offsets[0] != 0 || color_offsets[n_colors] != n_cells)
+    return fail(CIS_E_INVALID_ARG, "colour offsets must run from 0 to n_cells");
+  for (int64_t c = 0; c < n_colors; ++c)
+    if (color_offsets[c + 1] < color_offsets[c]) return fail(CIS_E_INVALID_ARG, "colour offsets must not decrease");
+  if (!finite_all(xyz, 3 * (size_t)n_nodes)) return fail(CIS_E_MESH, "non-finite node coordinate");
+  for (int64_t x = 0; x < 4 * n_cells; ++x)
+    if (tet[x] < 0 || tet[x] >= n_nodes) return fail(CIS_E_MESH, "tet node id out of range");
+
+  auto* m = new cis_mesh();
+  m->nc = n_cells;
+  m->n_colors = n_colors;
+  m->color_off.assign(color_offsets, color_offsets + n_colors + 1);
+  m->cell_face.assign(4 * n_cells, -1);
+  m->cell_nb.assign(4 * n_cells, -1);
+  m->V.resize(n_cells);
+  m->xc.resize(3 * n_cells);
+  // cells
+  for (int64_t i = 0; i < n_cells; ++i) {
+    const double* p0 = xyz + 3 * tet[4 * i];
+    const double* p1 = xyz + 3 * tet[4 * i + 1];
+    const double* p2 = xyz + 3 * tet[4 * i + 2];
+    const double* p3 = xyz + 3 * tet[4 * i + 3];
+    double a[3], b[3], c[3];
+    for (int d = 0; d < 3; ++d) {
+      a[d] = p1[d] - p0[d];
+      b[d] = p2[d] - p0[d];
+      c[d] = p3[d] - p0[d];
+    }
+    double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
+    m->V[i] = std::fabs(det) / 6.0;
+    if (!(m->V[i] > 0.0)) {
+      delete m;
+      return fail(CIS_E_MESH, "cell " + std::to_string(i) + " has zero volume");
+    }
+    for (int d = 0; d < 3; ++d) m->xc[3 * i + d] = 0.25 * (p0[d] + p1[d] + p2[d] + p3[d]);
+  }
+  // faces (face a of a tet is opposite its local vertex a)
+  std::unordered_map<TriKey, int64_t, TriHash> seen;
+  seen.reserve((size_t)(3 * n_cells));
+  std::vector<TriKey> fkey;
+  std::vector<int32_t> fslot;  // local slot of the first cell
+  for (int64_t i = 0; i < n_cells; ++i) {
+    const int32_t* t = tet + 4 * i;
+    for (int a = 0; a < 4; ++a) {
+      TriKey key = make_key(t[(a + 1) % 4], t[(a + 2) % 4], t[(a + 3) % 4]);
+      auto it = seen.find(key);
+      if (it == seen.end()) {
+        int64_t f = (int64_t)fkey.size();
+        seen.emplace(key, f);
+        fkey.push_back(key);
+        m->face_cell.push_back((int32_t)i);
+        m->face_cell.push_back(-1);
+        m->cell_face[4 * i + a] = (int32_t)f;
+      } else {
+        int64_t f = it->second;
+        if (m->face_cell[2 * f + 1] != -1 || m->face_cell[2 * f] == (int32_t)i) {
+          delete m;
+          return fail(CIS_E_MESH, "non-manifold face");
+        }
+        m->face_cell[2 * f + 1] = (int32_t)i;
+        m->cell_face[4 * i + a] = (int32_t)f;
+      }
+    }
+  }
+  m->nf = (int64_t)fkey.size();
+  m->face_tag.assign(m->nf, 0);
+  std::unordered_map<TriKey, int32_t, TriHash> tags;
+  for (int64_t b = 0; b < n_b; ++b) tags[make_key(btri[3 * b], btri[3 * b + 1], btri[3 * b + 2])] = btag[b];
+  m->n_int = 0;
+  m->n_b = 0;
+  for (int64_t f = 0; f < m->nf; ++f) {
+    if (m->face_cell[2 * f + 1] >= 0) {
+      ++m->n_int;
+      continue;
+    }
+    auto it = tags.find(fkey[f]);
+    if (it == tags.end()) {
+      delete m;
+      return fail(CIS_E_MESH, "open face without a boundary tag");
+    }
+    m->face_tag[f] = it->second;
+    ++m->n_b;
+  }
+  // face geometry; interior faces get the canonical orientation (first normal component beyond 1e-9 > 0)
+  m->xf.resize(3 * m->nf);
+  m->fA.resize(m->nf);
+  m->fn.resize(3 * m->nf);
+  for (int64_t f = 0; f < m->nf; ++f) {
+    const double* a = xyz + 3 * fkey[f].a;
+    const double* b = xyz + 3 * fkey[f].b;
+    const double* c = xyz + 3 * fkey[f].c;
+    double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(len > 0.0)) {
+      delete m;
+      return fail(CIS_E_MESH, "degenerate face");
+    }
+    for (int d = 0; d < 3; ++d) {
+      m->xf[3 * f + d] = (a[d] + b[d] + c[d]) / 3.0;
+      n[d] /= len;
+    }
+    m->fA[f] = 0.5 * len;
+    int32_t o = m->face_cell[2 * f];
+    double dot = 0.0;
+    for (int d = 0; d < 3; ++d) dot += n[d] * (m->xf[3 * f + d] - m->xc[3 * o + d]);
+    if (dot < 0.0)
+      for (int d = 0; d < 3; ++d) n[d] = -n[d];
+    if (m->face_cell[2 * f + 1] >= 0) {
+      int d0 = 0;
+      while (d0 < 2 && std::fabs(n[d0]) <= 1e-9) ++d0;
+      if (n[d0] < 0.0) {
+        for (int d = 0; d < 3; ++d) n[d] = -n[d];
+        std::swap(m->face_cell[2 * f], m->face_cell[2 * f + 1]);
+      }
+    }
+    for (int d = 0; d < 3; ++d) m->fn[3 * f + d] = n[d];
+  }
+  // neighbours, closure, h, colouring
+  m->h.resize(n_cells);
+  for (int64_t i = 0; i < n_cells; ++i) {
+    double acc[3] = {0, 0, 0}, asum = 0.0;
+    for (int a = 0; a < 4; ++a) {
+      int64_t f = m->cell_face[4 * i + a];
+      bool own = m->face_cell[2 * f] == (int32_t)i;
+      m->cell_nb[4 * i + a] = own ? m->face_cell[2 * f + 1] : m->face_cell[2 * f];
+      double sg = own ? 1.0 : -1.0;
+      for (int d = 0; d < 3; ++d) acc[d] += sg * m->fA[f] * m->fn[3 * f + d];
+      asum += m->fA[f];
+    }
+    if (std::sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]) > 1e-10 * asum) {
+      delete m;
+      return fail(CIS_E_MESH, "cell " + std::to_string(i) + " is not closed");
+    }
+    m->h[i] = 6.0 * m->V[i] / asum;
+  }
+  std::vector<int32_t> color(n_cells);
+  for (int64_t c = 0; c < n_colors; ++c)
+    for (int64_t i = color_offsets[c]; i < color_offsets[c + 1]; ++i) color[i] = (int32_t)c;
+  for (int64_t f = 0; f < m->nf; ++f) {
+    int32_t j = m->face_cell[2 * f + 1];
+    if (j >= 0 && color[j] == color[m->face_cell[2 * f]]) {
+      delete m;
+      return fail(CIS_E_MESH, "two face neighbours share a colour");
+    }
+  }
+  *out = m;
+  return CIS_OK;
+}
+
+cis_status cis_mesh_info(const cis_mesh* m, cis_mesh_info_t* out) {
+  if (!m || !out) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  out->n_cells = m->nc;
+  out->n_faces = m->nf;
+  out->n_interior = m->n_int;
+  out->n_boundary = m->n_b;
+  out->n_colors = m->n_colors;
+  return CIS_OK;
+}
+
+void cis_mesh_destroy(cis_mesh* m) { delete m; }
+
+cis_status cis_dvs_create(const double* u, const double* w, int64_t n, cis_dvs** out) {
+  if (!out) return fail(CIS_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!u || !w || n <= 0) return fail(CIS_E_INVALID_ARG, "bad DVS arrays");
+  if (!finite_all(u, 3 * (size_t)n)) return fail(CIS_E_DVS, "non-finite velocity");
+  for (int64_t k = 0; k < n; ++k)
+    if (!(w[k] > 0.0) || !std::isfinite(w[k])) return fail(CIS_E_DVS, "DVS weight must be positive");
+  auto* d = new cis_dvs();
+  d->n = n;
+  d->u.assign(u, u + 3 * n);
+  d->w.assign(w, w + n);
+  for (int64_t k = 0; k < n; ++k)
+    d->umax = std::max(d->umax, std::sqrt(u[3 * k] * u[3 * k] + u[3 * k + 1] * u[3 * k + 1] + u[3 * k + 2] * u[3 * k + 2]));
+  if (!(d->umax > 0.0)) {
+    delete d;
+    return fail(CIS_E_DVS, "all velocities are zero");
+  }
+  *out = d;
+  return CIS_OK;
+}
+
+void cis_dvs_destroy(cis_dvs* d) { delete d; }
+
+cis_status cis_state_required_bytes(const cis_mesh* m, const cis_dvs* d, int32_t precision, cis_buffer_sizes* out) {
+  if (!m || !d || !out) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  if (precision != CIS_FP64 && precision != CIS_MIXED) return fail(CIS_E_INVALID_ARG, "unknown precision");
+  int64_t es = precision == CIS_FP64 ? 8 : 4;
+  out->phi_bytes = m->nc * d->n * es;
+  out->face_bytes = m->nf * d->n * es;
+  out->cell6_bytes = m->nc * 6 * 8;
+  out->total_bytes = 6 * out->phi_bytes + 2 * out->face_bytes + 2 * out->cell6_bytes;
+  return CIS_OK;
+}
+
+cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas* gas, const cis_numerics* num,
+                            const cis_bc* bc, int32_t n_bc, int32_t precision, const cis_device_buffers* buf,
+                            void* stream, cis_state** out) {
+  if (!out) return fail(CIS_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!m || !dv || !gas || !buf || (n_bc > 0 && !bc) || n_bc < 0) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  if (precision != CIS_FP64 && precision != CIS_MIXED) return fail(CIS_E_INVALID_ARG, "unknown precision");
+  cis_status st = check_numerics(num);
+  if (st != CIS_OK) return st;
+  if (!buf->G || !buf->R || !buf->dG || !buf->dR || !buf->resG || !buf->resR || !buf->faceG || !buf->faceR || !buf->W ||
+      !buf->q)
+    return fail(CIS_E_INVALID_ARG, "a device buffer is NULL");
+  if (!(gas->R > 0) || !(gas->gamma > 1) || !(gas->Z > 0) || !(gas->mu_ref > 0) || !(gas->T_ref > 0))
+    return fail(CIS_E_INVALID_ARG, "gas constants out of range");
+  if (dv->n > (int64_t)INT32_MAX) return fail(CIS_E_UNSUPPORTED, "velocity set too large");
+  for (int b = 0; b < n_bc; ++b) {
+    if ((bc[b].kind != CIS_BC_WALL && bc[b].kind != CIS_BC_FARFIELD) || !(bc[b].T > 0.0) ||
+        (bc[b].kind == CIS_BC_FARFIELD && !(bc[b].rho > 0.0)))
+      return fail(CIS_E_INVALID_ARG, "bad boundary condition " + std::to_string(b));
+  }
+  std::vector<int32_t> face_bc(m->nf, -1);
+  for (int64_t f = 0; f < m->nf; ++f) {
+    if (m->face_cell[2 * f + 1] >= 0) continue;
+    int slot = -1;
+    for (int b = 0; b < n_bc; ++b)
+      if (bc[b].tag == m->face_tag[f]) slot = b;
+    if (slot < 0) return fail(CIS_E_INVALID_ARG, "no boundary condition for tag " + std::to_string(m->face_tag[f]));
+    face_bc[f] = slot;
+  }
+
+  auto* s = new cis_state();
+  s->mesh = m;
+  s->dvs = dv;
+  s->gas = *gas;
+  s->num = *num;
+  s->bcs.assign(bc, bc + n_bc);
+  s->precision = precision;
+  s->stream = (hipStream_t)stream;
+  const int64_t nc = m->nc, nf = m->nf, nv = dv->n;
+
+  // geometry that depends on the DVS: dt_i = cfl h_i / max|u|, s_f, Delta l_f, least-squares weights
+  std::vector<double> dt(nc);
+  for (int64_t i = 0; i < nc; ++i) dt[i] = num->cfl * m->h[i] / dv->umax;
+  std::vector<double> fgeo(FGW * nf, 0.0);
+  for (int64_t f = 0; f < nf; ++f) {
+    int32_t i = m->face_cell[2 * f], j = m->face_cell[2 * f + 1];
+    double* g = &fgeo[FGW * f];
+    g[0] = m->fA[f];
+    for (int d = 0; d < 3; ++d) g[1 + d] = m->fn[3 * f + d];
+    double d2 = 0.0;
+    if (j >= 0) {
+      g[4] = std::min(dt[i], dt[j]);
+      for (int d = 0; d < 3; ++d) d2 += (m->xc[3 * i + d] - m->xc[3 * j + d]) * (m->xc[3 * i + d] - m->xc[3 * j + d]);
+      g[5] = std::sqrt(d2);
+    } else {
+      g[4] = dt[i];
+      for (int d = 0; d < 3; ++d) d2 += (m->xf[3 * f + d] - m->xc[3 * i + d]) * (m->xf[3 * f + d] - m->xc[3 * i + d]);
+      g[5] = 2.0 * std::sqrt(d2);
+    }
+  }
+  std::vector<double> cgeo(CG * nc, 0.0);
+  for (int64_t i = 0; i < nc; ++i) {
+    double* g = &cgeo[CG * i];
+    g[0] = m->V[i];
+    g[1] = 1.0 / m->V[i];
+    g[2] = m->h[i];
+    for (int d = 0; d < 3; ++d) g[4 + d] = m->xc[3 * i + d];
+    double M[9] = {0}, dvec[4][3];
+    for (int a = 0; a < 4; ++a) {
+      int64_t f = m->cell_face[4 * i + a];
+      int32_t nb = m->cell_nb[4 * i + a];
+      double sg = m->face_cell[2 * f] == (int32_t)i ? 1.0 : -1.0;
+      double* sl = g + CG_FACE + CG_SLOT * a;
+      sl[0] = sg;
+      sl[1] = m->fA[f] / m->V[i];
+      for (int d = 0; d < 3; ++d) {
+        sl[2 + d] = sg * m->fn[3 * f + d];
+        sl[5 + d] = m->xf[3 * f + d] - m->xc[3 * i + d];
+        dvec[a][d] = (nb >= 0 ? m->xc[3 * nb + d] : m->xf[3 * f + d]) - m->xc[3 * i + d];
+      }
+      sl[8] = fgeo[FGW * f + 4];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[3 * r + c] += dvec[a][r] * dvec[a][c];
+    }
+    // inverse of the least-squares normal matrix (unweighted; boundary faces enter with a zero difference)
+    double c00 = M[4] * M[8] - M[5] * M[7], c01 = M[5] * M[6] - M[3] * M[8], c02 = M[3] * M[7] - M[4] * M[6];
+    double det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+    if (!(std::fabs(det) > 0.0)) {
+      delete s;
+      return fail(CIS_E_MESH, "singular least-squares matrix");
+    }
+    double I[9] = {c00, M[2] * M[7] - M[1] * M[8], M[1] * M[5] - M[2] * M[4],
+                   c01, M[0] * M[8] - M[2] * M[6], M[2] * M[3] - M[0] * M[5],
+                   c02, M[1] * M[6] - M[0] * M[7], M[0] * M[4] - M[1] * M[3]};
+    for (int a = 0; a < 4; ++a) {
+      double* sl = g + CG_FACE + CG_SLOT * a;
+      bool interior = m->cell_nb[4 * i + a] >= 0;
+      for (int r = 0; r < 3; ++r)
+        sl[9 + r] = interior ? (I[3 * r] * dvec[a][0] + I[3 * r + 1] * dvec[a][1] + I[3 * r + 2] * dvec[a][2]) / det : 0.0;
+    }
+  }
+  std::vector<double> dvsv(DV * nv, 0.0);
+  std::vector<float> dvsf(DV * nv, 0.0f);
+  for (int64_t k = 0; k < nv; ++k) {
+    double* p = &dvsv[DV * k];
+    for (int d = 0; d < 3; ++d) p[d] = dv->u[3 * k + d];
+    p[3] = dv->w[k];
+    p[4] = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    p[5] = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    for (int x = 0; x < DV; ++x) dvsf[DV * k + x] = (float)p[x];
+  }
+  std::vector<double> bct(BCW * std::max(n_bc, 1), 0.0);
+  for (int b = 0; b < n_bc; ++b) {
+    double* p = &bct[BCW * b];
+    p[0] = bc[b].kind;
+    p[1] = bc[b].rho;
+    for (int d = 0; d < 3; ++d) p[2 + d] = bc[b].U[d];
+    p[5] = bc[b].T;
+  }
+  cis_status e = CIS_OK;
+  auto chk = [&](cis_status x) {
+    if (e == CIS_OK) e = x;
+  };
+  chk(own_upload(s, &s->d_cell_nb, m->cell_nb));
+  chk(own_upload(s, &s->d_cell_face, m->cell_face));
+  chk(own_upload(s, &s->d_face_cell, m->face_cell));
+  chk(own_upload(s, &s->d_face_bc, face_bc));
+  chk(own_upload(s, &s->d_cell_geo, cgeo));
+  chk(own_upload(s, &s->d_face_geo, fgeo));
+  chk(own_upload(s, &s->d_dvs, dvsv));
+  chk(own_upload(s, &s->d_dvs_f, dvsf));
+  chk(own_upload(s, &s->d_bc, bct));
+  Work& w = s->work;
+  chk(own_alloc(s, &w.face_mac, 6 * nf));
+  chk(own_alloc(s, &w.cell_prim, 8 * nc));
+  chk(own_alloc(s, &w.rcf, 4 * nc));
+  chk(own_alloc(s, &w.mres, 6 * nc));
+  chk(own_alloc(s, &w.mD, 2 * nc));
+  chk(own_alloc(s, &w.Fmac, 6 * nc));
+  chk(own_alloc(s, &w.dW, 6 * nc));
+  chk(own_alloc(s, &w.Wt, 6 * nc));
+  chk(own_alloc(s, &w.eq, ER * nc));
+  chk(own_alloc(s, &w.cellres, 6 * nc));
+  chk(own_alloc(s, &w.flag, 4));
+  s->res_cap = 64;
+  chk(own_alloc(s, &w.res, 6 * s->res_cap));
+  if (e != CIS_OK) {
+    delete s;
+    return e;
+  }
+  if (hipStreamSynchronize(s->stream) != hipSuccess) {
+    delete s;
+    return fail(CIS_E_DEVICE, "upload failed");
+  }
+  Dev& d = s->dev;
+  d.nc = nc;
+  d.nf = nf;
+  d.nv = nv;
+  d.cell_nb = s->d_cell_nb;
+  d.cell_face = s->d_cell_face;
+  d.cell_geo = s->d_cell_geo;
+  d.face_cell = s->d_face_cell;
+  d.face_bc = s->d_face_bc;
+  d.face_geo = s->d_face_geo;
+  d.dvs = s->d_dvs;
+  d.dvs_f = s->d_dvs_f;
+  d.bc = s->d_bc;
+  d.gas = GasC{gas->R, gas->gamma, gas->Z, gas->delta, gas->omega0, gas->omega1, gas->mu_ref, gas->omega_vhs, gas->T_ref};
+  d.umax = dv->umax;
+  fill_dev_numerics(s);
+  s->buf = Bufs{buf->G, buf->R, buf->dG, buf->dR, buf->resG, buf->resR, buf->faceG, buf->faceR, buf->W, buf->q};
+  *out = s;
+  return CIS_OK;
+}
+
+cis_status cis_state_set_numerics(cis_state* s, const cis_numerics* num) {
+  if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
+  cis_status st = check_numerics(num);
+  if (st != CIS_OK) return st;
+  if (num->cfl != s->num.cfl) return fail(CIS_E_UNSUPPORTED, "cfl (face step s_ij) is fixed at state creation");
+  s->num = *num;
+  fill_dev_numerics(s);
+  return CIS_OK;
+}
+
+void cis_state_destroy(cis_state* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  delete s;
+}
+
+cis_status cis_state_init_equilibrium(cis_state* s, const double* W0, int32_t per_cell) {
+  if (!s || !W0) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  const int64_t nc = s->mesh->nc;
+  size_t n = per_cell ? 6 * (size_t)nc : 6;
+  if (!finite_all(W0, n)) return fail(CIS_E_INVALID_ARG, "non-finite W0");
+  for (size_t c = 0; c < n; c += 6) {
+    double ke = 0.5 * (W0[c + 1] * W0[c + 1] + W0[c + 2] * W0[c + 2] + W0[c + 3] * W0[c + 3]) / W0[c];
+    if (!(W0[c] > 0.0) || !(W0[c + 5] > 0.0) || !(W0[c + 4] - ke - W0[c + 5] > 0.0))
+      return fail(CIS_E_INVALID_ARG, "W0 must have rho, T_tr, T_rot > 0");
+  }
+  double* dW0 = nullptr;
+  HIP_TRY(hipMalloc((void**)&dW0, n * sizeof(double)));
+  hipError_t e1 = hipMemcpyAsync(dW0, W0, n * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  cis_status st = CIS_OK;
+  if (e1 == hipSuccess) {
+    st = dispatch(s, [&](auto* tp) {
+      using T = std::remove_pointer_t<decltype(tp)>;
+      launch_init_eq<T>(s->dev, s->buf, dW0, per_cell ? 1 : 0, s->work.eq, s->stream);
+      return device_check("init_equilibrium");
+    });
+  }
+  hipError_t e2 = hipStreamSynchronize(s->stream);
+  (void)hipFree(dW0);
+  if (e1 != hipSuccess || e2 != hipSuccess) return fail(CIS_E_DEVICE, "init_equilibrium failed");
+  return st;
+}
+
+cis_status cis_state_set(cis_state* s, const void* G, const void* R, const double* W, const double* q) {
+  if (!s || !G || !R || !W || !q) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  const int64_t nc = s->mesh->nc, nv = s->dvs->n;
+  size_t pb = (size_t)nc * nv * (s->precision == CIS_FP64 ? 8 : 4);
+  HIP_TRY(hipMemcpyAsync(s->buf.G, G, pb, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->buf.R, R, pb, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->buf.W, W, 6 * nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->buf.q, q, 6 * nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CIS_OK;
+}
+
+cis_status cis_state_get(cis_state* s, void* G, void* R, double* W, double* q) {
+  if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
+  const int64_t nc = s->mesh->nc, nv = s->dvs->n;
+  size_t pb = (size_t)nc * nv * (s->precision == CIS_FP64 ? 8 : 4);
+  if (G) HIP_TRY(hipMemcpyAsync(G, s->buf.G, pb, hipMemcpyDeviceToHost, s->stream));
+  if (R) HIP_TRY(hipMemcpyAsync(R, s->buf.R, pb, hipMemcpyDeviceToHost, s->stream));
+  if (W) HIP_TRY(hipMemcpyAsync(W, s->buf.W, 6 * nc * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  if (q) HIP_TRY(hipMemcpyAsync(q, s->buf.q, 6 * nc * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CIS_OK;
+}
+
+cis_status cis_iterate(cis_state* s, int32_t n_iter, double* res_hist) {
+  if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
+  if (n_iter < 0) return fail(CIS_E_INVALID_ARG, "n_iter < 0");
+  if (n_iter == 0) return CIS_OK;
+  if (n_iter > s->res_cap) {
+    double* nr = nullptr;
+    HIP_TRY(hipMalloc((void**)&nr, 6 * (size_t)n_iter * sizeof(double)));
+    for (auto& p : s->owned)
+      if (p == (void*)s->work.res) {
+        (void)hipStreamSynchronize(s->stream);
+        (void)hipFree(p);
+        p = (void*)nr;
+      }
+    s->work.res = nr;
+    s->res_cap = n_iter;
+  }
+  const cis_mesh* m = s->mesh;
+  std::vector<hipEvent_t> ev;
+  if (s->profile) {
+    ev.resize(7 * (size_t)n_iter, nullptr);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  }
+  auto mark = [&](int32_t it, int k) {
+    if (s->profile) (void)hipEventRecord(ev[7 * (size_t)it + k], s->stream);
+  };
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s->stream, s->work.flag, 4);
+  cis_status st = dispatch(s, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    for (int32_t it = 0; it < n_iter; ++it) {
+      mark(it, 0);
+      launch_recon<T>(s->dev, s->buf, s->stream);
+      mark(it, 1);
+      launch_face<T>(s->dev, s->buf, s->work, s->stream);
+      mark(it, 2);
+      launch_macro(s->dev, s->buf, s->work, m->color_off.data(), m->n_colors, s->num.n_macro, s->stream);
+      mark(it, 3);
+      launch_residual<T>(s->dev, s->buf, s->work, s->buf.resG, s->buf.resR, 0, s->stream);
+      mark(it, 4);
+      launch_micro<T>(s->dev, s->buf, s->work, m->color_off.data(), m->n_colors, s->num.n_micro, s->stream);
+      mark(it, 5);
+      launch_update<T>(s->dev, s->buf, s->work, it, s->stream);
+      mark(it, 6);
+    }
+    return device_check("iterate");
+  });
+  if (s->profile) {
+    (void)hipStreamSynchronize(s->stream);
+    int64_t nonempty = 0;
+    for (int64_t c = 0; c < m->n_colors; ++c) nonempty += (m->color_off[c + 1] > m->color_off[c]);
+    const int64_t per_it[6] = {1, 1, 3 + 2 * (int64_t)s->num.n_macro * nonempty, 1, 2 * (int64_t)s->num.n_micro * nonempty, 2};
+    for (int32_t it = 0; it < n_iter; ++it)
+      for (int k = 0; k < 6; ++k) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, ev[7 * (size_t)it + k], ev[7 * (size_t)it + k + 1]);
+        s->prof_ms[k] += ms;
+        s->prof_launch[k] += per_it[k];
+      }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  if (st != CIS_OK) return st;
+  int32_t flag[4] = {0, 0, 0, 0};
+  std::vector<double> hist(6 * (size_t)n_iter);
+  HIP_TRY(hipMemcpyAsync(flag, s->work.flag, sizeof(flag), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipMemcpyAsync(hist.data(), s->work.res, hist.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (res_hist) std::copy(hist.begin(), hist.end(), res_hist);
+  if (flag[0]) return fail(CIS_E_NONFINITE, "non-finite or non-positive state (flag " + std::to_string(flag[0]) + ")");
+  return CIS_OK;
+}
+
+cis_status cis_residual(cis_state* s, void* FG, void* FR, double* Fmac) {
+  if (!s || !FG || !FR) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  cis_status st = dispatch(s, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_recon<T>(s->dev, s->buf, s->stream);
+    launch_face<T>(s->dev, s->buf, s->work, s->stream);
+    launch_residual<T>(s->dev, s->buf, s->work, FG, FR, 1, s->stream);
+    launch_macro_flux_cells(s->dev, s->work, s->stream);
+    return device_check("residual");
+  });
+  if (st != CIS_OK) return st;
+  if (Fmac) HIP_TRY(hipMemcpyAsync(Fmac, s->work.Fmac, 6 * s->mesh->nc * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CIS_OK;
+}
+
+cis_status cis_moments(cis_state* s, double* W, double* q) { return cis_state_get(s, nullptr, nullptr, W, q); }
+
+cis_status cis_wall_heat_flux(cis_state* s, int32_t tag, double* Q) {
+  if (!s || !Q) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  const cis_mesh* m = s->mesh;
+  cis_status st = dispatch(s, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_recon<T>(s->dev, s->buf, s->stream);
+    launch_face<T>(s->dev, s->buf, s->work, s->stream);
+    return device_check("wall_heat_flux");
+  });
+  if (st != CIS_OK) return st;
+  std::vector<double> fm(6 * m->nf);
+  HIP_TRY(hipMemcpyAsync(fm.data(), s->work.face_mac, fm.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  double acc = 0.0;
+  for (int64_t f = 0; f < m->nf; ++f)
+    if (m->face_cell[2 * f + 1] < 0 && m->face_tag[f] == tag) acc += fm[6 * f + 4];
+  *Q = acc;
+  return CIS_OK;
+}
+
+cis_status cis_profile_enable(cis_state* s, int32_t enable) {
+  if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
+  s->profile = enable != 0;
+  for (int k = 0; k < 6; ++k) {
+    s->prof_ms[k] = 0.0;
+    s->prof_launch[k] = 0;
+  }
+  return CIS_OK;
+}
+
+cis_status cis_profile_read(cis_state* s, double* ms, int64_t* launches) {
+  if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
+  for (int k = 0; k < 6; ++k) {
+    if (ms) ms[k] = s->prof_ms[k];
+    if (launches) launches[k] = s->prof_launch[k];
+  }
+  return CIS_OK;
+}
+
+cis_status cis_debug_stage(cis_state* s, int32_t which, double* out) {
+  if (!s || !out) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  const int64_t nc = s->mesh->nc;
+  if (which == 0 || which == 1 || which == 2) {
+    const double* src = which == 0 ? s->work.dW : which == 1 ? s->work.Wt : s->work.Fmac;
+    HIP_TRY(hipMemcpyAsync(out, src, 6 * nc * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return CIS_OK;
+  }
+  if (which == 3) {
+    std::vector<double> eq(ER * nc);
+    HIP_TRY(hipMemcpyAsync(eq.data(), s->work.eq, eq.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < nc; ++i) out[i] = eq[ER * i + 7];
+    return CIS_OK;
+  }
+  return fail(CIS_E_INVALID_ARG, "unknown stage");
+}
+
+}  // extern "C"

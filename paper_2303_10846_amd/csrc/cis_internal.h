@@ -1,0 +1,87 @@
+// Internal device layouts and kernel launchers of the cis library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cis {
+
+// Per-cell geometry record, FP64, CG doubles per cell:
+//   [0] V  [1] 1/V  [2] h = 6V/sum A  [3] unused  [4..6] centroid  [7] unused
+//   face slot a (a = 0..3, face opposite local vertex a) at 8 + 12a:
+//   [0] sign (+1: the face normal points out of this cell, -1: into it)  [1] A/V
+//   [2..4] outward unit normal  [5..7] x_f - x_i  [8] s_f (Eq. 45)  [9..11] least-squares weight M^-1 d
+constexpr int CG = 56;
+constexpr int CG_FACE = 8;
+constexpr int CG_SLOT = 12;
+
+// Per-face record, FP64, FGW doubles: [0] A  [1..3] unit normal (out of face_cell[2f])  [4] s  [5] dl
+constexpr int FGW = 8;
+
+// DVS record, DV values per velocity: [0..2] u  [3] w  [4] |u|  [5] |u|^2/2  [6..7] unused
+constexpr int DV = 8;
+
+// Boundary-condition record: [0] kind  [1] rho  [2..4] U  [5] T  [6..7] unused
+constexpr int BCW = 8;
+
+// Cell equilibrium record (predicted state of Step 4), ER doubles:
+//   [0] rho [1..3] U [4] T [5] T_tr [6] T_rot [7] tau [8..10] q_tr [11..13] q_rot
+//   [14] a_tr [15] b_tr [16] a_T [17] b_T [18] k_tr [19] k_T [20] k_tr_r [21] k_T_r
+//   [22] 1/(R T_tr) [23] 1/(R T) [24] R T_rot [25] R T [26] 1-1/Z [27] 1/Z
+constexpr int ER = 32;
+
+struct GasC {
+  double R, gamma, Z, delta, omega0, omega1, mu_ref, omega_v, T_ref;
+};
+
+struct Dev {
+  int64_t nc, nf, nv;
+  const int32_t* cell_nb;    // [nc][4] neighbour cell or -1
+  const int32_t* cell_face;  // [nc][4]
+  const double* cell_geo;    // [nc][CG]
+  const int32_t* face_cell;  // [nf][2] (cell the normal points out of, other cell or -1)
+  const int32_t* face_bc;    // [nf] slot in bc table, -1 interior
+  const double* face_geo;    // [nf][FGW]
+  const double* dvs;         // [nv][DV]
+  const float* dvs_f;        // [nv][DV]
+  const double* bc;          // [nbc][BCW]
+  GasC gas;
+  double snap, lim_K, inv_dt, cfl_imp, umax;
+  int limiter;
+};
+
+struct Work {
+  double* face_mac;  // [nf][6]
+  double* cell_prim; // [nc][8]: rho U T T_tr tau 0
+  double* rcf;       // [nc][4]
+  double* mres;      // [nc][6]
+  double* mD;        // [nc][2]
+  double* Fmac;      // [nc][6]
+  double* dW;        // [nc][6]
+  double* Wt;        // [nc][6]
+  double* eq;        // [nc][ER]
+  double* cellres;   // [nc][6]
+  double* res;       // [hist][6]
+  int32_t* flag;     // [4]
+};
+
+struct Bufs {
+  void *G, *R, *dG, *dR, *resG, *resR, *faceG, *faceR;
+  double *W, *q;
+};
+
+// Launchers (all enqueue on `st`); T = double or float selects the precision mode.
+template <class T> void launch_init_eq(const Dev& d, const Bufs& b, const double* W0, int per_cell, double* eqtmp,
+                                       hipStream_t st);
+template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st);
+template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st);
+void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors,
+                  int n_macro, hipStream_t st);
+template <class T> void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR,
+                                        int flux_only, hipStream_t st);
+template <class T> void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off,
+                                     int64_t n_colors, int n_micro, hipStream_t st);
+template <class T> void launch_update(const Dev& d, const Bufs& b, const Work& w, int64_t it, hipStream_t st);
+void launch_macro_flux_cells(const Dev& d, const Work& w, hipStream_t st);
+
+}  // namespace cis

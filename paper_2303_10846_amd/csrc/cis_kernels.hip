@@ -1,0 +1,880 @@
+// gfx950 kernels of one implicit iteration of the conservative implicit scheme
+// (arXiv 2303.10846, Sec. 3.5, Steps 2-6).
+//
+// Layout: distributions are [cell][velocity] rows (velocity contiguous), so a
+// workgroup that owns one cell or one face streams whole rows with coalesced
+// 64-wide wavefront accesses.  Per-cell and per-face geometry is read through
+// uniform (scalar) loads.  DVS moment sums are FP64 wavefront reductions
+// (Neumaier-compensated in the mixed-precision mode).  The coloured
+// Gauss-Seidel sweeps launch one kernel per colour: cells of one colour share
+// no face, so they update independently.  Nothing here is a dense
+// contraction; the kernels are bound by HBM bandwidth, not by MFMA.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "cis_internal.h"
+
+namespace cis {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+// ---------------------------------------------------------------------------
+// Reductions over a 256-thread workgroup (4 wave64 wavefronts)
+// ---------------------------------------------------------------------------
+
+__device__ inline void two_sum_add(double& s, double& c, double x) {
+  double t = s + x;
+  c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+  s = t;
+}
+
+// N running sums per thread; Comp selects Neumaier compensation.
+template <int N, bool Comp> struct Acc {
+  double s[N];
+  double c[N];
+  __device__ inline void zero() {
+#pragma unroll
+    for (int m = 0; m < N; ++m) s[m] = c[m] = 0.0;
+  }
+  __device__ inline void add(int m, double x) {
+    if (Comp)
+      two_sum_add(s[m], c[m], x);
+    else
+      s[m] += x;
+  }
+  // Block-wide total; every thread receives the same values. red: kWaves * 2N doubles of LDS.
+  __device__ inline void reduce(double* out, double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      double a = s[m], b = c[m];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        double a2 = __shfl_xor(a, o, 64);
+        if (Comp) {
+          double b2 = __shfl_xor(b, o, 64);
+          two_sum_add(a, b, a2);
+          b += b2;
+        } else {
+          a += a2;
+        }
+      }
+      if (lane == 0) {
+        red[wid * 2 * N + m] = a;
+        red[wid * 2 * N + N + m] = b;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      double a = red[m], b = red[N + m];
+      for (int q = 1; q < kWaves; ++q) {
+        if (Comp) {
+          two_sum_add(a, b, red[q * 2 * N + m]);
+          b += red[q * 2 * N + N + m];
+        } else {
+          a += red[q * 2 * N + m];
+        }
+      }
+      out[m] = Comp ? a + b : a;
+    }
+    __syncthreads();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Gas model (Sec. 2)
+// ---------------------------------------------------------------------------
+
+struct Prim {
+  double rho, U[3], T, Ttr, Trot;
+};
+
+// Eqs. 1-5 with K_tr = 3, K_rot = 2
+__device__ inline Prim prim_of(const double* W, double R) {
+  Prim p;
+  p.rho = W[0];
+  double ir = 1.0 / W[0];
+  p.U[0] = W[1] * ir;
+  p.U[1] = W[2] * ir;
+  p.U[2] = W[3] * ir;
+  double ke = 0.5 * W[0] * (p.U[0] * p.U[0] + p.U[1] * p.U[1] + p.U[2] * p.U[2]);
+  double irR = ir / R;
+  p.T = 0.4 * (W[4] - ke) * irR;
+  p.Trot = W[5] * irR;
+  p.Ttr = (2.0 / 3.0) * (W[4] - ke - W[5]) * irR;
+  return p;
+}
+
+// Eq. 13
+__device__ inline double visc(double Ttr, const GasC& g) { return g.mu_ref * pow(Ttr / g.T_ref, g.omega_v); }
+
+// Coefficients of the reduced Rykov equilibria (Eqs. 17-23) for one macroscopic state.
+__device__ inline void eq_coeffs(const Prim& p, const double* q, const GasC& g, double* e) {
+  const double R = g.R, twopi = 6.283185307179586476925;
+  double RTtr = R * p.Ttr, RT = R * p.T, RTrot = R * p.Trot;
+  double ptr = p.rho * RTtr, pp = p.rho * RT, prot = p.rho * RTrot;
+  e[0] = p.rho;
+  e[1] = p.U[0];
+  e[2] = p.U[1];
+  e[3] = p.U[2];
+  e[4] = p.T;
+  e[5] = p.Ttr;
+  e[6] = p.Trot;
+  for (int d = 0; d < 6; ++d) e[8 + d] = q[d];
+  e[14] = p.rho * pow(twopi * RTtr, -1.5);
+  e[15] = 1.0 / (2.0 * RTtr);
+  e[16] = p.rho * pow(twopi * RT, -1.5);
+  e[17] = 1.0 / (2.0 * RT);
+  e[18] = 1.0 / (15.0 * RTtr * ptr);                       // Eq. 19
+  e[19] = g.omega0 / (15.0 * RT * pp);                     // Eq. 20
+  e[20] = (1.0 - g.delta) / (RTtr * prot);                 // Eq. 21
+  e[21] = g.omega1 * (1.0 - g.delta) / (RT * pp);          // Eq. 22
+  e[22] = 1.0 / RTtr;
+  e[23] = 1.0 / RT;
+  e[24] = RTrot;
+  e[25] = RT;
+  e[26] = 1.0 - 1.0 / g.Z;                                 // Eqs. 17-18
+  e[27] = 1.0 / g.Z;
+}
+
+template <class C> struct Eq {
+  C Ux, Uy, Uz, qtx, qty, qtz, qrx, qry, qrz, a_tr, b_tr, a_T, b_T, ktr, kT, ktr_r, kT_r, iRTtr, iRT, RTrot, RT, z1,
+      z2;
+  __device__ inline void load(const double* e) {
+    Ux = (C)e[1];
+    Uy = (C)e[2];
+    Uz = (C)e[3];
+    qtx = (C)e[8];
+    qty = (C)e[9];
+    qtz = (C)e[10];
+    qrx = (C)e[11];
+    qry = (C)e[12];
+    qrz = (C)e[13];
+    a_tr = (C)e[14];
+    b_tr = (C)e[15];
+    a_T = (C)e[16];
+    b_T = (C)e[17];
+    ktr = (C)e[18];
+    kT = (C)e[19];
+    ktr_r = (C)e[20];
+    kT_r = (C)e[21];
+    iRTtr = (C)e[22];
+    iRT = (C)e[23];
+    RTrot = (C)e[24];
+    RT = (C)e[25];
+    z1 = (C)e[26];
+    z2 = (C)e[27];
+  }
+  // G*, R* at velocity u (Eqs. 17-23)
+  __device__ inline void eval(C ux, C uy, C uz, C& Gs, C& Rs) const {
+    C cx = ux - Ux, cy = uy - Uy, cz = uz - Uz;
+    C c2 = cx * cx + cy * cy + cz * cz;
+    C cqt = cx * qtx + cy * qty + cz * qtz;
+    C cqr = cx * qrx + cy * qry + cz * qrz;
+    C gtr = a_tr * exp(-c2 * b_tr);
+    C gT = a_T * exp(-c2 * b_T);
+    C Gtr = gtr * (C(1) + cqt * ktr * (c2 * iRTtr - C(5)));
+    C Grot = gT * (C(1) + cqt * kT * (c2 * iRT - C(5)));
+    C Rtr = RTrot * (Gtr + cqr * ktr_r * gtr);
+    C Rrot = RT * (Grot + cqr * kT_r * gT);
+    Gs = z1 * Gtr + z2 * Grot;
+    Rs = z1 * Rtr + z2 * Rrot;
+  }
+};
+
+// u.n with the tie rule (|u.n| <= snap |u| -> 0)
+__device__ inline double udotn(const double* dv, double nx, double ny, double nz, double snap) {
+  double un = dv[0] * nx + dv[1] * ny + dv[2] * nz;
+  return fabs(un) <= snap * dv[4] ? 0.0 : un;
+}
+
+__device__ inline double inv_dt_cell(const Dev& d, double h) {
+  double v = d.inv_dt;
+  if (d.cfl_imp > 0.0) v += d.umax / (d.cfl_imp * h);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Step 1: equilibrium initial state
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_eq_from_W(const double* W0, int per_cell, GasC g, int64_t nc, double* eq) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  const double* w = per_cell ? W0 + 6 * i : W0;
+  Prim p = prim_of(w, g.R);
+  double q0[6] = {0, 0, 0, 0, 0, 0};
+  eq_coeffs(p, q0, g, eq + ER * i);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fill_eq(Dev d, const double* eq, T* G, T* R, double* W, double* q,
+                                                    const double* W0, int per_cell) {
+  const int64_t i = blockIdx.x;
+  Eq<T> e;
+  e.load(eq + ER * i);
+  const double* dvs = d.dvs;
+  for (int64_t k = threadIdx.x; k < d.nv; k += kBlock) {
+    const double* dv = dvs + DV * k;
+    T gs, rs;
+    e.eval((T)dv[0], (T)dv[1], (T)dv[2], gs, rs);
+    G[i * d.nv + k] = gs;
+    R[i * d.nv + k] = rs;
+  }
+  if (threadIdx.x < 6) {
+    W[6 * i + threadIdx.x] = per_cell ? W0[6 * i + threadIdx.x] : W0[threadIdx.x];
+    q[6 * i + threadIdx.x] = 0.0;
+  }
+}
+
+template <class T>
+void launch_init_eq(const Dev& d, const Bufs& b, const double* W0, int per_cell, double* eqtmp, hipStream_t st) {
+  int nb = (int)((d.nc + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_eq_from_W, dim3(nb), dim3(kBlock), 0, st, W0, per_cell, d.gas, d.nc, eqtmp);
+  hipLaunchKernelGGL(k_fill_eq<T>, dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, (const double*)eqtmp, (T*)b.G,
+                     (T*)b.R, b.W, b.q, W0, per_cell);
+}
+
+// ---------------------------------------------------------------------------
+// Step 2(a): least-squares gradient, Venkatakrishnan limiter and upwind reconstruction (Eq. 46).
+// One workgroup per cell; each (face, velocity) value phi_bar is written once, by its upwind cell.
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ inline void recon_one(const Dev& d, const T* __restrict__ src, T* __restrict__ dst, int64_t i, int64_t k,
+                                 const int32_t* nb, const int32_t* fc, const double* geo, double kh3,
+                                 const double* dv, const double* un) {
+  const int64_t nv = d.nv;
+  T phi = src[i * nv + k];
+  T pn[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) pn[a] = nb[a] >= 0 ? src[(int64_t)nb[a] * nv + k] : phi;
+  T gx = 0, gy = 0, gz = 0, pmax = phi, pmin = phi;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (nb[a] < 0) continue;
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    T dphi = pn[a] - phi;
+    gx += (T)s[9] * dphi;
+    gy += (T)s[10] * dphi;
+    gz += (T)s[11] * dphi;
+    pmax = pn[a] > pmax ? pn[a] : pmax;
+    pmin = pn[a] < pmin ? pn[a] : pmin;
+  }
+  T L = 1;
+  if (d.limiter) {
+    T scale = fabs(pmax) > fabs(pmin) ? fabs(pmax) : fabs(pmin);
+    T eps2 = (T)kh3 * scale * scale;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double* s = geo + CG_FACE + CG_SLOT * a;
+      T d2 = gx * (T)s[5] + gy * (T)s[6] + gz * (T)s[7];
+      if (d2 != T(0)) {
+        T d1 = d2 > T(0) ? pmax - phi : pmin - phi;
+        T psi = ((d1 * d1 + eps2) * d2 + T(2) * d2 * d2 * d1) / (d2 * (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2));
+        L = psi < L ? psi : L;
+      }
+    }
+  }
+  gx *= L;
+  gy *= L;
+  gz *= L;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    // upwind cell of the face for this velocity: the owner when u.n_face > 0, else the neighbour
+    bool up = nb[a] >= 0 ? (s[0] > 0.0 ? un[a] > 0.0 : un[a] >= 0.0) : un[a] > 0.0;
+    if (!up) continue;
+    T sf = (T)s[8];
+    T v = phi + ((T)s[5] - (T)dv[0] * sf) * gx + ((T)s[6] - (T)dv[1] * sf) * gy + ((T)s[7] - (T)dv[2] * sf) * gz;
+    dst[(int64_t)fc[a] * nv + k] = v;
+  }
+}
+
+template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b) {
+  const int64_t i = blockIdx.x;
+  int32_t nb[4], fc[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    nb[a] = d.cell_nb[4 * i + a];
+    fc[a] = d.cell_face[4 * i + a];
+  }
+  const double* geo = d.cell_geo + CG * i;
+  double kh3 = d.lim_K * geo[2];
+  kh3 = kh3 * kh3 * kh3;
+  for (int64_t k = threadIdx.x; k < d.nv; k += kBlock) {
+    const double* dv = d.dvs + DV * k;
+    double un[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double* s = geo + CG_FACE + CG_SLOT * a;
+      un[a] = udotn(dv, s[2], s[3], s[4], d.snap);
+    }
+    recon_one<T>(d, (const T*)b.G, (T*)b.faceG, i, k, nb, fc, geo, kh3, dv, un);
+    recon_one<T>(d, (const T*)b.R, (T*)b.faceR, i, k, nb, fc, geo, kh3, dv, un);
+  }
+}
+
+template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_recon<T>, dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, b);
+}
+
+// ---------------------------------------------------------------------------
+// Steps 2(b)-(e) and 3 on one face per workgroup: face moments (Eqs. 47-52), face equilibrium,
+// collision-coupled face distribution (Eq. 45), micro flux A (u.n) phi_f (written in place over phi_bar)
+// and the face's macro flux A sum_k w (u.n) Phi phi_f (Eq. 37).  Boundary faces: diffuse wall with rho_w
+// from zero net mass flux, or far-field Maxwellian, for incoming velocities.
+// ---------------------------------------------------------------------------
+
+template <class T, bool Comp, bool UseLds>
+__global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sG = reinterpret_cast<T*>(smem_raw);
+  T* sR = sG + d.nv;
+  __shared__ double red[kWaves * 2 * 6];
+  const int64_t f = blockIdx.x;
+  const int64_t nv = d.nv;
+  const double* fg = d.face_geo + FGW * f;
+  const double A = fg[0], nx = fg[1], ny = fg[2], nz = fg[3], s = fg[4];
+  T* rowG = (T*)b.faceG + f * nv;
+  T* rowR = (T*)b.faceR + f * nv;
+  const int32_t bcs = d.face_bc[f];
+  const GasC& g = d.gas;
+  Acc<6, Comp> acc;
+  double tot[6];
+
+  if (bcs < 0) {
+    // pass 1: Eqs. 47-49 and sum_k w R_bar
+    acc.zero();
+    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+      T gb = rowG[k], rb = rowR[k];
+      if (UseLds) {
+        sG[k] = gb;
+        sR[k] = rb;
+      }
+      const double* dv = d.dvs + DV * k;
+      double wg = dv[3] * (double)gb, wr = dv[3] * (double)rb;
+      acc.add(0, wg);
+      acc.add(1, dv[0] * wg);
+      acc.add(2, dv[1] * wg);
+      acc.add(3, dv[2] * wg);
+      acc.add(4, dv[5] * wg + wr);
+      acc.add(5, wr);
+    }
+    acc.reduce(tot, red);
+    const double rho = tot[0];
+    const double U[3] = {tot[1] / rho, tot[2] / rho, tot[3] / rho};
+    const double ke = 0.5 * rho * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+    const double E = tot[4], Er = tot[5];
+    const double rR = rho * g.R;
+    Prim p;
+    p.rho = rho;
+    p.U[0] = U[0];
+    p.U[1] = U[1];
+    p.U[2] = U[2];
+    p.T = 0.4 * (E - ke) / rR;
+    const double Ttr_bar = (2.0 / 3.0) * (E - ke - Er) / rR;
+    const double tau = visc(Ttr_bar, g) / (rR * Ttr_bar);
+    const double Erot = (g.Z * tau * Er + s * rR * p.T) / (g.Z * tau + s);  // Eq. 50
+    p.Trot = Erot / rR;
+    p.Ttr = (2.0 / 3.0) * (E - ke - Erot) / rR;
+    // pass 2: heat fluxes, Eqs. 51-52, c = u - U_f
+    acc.zero();
+    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+      T gb = UseLds ? sG[k] : rowG[k];
+      T rb = UseLds ? sR[k] : rowR[k];
+      const double* dv = d.dvs + DV * k;
+      double cx = dv[0] - U[0], cy = dv[1] - U[1], cz = dv[2] - U[2];
+      double c2 = cx * cx + cy * cy + cz * cz;
+      double wg = dv[3] * c2 * (double)gb, wr = dv[3] * (double)rb;
+      acc.add(0, cx * wg);
+      acc.add(1, cy * wg);
+      acc.add(2, cz * wg);
+      acc.add(3, cx * wr);
+      acc.add(4, cy * wr);
+      acc.add(5, cz * wr);
+    }
+    acc.reduce(tot, red);
+    const double den_tr = tau + s - (s / 3.0) * (1.0 - 1.0 / g.Z + g.omega0 / g.Z);
+    const double den_rot = tau + s - s * (1.0 - g.delta) * (1.0 - 1.0 / g.Z + g.omega1 / g.Z);
+    double q[6];
+    for (int m = 0; m < 3; ++m) {
+      q[m] = tau * 0.5 * tot[m] / den_tr;
+      q[3 + m] = tau * tot[3 + m] / den_rot;
+    }
+    double ec[ER];
+    eq_coeffs(p, q, g, ec);
+    Eq<T> e;
+    e.load(ec);
+    const T ct = (T)(tau / (tau + s)), cs = (T)(s / (tau + s));
+    // pass 3: phi_f (Eq. 45), micro flux and macro flux
+    acc.zero();
+    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+      T gb = UseLds ? sG[k] : rowG[k];
+      T rb = UseLds ? sR[k] : rowR[k];
+      const double* dv = d.dvs + DV * k;
+      T gs, rs;
+      e.eval((T)dv[0], (T)dv[1], (T)dv[2], gs, rs);
+      T gf = ct * gb + cs * gs;
+      T rf = ct * rb + cs * rs;
+      double un = udotn(dv, nx, ny, nz, d.snap);
+      rowG[k] = (T)(A * un) * gf;
+      rowR[k] = (T)(A * un) * rf;
+      double wg = dv[3] * un * (double)gf, wr = dv[3] * un * (double)rf;
+      acc.add(0, wg);
+      acc.add(1, dv[0] * wg);
+      acc.add(2, dv[1] * wg);
+      acc.add(3, dv[2] * wg);
+      acc.add(4, dv[5] * wg + wr);
+      acc.add(5, wr);
+    }
+    acc.reduce(tot, red);
+  } else {
+    const double* bc = d.bc + BCW * bcs;
+    const bool wall = bc[0] == 1.0;
+    const double Ub[3] = {bc[2], bc[3], bc[4]}, Tb = bc[5];
+    const double RTb = g.R * Tb;
+    double rho_g = bc[1];
+    if (wall) {
+      // rho_w from zero net mass flux through the wall
+      Acc<2, Comp> a2;
+      a2.zero();
+      for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+        const double* dv = d.dvs + DV * k;
+        double un = udotn(dv, nx, ny, nz, d.snap);
+        if (un > 0.0) {
+          a2.add(0, dv[3] * un * (double)rowG[k]);
+        } else {
+          double cx = dv[0] - Ub[0], cy = dv[1] - Ub[1], cz = dv[2] - Ub[2];
+          double mw = pow(6.283185307179586476925 * RTb, -1.5) * exp(-(cx * cx + cy * cy + cz * cz) / (2.0 * RTb));
+          a2.add(1, dv[3] * (-un) * mw);
+        }
+      }
+      double t2[2];
+      a2.reduce(t2, red);
+      rho_g = t2[0] / t2[1];
+    }
+    const T amax = (T)(rho_g * pow(6.283185307179586476925 * RTb, -1.5));
+    const T bmax = (T)(1.0 / (2.0 * RTb));
+    acc.zero();
+    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+      const double* dv = d.dvs + DV * k;
+      double un = udotn(dv, nx, ny, nz, d.snap);
+      T gf, rf;
+      if (un > 0.0) {
+        gf = rowG[k];
+        rf = rowR[k];
+      } else {
+        T cx = (T)(dv[0] - Ub[0]), cy = (T)(dv[1] - Ub[1]), cz = (T)(dv[2] - Ub[2]);
+        gf = amax * exp(-(cx * cx + cy * cy + cz * cz) * bmax);
+        rf = (T)RTb * gf;
+      }
+      rowG[k] = (T)(A * un) * gf;
+      rowR[k] = (T)(A * un) * rf;
+      double wg = dv[3] * un * (double)gf, wr = dv[3] * un * (double)rf;
+      acc.add(0, wg);
+      acc.add(1, dv[0] * wg);
+      acc.add(2, dv[1] * wg);
+      acc.add(3, dv[2] * wg);
+      acc.add(4, dv[5] * wg + wr);
+      acc.add(5, wr);
+    }
+    acc.reduce(tot, red);
+  }
+  if (threadIdx.x < 6) w.face_mac[6 * f + threadIdx.x] = A * tot[threadIdx.x];
+}
+
+template <class T> static bool face_lds_ok(int64_t nv) { return nv * 2 * (int64_t)sizeof(T) <= 64 * 1024; }
+
+template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
+  constexpr bool Comp = sizeof(T) == 4;
+  if (face_lds_ok<T>(d.nv)) {
+    size_t lds = (size_t)d.nv * 2 * sizeof(T);
+    hipLaunchKernelGGL((k_face<T, Comp, true>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
+  } else {
+    hipLaunchKernelGGL((k_face<T, Comp, false>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, w);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 4: implicit macroscopic prediction (Eqs. 38-43), one thread per cell.
+// ---------------------------------------------------------------------------
+
+// Euler flux with the rotational-energy row (Eq. 40), p = rho R T
+__device__ inline void euler_flux(const double* W, double nx, double ny, double nz, double* out) {
+  double ir = 1.0 / W[0];
+  double Ux = W[1] * ir, Uy = W[2] * ir, Uz = W[3] * ir;
+  double p = 0.4 * (W[4] - 0.5 * W[0] * (Ux * Ux + Uy * Uy + Uz * Uz));
+  double Un = Ux * nx + Uy * ny + Uz * nz;
+  out[0] = W[0] * Un;
+  out[1] = W[1] * Un + p * nx;
+  out[2] = W[2] * Un + p * ny;
+  out[3] = W[3] * Un + p * nz;
+  out[4] = (W[4] + p) * Un;
+  out[5] = W[5] * Un;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_prim(Dev d, const double* W, Work w) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.nc) return;
+  Prim p = prim_of(W + 6 * i, d.gas.R);
+  double* o = w.cell_prim + 8 * i;
+  o[0] = p.rho;
+  o[1] = p.U[0];
+  o[2] = p.U[1];
+  o[3] = p.U[2];
+  o[4] = p.T;
+  o[5] = p.Ttr;
+  o[6] = visc(p.Ttr, d.gas) / (p.rho * d.gas.R * p.Ttr);
+  o[7] = 0.0;
+}
+
+// Macro flux per cell (Eq. 37), diagonal D_i and right-hand side Res_i of Eq. 43, spectral radii r_ij (Eq. 41)
+__global__ __launch_bounds__(kBlock) void k_macro_prep(Dev d, const double* W, Work w) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.nc) return;
+  const double* geo = d.cell_geo + CG * i;
+  const double* pa = w.cell_prim + 8 * i;
+  const GasC& g = d.gas;
+  double F[6] = {0, 0, 0, 0, 0, 0};
+  double acc = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    int32_t nb = d.cell_nb[4 * i + a];
+    int32_t f = d.cell_face[4 * i + a];
+    const double* pb = nb >= 0 ? w.cell_prim + 8 * (int64_t)nb : pa;
+    // face state: arithmetic mean of the two cells
+    double rho = 0.5 * (pa[0] + pb[0]);
+    double T = 0.5 * (pa[4] + pb[4]);
+    double Ttr = 0.5 * (pa[5] + pb[5]);
+    double Un = 0.5 * (pa[1] + pb[1]) * s[2] + 0.5 * (pa[2] + pb[2]) * s[3] + 0.5 * (pa[3] + pb[3]) * s[4];
+    double r = fabs(Un) + sqrt(g.gamma * g.R * T) + 2.0 * visc(Ttr, g) / (rho * d.face_geo[FGW * (int64_t)f + 5]);
+    w.rcf[4 * i + a] = r;
+    acc += 0.5 * s[1] * r;
+    const double* fm = w.face_mac + 6 * (int64_t)f;
+    for (int m = 0; m < 6; ++m) F[m] += s[0] * fm[m] * geo[1];
+  }
+  const double tau = pa[6];
+  const double D = inv_dt_cell(d, geo[2]) + acc;
+  w.mD[2 * i] = D;
+  w.mD[2 * i + 1] = D + 1.0 / (g.Z * tau);
+  for (int m = 0; m < 6; ++m) {
+    w.Fmac[6 * i + m] = F[m];
+    w.mres[6 * i + m] = -F[m];
+    w.dW[6 * i + m] = 0.0;
+  }
+  w.mres[6 * i + 5] += (pa[0] * g.R * pa[4] - W[6 * i + 5]) / (g.Z * tau);
+}
+
+__global__ __launch_bounds__(kBlock) void k_macro_sweep(Dev d, const double* W, Work w, int64_t c0, int64_t c1) {
+  int64_t i = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c1) return;
+  const double* geo = d.cell_geo + CG * i;
+  double acc[6];
+  for (int m = 0; m < 6; ++m) acc[m] = w.mres[6 * i + m];
+  for (int a = 0; a < 4; ++a) {
+    int32_t nb = d.cell_nb[4 * i + a];
+    if (nb < 0) continue;
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    const double* Wj = W + 6 * (int64_t)nb;
+    const double* dWj = w.dW + 6 * (int64_t)nb;
+    double Wp[6], G1[6], G0[6];
+    for (int m = 0; m < 6; ++m) Wp[m] = Wj[m] + dWj[m];
+    euler_flux(Wp, s[2], s[3], s[4], G1);
+    euler_flux(Wj, s[2], s[3], s[4], G0);
+    double r = w.rcf[4 * i + a];
+    for (int m = 0; m < 6; ++m) acc[m] -= 0.5 * s[1] * ((G1[m] - G0[m]) - r * dWj[m]);
+  }
+  double D = w.mD[2 * i], D5 = w.mD[2 * i + 1];
+  for (int m = 0; m < 5; ++m) w.dW[6 * i + m] = acc[m] / D;
+  w.dW[6 * i + 5] = acc[5] / D5;
+}
+
+// W~ = W^n + dW~; predicted equilibrium coefficients with q~ = q^n
+__global__ __launch_bounds__(kBlock) void k_cell_eq(Dev d, const double* W, const double* q, Work w) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.nc) return;
+  double Wt[6];
+  for (int m = 0; m < 6; ++m) {
+    Wt[m] = W[6 * i + m] + w.dW[6 * i + m];
+    w.Wt[6 * i + m] = Wt[m];
+  }
+  Prim p = prim_of(Wt, d.gas.R);
+  if (!(p.rho > 0.0) || !(p.T > 0.0) || !(p.Ttr > 0.0) || !(p.Trot > 0.0)) atomicOr(&w.flag[0], 1);
+  double* e = w.eq + ER * i;
+  eq_coeffs(p, q + 6 * i, d.gas, e);
+  e[7] = visc(p.Ttr, d.gas) / (p.rho * d.gas.R * p.Ttr);
+}
+
+__global__ __launch_bounds__(kBlock) void k_macro_flux_cells(Dev d, Work w) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.nc) return;
+  const double* geo = d.cell_geo + CG * i;
+  double F[6] = {0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 4; ++a) {
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    const double* fm = w.face_mac + 6 * (int64_t)d.cell_face[4 * i + a];
+    for (int m = 0; m < 6; ++m) F[m] += s[0] * fm[m] * geo[1];
+  }
+  for (int m = 0; m < 6; ++m) w.Fmac[6 * i + m] = F[m];
+}
+
+void launch_macro_flux_cells(const Dev& d, const Work& w, hipStream_t st) {
+  int nb = (int)((d.nc + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_macro_flux_cells, dim3(nb), dim3(kBlock), 0, st, d, w);
+}
+
+void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_macro,
+                  hipStream_t st) {
+  int nb = (int)((d.nc + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_cell_prim, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, w);
+  hipLaunchKernelGGL(k_macro_prep, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, w);
+  for (int it = 0; it < n_macro; ++it) {
+    for (int64_t c = 0; c < n_colors; ++c) {
+      int64_t n = color_off[c + 1] - color_off[c];
+      if (n <= 0) continue;
+      hipLaunchKernelGGL(k_macro_sweep, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d,
+                         (const double*)b.W, w, color_off[c], color_off[c + 1]);
+    }
+    for (int64_t c = n_colors - 1; c >= 0; --c) {
+      int64_t n = color_off[c + 1] - color_off[c];
+      if (n <= 0) continue;
+      hipLaunchKernelGGL(k_macro_sweep, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d,
+                         (const double*)b.W, w, color_off[c], color_off[c + 1]);
+    }
+  }
+  hipLaunchKernelGGL(k_cell_eq, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, (const double*)b.q, w);
+}
+
+// ---------------------------------------------------------------------------
+// Step 4-5: micro flux per cell (Eq. 31) and right-hand side of Eq. 33, Res = (phi~* - phi)/tau~ - F.
+// flux_only = 1 writes F instead (explicit operator).
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* outG, T* outR, int flux_only) {
+  const int64_t i = blockIdx.x;
+  const int64_t nv = d.nv;
+  const double* geo = d.cell_geo + CG * i;
+  int64_t fr[4];
+  T sg[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    fr[a] = (int64_t)d.cell_face[4 * i + a] * nv;
+    sg[a] = (T)(geo[CG_FACE + CG_SLOT * a] * geo[1]);
+  }
+  const T* fG = (const T*)b.faceG;
+  const T* fR = (const T*)b.faceR;
+  if (flux_only) {
+    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+      outG[i * nv + k] = sg[0] * fG[fr[0] + k] + sg[1] * fG[fr[1] + k] + sg[2] * fG[fr[2] + k] + sg[3] * fG[fr[3] + k];
+      outR[i * nv + k] = sg[0] * fR[fr[0] + k] + sg[1] * fR[fr[1] + k] + sg[2] * fR[fr[2] + k] + sg[3] * fR[fr[3] + k];
+    }
+    return;
+  }
+  const double* ec = w.eq + ER * i;
+  Eq<T> e;
+  e.load(ec);
+  const T itau = (T)(1.0 / ec[7]);
+  const T* G = (const T*)b.G;
+  const T* R = (const T*)b.R;
+  for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+    const double* dv = d.dvs + DV * k;
+    T FG = sg[0] * fG[fr[0] + k] + sg[1] * fG[fr[1] + k] + sg[2] * fG[fr[2] + k] + sg[3] * fG[fr[3] + k];
+    T FR = sg[0] * fR[fr[0] + k] + sg[1] * fR[fr[1] + k] + sg[2] * fR[fr[2] + k] + sg[3] * fR[fr[3] + k];
+    T gs, rs;
+    e.eval((T)dv[0], (T)dv[1], (T)dv[2], gs, rs);
+    outG[i * nv + k] = (gs - G[i * nv + k]) * itau - FG;
+    outR[i * nv + k] = (rs - R[i * nv + k]) * itau - FR;
+  }
+}
+
+template <class T>
+void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR, int flux_only, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, b, w, (T*)outG, (T*)outR, flux_only);
+}
+
+// ---------------------------------------------------------------------------
+// Step 5: PR-SGS sweep of Eq. 33 over one colour, first-order upwind increments (Eq. 32).
+// D_ik = 1/dt_i + 1/tau~_i + sum_f (A/V) max(u.n, 0) in FP64.  In the first forward sweep the
+// increments of later colours are still zero and are not read.
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, int64_t c0, int64_t cnext, int first) {
+  const int64_t i = c0 + blockIdx.x;
+  const int64_t nv = d.nv;
+  const double* geo = d.cell_geo + CG * i;
+  int64_t nrow[4];
+  bool use[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int32_t nb = d.cell_nb[4 * i + a];
+    use[a] = nb >= 0 && !(first && nb >= cnext);
+    nrow[a] = nb >= 0 ? (int64_t)nb * nv : 0;
+  }
+  const double base = inv_dt_cell(d, geo[2]) + 1.0 / w.eq[ER * i + 7];
+  const T* rG = (const T*)b.resG;
+  const T* rR = (const T*)b.resR;
+  T* dG = (T*)b.dG;
+  T* dR = (T*)b.dR;
+  for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+    const double* dv = d.dvs + DV * k;
+    double D = base;
+    double aG = (double)rG[i * nv + k], aR = (double)rR[i * nv + k];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double* s = geo + CG_FACE + CG_SLOT * a;
+      double un = udotn(dv, s[2], s[3], s[4], d.snap);
+      double av = s[1];
+      D += av * fmax(un, 0.0);
+      if (use[a] && un < 0.0) {
+        aG -= av * un * (double)dG[nrow[a] + k];
+        aR -= av * un * (double)dR[nrow[a] + k];
+      }
+    }
+    dG[i * nv + k] = (T)(aG / D);
+    dR[i * nv + k] = (T)(aR / D);
+  }
+}
+
+template <class T>
+void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_micro,
+                  hipStream_t st) {
+  for (int it = 0; it < n_micro; ++it) {
+    for (int64_t c = 0; c < n_colors; ++c) {
+      int64_t n = color_off[c + 1] - color_off[c];
+      if (n <= 0) continue;
+      hipLaunchKernelGGL(k_micro_sweep<T>, dim3((unsigned)n), dim3(kBlock), 0, st, d, b, w, color_off[c],
+                         color_off[c + 1], it == 0 ? 1 : 0);
+    }
+    for (int64_t c = n_colors - 1; c >= 0; --c) {
+      int64_t n = color_off[c + 1] - color_off[c];
+      if (n <= 0) continue;
+      hipLaunchKernelGGL(k_micro_sweep<T>, dim3((unsigned)n), dim3(kBlock), 0, st, d, b, w, color_off[c],
+                         color_off[c + 1], 0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 6: phi^{n+1} = phi^n + dphi and the integral error compensation (Eqs. 62-67), c = u - U~;
+// Step 7: per-cell |W^{n+1} - W^n|, reduced by k_reduce_res.
+// ---------------------------------------------------------------------------
+
+template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update(Dev d, Bufs b, Work w) {
+  __shared__ double red[kWaves * 2 * 12];
+  const int64_t i = blockIdx.x;
+  const int64_t nv = d.nv;
+  const double* ec = w.eq + ER * i;
+  Eq<T> e;
+  e.load(ec);
+  const double Ux = ec[1], Uy = ec[2], Uz = ec[3];
+  T* G = (T*)b.G;
+  T* R = (T*)b.R;
+  const T* dG = (const T*)b.dG;
+  const T* dR = (const T*)b.dR;
+  Acc<12, Comp> acc;
+  acc.zero();
+  for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+    const double* dv = d.dvs + DV * k;
+    T g = G[i * nv + k] + dG[i * nv + k];
+    T r = R[i * nv + k] + dR[i * nv + k];
+    G[i * nv + k] = g;
+    R[i * nv + k] = r;
+    T gs, rs;
+    e.eval((T)dv[0], (T)dv[1], (T)dv[2], gs, rs);
+    double gd = (double)g - (double)gs, rd = (double)r - (double)rs;
+    double wk = dv[3];
+    double cx = dv[0] - Ux, cy = dv[1] - Uy, cz = dv[2] - Uz;
+    double c2 = cx * cx + cy * cy + cz * cz;
+    double wg = wk * gd, wr = wk * rd;
+    acc.add(0, wg);
+    acc.add(1, dv[0] * wg);
+    acc.add(2, dv[1] * wg);
+    acc.add(3, dv[2] * wg);
+    acc.add(4, dv[5] * wg + wr);
+    acc.add(5, wr);
+    double hc = 0.5 * c2 * wg;
+    acc.add(6, cx * hc);
+    acc.add(7, cy * hc);
+    acc.add(8, cz * hc);
+    acc.add(9, cx * wr);
+    acc.add(10, cy * wr);
+    acc.add(11, cz * wr);
+  }
+  double s[12];
+  acc.reduce(s, red);
+  if (threadIdx.x == 0) {
+    const GasC& g = d.gas;
+    const double* Wt = w.Wt + 6 * i;
+    double* W = b.W + 6 * i;
+    double* q = b.q + 6 * i;
+    double Wn[6], qn[6];
+    Wn[0] = s[0] + Wt[0];                                                   // Eq. 62
+    Wn[1] = s[1] + Wt[1];                                                   // Eq. 63
+    Wn[2] = s[2] + Wt[2];
+    Wn[3] = s[3] + Wt[3];
+    Wn[4] = s[4] + Wt[4];                                                   // Eq. 64
+    Wn[5] = s[5] + ec[0] * g.R * ((1.0 - 1.0 / g.Z) * ec[6] + ec[4] / g.Z);  // Eq. 65
+    const double ctr = (1.0 / 3.0) * (1.0 - (1.0 - g.omega0) / g.Z);
+    const double crot = (1.0 - g.delta) * (1.0 - (1.0 - g.omega1) / g.Z);
+    for (int m = 0; m < 3; ++m) {
+      qn[m] = s[6 + m] + q[m] * ctr;          // Eq. 66
+      qn[3 + m] = s[9 + m] + q[3 + m] * crot;  // Eq. 67
+    }
+    for (int m = 0; m < 6; ++m) {
+      w.cellres[6 * i + m] = fabs(Wn[m] - W[m]);
+      W[m] = Wn[m];
+      q[m] = qn[m];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_res(int64_t nc, const double* cellres, double* res, int32_t* flag,
+                                                       const double* W) {
+  __shared__ double red[kWaves * 2 * 6];
+  Acc<6, false> acc;
+  acc.zero();
+  int bad = 0;
+  for (int64_t i = threadIdx.x; i < nc; i += kBlock) {
+    for (int m = 0; m < 6; ++m) acc.add(m, cellres[6 * i + m]);
+    const double* Wi = W + 6 * i;
+    double ke = 0.5 * (Wi[1] * Wi[1] + Wi[2] * Wi[2] + Wi[3] * Wi[3]) / Wi[0];
+    if (!(Wi[0] > 0.0) || !(Wi[4] - ke > 0.0) || !(Wi[5] > 0.0)) bad = 1;
+  }
+  double tot[6];
+  acc.reduce(tot, red);
+  if (bad) atomicOr(&flag[0], 2);
+  if (threadIdx.x < 6) {
+    double v = tot[threadIdx.x] / (double)nc;
+    res[threadIdx.x] = v;
+    if (!isfinite(v)) atomicOr(&flag[0], 4);
+  }
+}
+
+template <class T> void launch_update(const Dev& d, const Bufs& b, const Work& w, int64_t it, hipStream_t st) {
+  constexpr bool Comp = sizeof(T) == 4;
+  hipLaunchKernelGGL((k_update<T, Comp>), dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, b, w);
+  hipLaunchKernelGGL(k_reduce_res, dim3(1), dim3(kBlock), 0, st, d.nc, (const double*)w.cellres, w.res + 6 * it,
+                     w.flag, (const double*)b.W);
+}
+
+// explicit instantiations
+template void launch_init_eq<double>(const Dev&, const Bufs&, const double*, int, double*, hipStream_t);
+template void launch_init_eq<float>(const Dev&, const Bufs&, const double*, int, double*, hipStream_t);
+template void launch_recon<double>(const Dev&, const Bufs&, hipStream_t);
+template void launch_recon<float>(const Dev&, const Bufs&, hipStream_t);
+template void launch_face<double>(const Dev&, const Bufs&, const Work&, hipStream_t);
+template void launch_face<float>(const Dev&, const Bufs&, const Work&, hipStream_t);
+template void launch_residual<double>(const Dev&, const Bufs&, const Work&, void*, void*, int, hipStream_t);
+template void launch_residual<float>(const Dev&, const Bufs&, const Work&, void*, void*, int, hipStream_t);
+template void launch_micro<double>(const Dev&, const Bufs&, const Work&, const int64_t*, int64_t, int, hipStream_t);
+template void launch_micro<float>(const Dev&, const Bufs&, const Work&, const int64_t*, int64_t, int, hipStream_t);
+template void launch_update<double>(const Dev&, const Bufs&, const Work&, int64_t, hipStream_t);
+template void launch_update<float>(const Dev&, const Bufs&, const Work&, int64_t, hipStream_t);
+
+}  // namespace cis

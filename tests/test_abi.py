@@ -1,0 +1,114 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared entry point,
+and the host-side validation of meshes, velocity sets and arguments reports the documented errors."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2303_10846_amd import binding
+from paper_2303_10846_amd.cases import configs, mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "cis.h")).read()
+    return sorted(set(re.findall(r"\b(cis_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_what_the_binding_expects():
+    assert declared_symbols() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def _mesh_args(m):
+    xyz = np.ascontiguousarray(m["xyz"], dtype=np.float64)
+    tets = np.ascontiguousarray(m["tets"], dtype=np.int32)
+    btri = np.ascontiguousarray(m["btri"], dtype=np.int32)
+    btag = np.ascontiguousarray(m["btag"], dtype=np.int32)
+    off = np.ascontiguousarray(m["color_offsets"], dtype=np.int64)
+    return xyz, tets, btri, btag, off
+
+
+def test_mesh_create_info_and_errors():
+    c = configs.cavity_case(n=2, nv_side=4)
+    mm = binding.Mesh(c["mesh"])
+    info = mm.info
+    assert info.n_cells == 48
+    assert info.n_boundary == len(c["mesh"]["btri"])
+    assert 4 * info.n_cells == 2 * info.n_interior + info.n_boundary
+    # a colouring that puts two neighbours in one colour is rejected
+    bad = dict(c["mesh"], color_offsets=np.array([0, 48]))
+    with pytest.raises(binding.CisError) as e:
+        binding.Mesh(bad)
+    assert e.value.status == -2
+    # an untagged open face is rejected
+    bad = dict(c["mesh"], btri=c["mesh"]["btri"][1:], btag=c["mesh"]["btag"][1:])
+    with pytest.raises(binding.CisError) as e:
+        binding.Mesh(bad)
+    assert e.value.status == -2
+    # a collapsed tet is rejected
+    xyz = c["mesh"]["xyz"].copy()
+    t0 = c["mesh"]["tets"][0]
+    xyz[t0[3]] = xyz[t0[0]]
+    with pytest.raises(binding.CisError) as e:
+        binding.Mesh(dict(c["mesh"], xyz=xyz))
+    assert e.value.status in (-2,)
+    # offsets not covering the cells
+    with pytest.raises(binding.CisError) as e:
+        binding.Mesh(dict(c["mesh"], color_offsets=np.array([0, 10])))
+    assert e.value.status == -1
+
+
+def test_dvs_validation():
+    u = np.zeros((4, 3))
+    u[:, 0] = [1, 2, 3, 4]
+    with pytest.raises(binding.CisError) as e:
+        binding.Dvs(u, np.array([1.0, 0.0, 1.0, 1.0]))
+    assert e.value.status == -3
+    u2 = u.copy()
+    u2[1, 1] = np.nan
+    with pytest.raises(binding.CisError) as e:
+        binding.Dvs(u2, np.ones(4))
+    assert e.value.status == -3
+    d = binding.Dvs(u, np.ones(4))
+    assert d.n == 4
+
+
+def test_required_bytes():
+    lib = binding.load()
+    c = configs.cavity_case(n=2, nv_side=4)
+    mm = binding.Mesh(c["mesh"])
+    dv = binding.Dvs(c["u"], c["w"])
+    for prec, es in ((binding.FP64, 8), (binding.MIXED, 4)):
+        s = binding.BufferSizes()
+        assert lib.cis_state_required_bytes(mm.h, dv.h, prec, C.byref(s)) == 0
+        assert s.phi_bytes == 48 * 64 * es
+        assert s.face_bytes == mm.info.n_faces * 64 * es
+    s = binding.BufferSizes()
+    assert lib.cis_state_required_bytes(mm.h, dv.h, 7, C.byref(s)) == -1
+
+
+def test_state_create_rejects_null_buffers_before_touching_the_device():
+    lib = binding.load()
+    c = configs.cavity_case(n=2, nv_side=4)
+    mm = binding.Mesh(c["mesh"])
+    dv = binding.Dvs(c["u"], c["w"])
+    gas = binding.gas_struct(c["gas"])
+    num = binding.numerics_struct(c["num"])
+    bufs = binding.DeviceBuffers()
+    h = C.c_void_p()
+    bcs = (binding.Bc * 2)(*[binding.Bc(b["tag"], b["kind"], b["rho"], (C.c_double * 3)(*b["U"]), b["T"])
+                             for b in c["bcs"]])
+    assert lib.cis_state_create(mm.h, dv.h, C.byref(gas), C.byref(num), bcs, 2, 0, C.byref(bufs), None,
+                                C.byref(h)) == -1
+    bad = binding.numerics_struct(dict(c["num"], cfl=-1.0))
+    assert lib.cis_state_create(mm.h, dv.h, C.byref(gas), C.byref(bad), bcs, 2, 0, C.byref(bufs), None,
+                                C.byref(h)) == -1

@@ -1,0 +1,205 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Metric: for an array a against the oracle's b, max|a - b| / max|b| per field
+(per component for W and q).  Bar for the FP64 path: 1e-11.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_10846_amd.cases import configs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def nrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def colrel(a, b):
+    return max(nrel(a[:, m], b[:, m]) for m in range(a.shape[1]))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def solver(case, precision="fp64", num=None):
+    from paper_2303_10846_amd.binding import Solver
+    return Solver(case, precision=precision, num=num)
+
+
+def _pair(case, warm=3, num=None):
+    """Oracle and GPU solver on the same case, both set to the oracle's state after `warm` iterations."""
+    o = oracle.Oracle(case, num=num)
+    o.init_equilibrium(case["W0"])
+    if warm:
+        o.iterate(warm)
+    G, R, W, q = o.get_state()
+    s = solver(case, num=num)
+    s.set_state(G, R, W, q)
+    return o, s
+
+
+CASES = {
+    "cavity_n2_dvs4": lambda: configs.cavity_case(n=2, nv_side=4),          # nv = 64 < one workgroup
+    "cavity_n3_dvs7": lambda: configs.cavity_case(n=3, nv_side=7),          # nv = 343, ragged tail
+    "open_box_n3": lambda: configs.open_box_case(n=3, nv_side=6),           # far field + hot wall
+    "small_sphere": lambda: configs.small_sphere_case(),                    # unstructured DVS, 1944 tets
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_explicit_operator_fp64(name):
+    say("case", name)
+    c = CASES[name]()
+    o, s = _pair(c)
+    o.explicit()
+    FG, FR, Fm = s.residual()
+    assert nrel(FG.cpu().numpy(), o.stage("FG")) < TOL
+    assert nrel(FR.cpu().numpy(), o.stage("FR")) < TOL
+    assert colrel(Fm, o.stage("Fmac")) < TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_one_iteration_stage_by_stage_fp64(name):
+    say("case", name)
+    c = CASES[name]()
+    o, s = _pair(c)
+    ho = o.iterate(1)
+    hs = s.iterate(1)
+    assert colrel(s.debug_stage("dW"), o.stage("dW")) < TOL          # Eq. 43 (40 PR-SGS sweeps)
+    assert colrel(s.debug_stage("Wt"), o.stage("Wt")) < TOL
+    assert nrel(s.debug_stage("tau_t"), o.stage("tau_t")) < TOL
+    assert nrel(s.resG.cpu().numpy(), o.stage("ResG")) < TOL          # Eq. 33 right-hand side
+    assert nrel(s.resR.cpu().numpy(), o.stage("ResR")) < TOL
+    assert nrel(s.dG.cpu().numpy(), o.stage("dG")) < TOL              # 2 PR-SGS sweeps of Eq. 33
+    assert nrel(s.dR.cpu().numpy(), o.stage("dR")) < TOL
+    G, R, W, q = s.get_state()
+    Go, Ro, Wo, qo = o.get_state()
+    assert nrel(G, Go) < TOL and nrel(R, Ro) < TOL
+    assert colrel(W, Wo) < TOL                                        # Eqs. 62-65
+    assert colrel(q, qo) < 1e-10                                      # Eqs. 66-67 (small, cancelling sums)
+    assert np.max(np.abs(hs - ho)) <= 1e-11 * np.max(np.abs(ho)) + 1e-20
+
+
+def test_cavity_full_config_200_iterations_fp64():
+    """The 6x6x6x6-tet cavity with the 8^3 DVS (1296 x 512), 200 iterations from rest."""
+    c = configs.cavity_case(seed=0)
+    say("case", c["name"])
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    s = solver(c)
+    s.init_equilibrium(c["W0"])
+    for n in (1, 9, 190):
+        ho = o.iterate(n)
+        hs = s.iterate(n)
+        _, _, Wo, _ = o.get_state()
+        W, _ = s.moments()
+        e = colrel(W, Wo)
+        say(f"after {n} more iterations: W parity {e:.2e}, residual gpu {hs[-1].max():.2e} oracle {ho[-1].max():.2e}")
+        assert e < TOL
+    assert hs[-1].max() < 1e-13
+    ql, qw = s.wall_heat_flux(2), s.wall_heat_flux(1)
+    assert abs(ql - o.wall_heat_flux(2)) < 1e-11 * abs(ql)
+    assert abs(ql + qw) < 1e-10 * abs(ql)
+
+
+def test_small_sphere_from_rest_ten_iterations_fp64():
+    c = configs.small_sphere_case()
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    s = solver(c)
+    s.init_equilibrium(c["W0"])
+    ho = o.iterate(10)
+    hs = s.iterate(10)
+    _, _, Wo, qo = o.get_state()
+    W, q = s.moments()
+    assert colrel(W, Wo) < TOL
+    assert colrel(q, qo) < 1e-10
+    assert np.max(np.abs(hs - ho) / np.maximum(np.abs(ho), 1e-300)) < 1e-9
+    assert abs(s.wall_heat_flux(1) - o.wall_heat_flux(1)) < 1e-11 * abs(o.wall_heat_flux(1))
+
+
+def test_large_dvs_takes_the_global_memory_face_path():
+    """nv = 17^3 = 4913 > 4096: the face kernel re-reads phi_bar from global memory instead of LDS (FP64)."""
+    c = configs.cavity_case(n=2, nv_side=17)
+    o, s = _pair(c, warm=2)
+    o.iterate(1)
+    s.iterate(1)
+    G, R, W, q = s.get_state()
+    Go, Ro, Wo, qo = o.get_state()
+    assert nrel(G, Go) < TOL and colrel(W, Wo) < TOL
+
+
+def test_determinism_bitwise():
+    c = configs.small_sphere_case()
+    outs = []
+    for _ in range(2):
+        s = solver(c)
+        s.init_equilibrium(c["W0"])
+        s.iterate(3)
+        outs.append(s.get_state())
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_uniform_free_stream_zero_residual_on_gpu():
+    from paper_2303_10846_amd.cases import dvs
+    U = np.array([0.3, -0.1, 0.2])
+    c = configs.freestream_box_case(n=2, U=U, dvs=dvs.gauss_hermite_dvs(6, U, 1.0))
+    s = solver(c)
+    s.init_equilibrium(c["W0"])
+    G0, _, W0, _ = s.get_state()
+    h = s.iterate(2)
+    G1, _, W1, _ = s.get_state()
+    assert h.max() < 1e-14
+    assert nrel(G1, G0) < 1e-13 and colrel(W1, W0) < 1e-14
+
+
+def test_nonfinite_state_is_reported():
+    """A negative density planted from the host is reported as CIS_E_NONFINITE (no kernel faults)."""
+    from paper_2303_10846_amd.binding import CisError
+    c = configs.cavity_case(n=2, nv_side=4)
+    s = solver(c)
+    s.init_equilibrium(c["W0"])
+    G, R, W, q = s.get_state()
+    W[3, 0] = -1.0
+    s.set_state(G, R, W, q)
+    with pytest.raises(CisError) as e:
+        s.iterate(1)
+    assert e.value.status == -5
+
+
+def test_mixed_precision_cavity_converged_fields():
+    """FP32 distributions and flux kernels, FP64 compensated moments/macro/diagonal: error of the
+    converged density, temperature and wall heat flux against the FP64 oracle."""
+    c = configs.cavity_case(seed=0)
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(200)
+    _, _, Wo, _ = o.get_state()
+    s = solver(c, precision="mixed")
+    s.init_equilibrium(c["W0"])
+    h = s.iterate(200)
+    W, _ = s.moments()
+
+    def rho_T(W):
+        rho = W[:, 0]
+        ke = 0.5 * np.sum(W[:, 1:4] ** 2, axis=1) / rho
+        return rho, 0.4 * (W[:, 4] - ke) / (rho * 0.5)
+
+    r, T = rho_T(W)
+    ro, To = rho_T(Wo)
+    er, eT = nrel(r, ro), nrel(T, To)
+    eq = abs(s.wall_heat_flux(2) - o.wall_heat_flux(2)) / abs(o.wall_heat_flux(2))
+    say(f"mixed vs FP64 oracle: rho {er:.2e} T {eT:.2e} Q_lid {eq:.2e}; final residual {h[-1].max():.2e}")
+    assert er < 1e-5 and eT < 1e-5 and eq < 1e-5
