@@ -96,11 +96,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the DVS-sharded multi-GPU path is a design, not code); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe_mb:
+        import torch
+        n = args.copy_probe_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.mul(a, 2.0, out=b)   # one elementwise kernel: reads n floats, writes n floats
+        torch.cuda.synchronize()
+        print(f"bench: copy probe {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written",
+              file=sys.stderr, flush=True)
+        del a, b
     from paper_2303_10846_amd.cases import configs
     case = configs.sphere_case(seed=0)
     print(f"bench: {case['name']} tets={len(case['mesh']['tets'])} nv={len(case['u'])}", file=sys.stderr, flush=True)

@@ -69,7 +69,8 @@ _lib = None
 
 
 def lib_path() -> str:
-    return _build.LIB
+    """The library this process loads: $CIS_LIBRARY if set (alternative builds), else the in-tree build."""
+    return os.environ.get("CIS_LIBRARY") or _build.LIB
 
 
 def load(allow_build: bool = True):
@@ -77,11 +78,12 @@ def load(allow_build: bool = True):
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB):
-        if not allow_build:
-            raise RuntimeError(f"libcis.so is not built ({_build.LIB}); run paper_2303_10846_amd/build.py")
+    path = lib_path()
+    if not os.path.exists(path):
+        if not allow_build or path != _build.LIB:
+            raise RuntimeError(f"libcis.so is not built ({path}); run paper_2303_10846_amd/build.py")
         _build.build()
-    lib = C.CDLL(_build.LIB)
+    lib = C.CDLL(path)
     P = C.c_void_p
     d = C.POINTER(C.c_double)
     i32 = C.POINTER(C.c_int32)

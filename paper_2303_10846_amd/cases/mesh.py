@@ -17,6 +17,7 @@ import math
 import numpy as np
 
 __all__ = [
+    "folded_faces",
     "kuhn_box_mesh",
     "shell_mesh",
     "sphere_body",
@@ -71,6 +72,23 @@ def _match_faces(tets: np.ndarray):
 
 def boundary_triangles(tets: np.ndarray) -> np.ndarray:
     return _match_faces(tets)[1]
+
+
+def folded_faces(xyz: np.ndarray, tets: np.ndarray) -> int:
+    """Number of interior faces whose two tets lie on the same side of the face plane (a folded mesh)."""
+    keys = _face_keys(tets)
+    owner = np.repeat(np.arange(len(tets)), 4)
+    opp = tets[:, [0, 1, 2, 3]].reshape(-1)  # vertex opposite face slot a is tets[:, a]
+    order = np.lexsort((keys[:, 2], keys[:, 1], keys[:, 0]))
+    ks = keys[order]
+    same = np.nonzero(np.all(ks[1:] == ks[:-1], axis=1))[0]
+    fa, fb = order[same], order[same + 1]
+    k = keys[fa]
+    a, b, c = xyz[k[:, 0]], xyz[k[:, 1]], xyz[k[:, 2]]
+    n = np.cross(b - a, c - a)
+    sa = np.einsum("ij,ij->i", xyz[opp[fa]] - a, n)
+    sb = np.einsum("ij,ij->i", xyz[opp[fb]] - a, n)
+    return int(np.sum(sa * sb >= 0.0))
 
 
 def color_major(xyz: np.ndarray, tets: np.ndarray):
@@ -256,7 +274,7 @@ def _cubed_sphere_dirs(n: int):
 
 
 def shell_mesh(body, n_ang: int, n_rad: int, r_far: float, first_layer: float, seed: int = 0,
-               jitter: float = 0.1):
+               jitter: float = 0.1, smooth_passes: int = 0):
     """Graded tetrahedral shell between a star-shaped body and a far-field sphere.
 
     Nodes sit on rays of an equiangular cubed sphere; along each ray the layers
@@ -264,12 +282,32 @@ def shell_mesh(body, n_ang: int, n_rad: int, r_far: float, first_layer: float, s
     Each hexahedron is split into 6 pyramids on its centre, and every pyramid
     base is cut along the diagonal through its lowest-numbered node, so the
     12-tet split is conforming.  Interior layer nodes get an isotropic
-    U(-j, j)^3 jitter scaled by the local radial spacing.
+    U(-j, j)^3 jitter scaled by the local radial spacing; a draw that folds the mesh
+    (two tets on one side of their shared face) or makes a volume non-positive is redrawn.
+    ``smooth_passes`` rounds sharp body edges by smoothing the wall radius over the ray grid.
     Tags: 1 = wall, 2 = far field.
     """
     inside, centre = body
     dirs, pidx = _cubed_sphere_dirs(n_ang)
     rb = _ray_hit(inside, centre, dirs, rmax=r_far)
+    if smooth_passes:
+        # round sharp edges of the body: Laplacian smoothing of the wall radius over the direction grid
+        edges = set()
+        for p in range(6):
+            P = pidx[p]
+            for i in range(n_ang + 1):
+                for j in range(n_ang + 1):
+                    if i < n_ang:
+                        edges.add((min(P[i, j], P[i + 1, j]), max(P[i, j], P[i + 1, j])))
+                    if j < n_ang:
+                        edges.add((min(P[i, j], P[i, j + 1]), max(P[i, j], P[i, j + 1])))
+        e = np.array(sorted(edges))
+        deg = np.bincount(e.ravel(), minlength=len(dirs)).astype(float)
+        for _ in range(smooth_passes):
+            acc = np.zeros(len(dirs))
+            np.add.at(acc, e[:, 0], rb[e[:, 1]])
+            np.add.at(acc, e[:, 1], rb[e[:, 0]])
+            rb = 0.5 * rb + 0.5 * acc / deg
     # geometric grading on the unit interval with a first step first_layer/(r_far-mean rb)
     span = r_far - rb.mean()
     f = first_layer / span
@@ -341,10 +379,10 @@ def shell_mesh(body, n_ang: int, n_rad: int, r_far: float, first_layer: float, s
         tets = np.concatenate(tets)
         tets = _orient(allxyz, tets)
         vol = tet_volumes(allxyz, tets)
-        if np.all(vol > 1e-14):
+        if np.all(vol > 1e-14) and folded_faces(allxyz, tets) == 0:
             break
     else:
-        raise RuntimeError("shell mesh: non-positive tet volume after 50 jitter draws")
+        raise RuntimeError("shell mesh: folded or degenerate tets after 50 jitter draws")
 
     tets_c, offsets = color_major(allxyz, tets)
     bkeys = boundary_triangles(tets_c)

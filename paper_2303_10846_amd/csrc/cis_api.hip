@@ -380,7 +380,8 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
     return fail(CIS_E_INVALID_ARG, "a device buffer is NULL");
   if (!(gas->R > 0) || !(gas->gamma > 1) || !(gas->Z > 0) || !(gas->mu_ref > 0) || !(gas->T_ref > 0))
     return fail(CIS_E_INVALID_ARG, "gas constants out of range");
-  if (dv->n > (int64_t)INT32_MAX) return fail(CIS_E_UNSUPPORTED, "velocity set too large");
+  if (dv->n > (int64_t)max_velocities())
+    return fail(CIS_E_UNSUPPORTED, "velocity set larger than " + std::to_string(max_velocities()));
   for (int b = 0; b < n_bc; ++b) {
     if ((bc[b].kind != CIS_BC_WALL && bc[b].kind != CIS_BC_FARFIELD) || !(bc[b].T > 0.0) ||
         (bc[b].kind == CIS_BC_FARFIELD && !(bc[b].rho > 0.0)))
@@ -467,15 +468,18 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
         sl[9 + r] = interior ? (I[3 * r] * dvec[a][0] + I[3 * r + 1] * dvec[a][1] + I[3 * r + 2] * dvec[a][2]) / det : 0.0;
     }
   }
-  std::vector<double> dvsv(DV * nv, 0.0);
-  std::vector<float> dvsf(DV * nv, 0.0f);
+  std::vector<double> dvsv(DVS_ARRAYS * nv, 0.0);
+  std::vector<float> dvsf(DVS_F_ARRAYS * nv, 0.0f);
   for (int64_t k = 0; k < nv; ++k) {
-    double* p = &dvsv[DV * k];
-    for (int d = 0; d < 3; ++d) p[d] = dv->u[3 * k + d];
-    p[3] = dv->w[k];
-    p[4] = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-    p[5] = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-    for (int x = 0; x < DV; ++x) dvsf[DV * k + x] = (float)p[x];
+    const double* u = &dv->u[3 * k];
+    double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int d = 0; d < 3; ++d) {
+      dvsv[d * nv + k] = u[d];
+      dvsf[d * nv + k] = (float)u[d];
+    }
+    dvsv[3 * nv + k] = dv->w[k];
+    dvsv[4 * nv + k] = std::sqrt(u2);
+    dvsv[5 * nv + k] = 0.5 * u2;
   }
   std::vector<double> bct(BCW * std::max(n_bc, 1), 0.0);
   for (int b = 0; b < n_bc; ++b) {
@@ -502,6 +506,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   chk(own_alloc(s, &w.face_mac, 6 * nf));
   chk(own_alloc(s, &w.cell_prim, 8 * nc));
   chk(own_alloc(s, &w.rcf, 4 * nc));
+  chk(own_alloc(s, &w.G0, 24 * nc));
   chk(own_alloc(s, &w.mres, 6 * nc));
   chk(own_alloc(s, &w.mD, 2 * nc));
   chk(own_alloc(s, &w.Fmac, 6 * nc));
@@ -510,6 +515,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   chk(own_alloc(s, &w.eq, ER * nc));
   chk(own_alloc(s, &w.cellres, 6 * nc));
   chk(own_alloc(s, &w.flag, 4));
+  chk(own_alloc(s, &w.respart, 6 * 256));
   s->res_cap = 64;
   chk(own_alloc(s, &w.res, 6 * s->res_cap));
   if (e != CIS_OK) {
@@ -657,7 +663,7 @@ cis_status cis_iterate(cis_state* s, int32_t n_iter, double* res_hist) {
     (void)hipStreamSynchronize(s->stream);
     int64_t nonempty = 0;
     for (int64_t c = 0; c < m->n_colors; ++c) nonempty += (m->color_off[c + 1] > m->color_off[c]);
-    const int64_t per_it[6] = {1, 1, 3 + 2 * (int64_t)s->num.n_macro * nonempty, 1, 2 * (int64_t)s->num.n_micro * nonempty, 2};
+    const int64_t per_it[6] = {1, 1, 3 + 2 * (int64_t)s->num.n_macro * nonempty, 1, 2 * (int64_t)s->num.n_micro * nonempty, 3};
     for (int32_t it = 0; it < n_iter; ++it)
       for (int k = 0; k < 6; ++k) {
         float ms = 0.0f;

@@ -18,8 +18,17 @@ constexpr int CG_SLOT = 12;
 // Per-face record, FP64, FGW doubles: [0] A  [1..3] unit normal (out of face_cell[2f])  [4] s  [5] dl
 constexpr int FGW = 8;
 
-// DVS record, DV values per velocity: [0..2] u  [3] w  [4] |u|  [5] |u|^2/2  [6..7] unused
-constexpr int DV = 8;
+// DVS, structure of arrays: dvs = 6 FP64 arrays of nv values (u_x, u_y, u_z, w, |u|, |u|^2/2),
+// dvs_f = 3 FP32 arrays (u_x, u_y, u_z) for the FP32 equilibrium evaluation of the mixed mode.
+constexpr int DVS_ARRAYS = 6;
+constexpr int DVS_F_ARRAYS = 3;
+
+// Colour offsets passed by value to the cooperative sweep kernel.
+constexpr int kMaxColors = 15;
+struct ColorOff {
+  int n;
+  int64_t off[kMaxColors + 1];
+};
 
 // Boundary-condition record: [0] kind  [1] rho  [2..4] U  [5] T  [6..7] unused
 constexpr int BCW = 8;
@@ -42,8 +51,8 @@ struct Dev {
   const int32_t* face_cell;  // [nf][2] (cell the normal points out of, other cell or -1)
   const int32_t* face_bc;    // [nf] slot in bc table, -1 interior
   const double* face_geo;    // [nf][FGW]
-  const double* dvs;         // [nv][DV]
-  const float* dvs_f;        // [nv][DV]
+  const double* dvs;         // [DVS_ARRAYS][nv]
+  const float* dvs_f;        // [DVS_F_ARRAYS][nv]
   const double* bc;          // [nbc][BCW]
   GasC gas;
   double snap, lim_K, inv_dt, cfl_imp, umax;
@@ -54,6 +63,7 @@ struct Work {
   double* face_mac;  // [nf][6]
   double* cell_prim; // [nc][8]: rho U T T_tr tau 0
   double* rcf;       // [nc][4]
+  double* G0;        // [nc][4][6] Euler flux of the neighbour's W^n along the outward normal
   double* mres;      // [nc][6]
   double* mD;        // [nc][2]
   double* Fmac;      // [nc][6]
@@ -62,6 +72,7 @@ struct Work {
   double* eq;        // [nc][ER]
   double* cellres;   // [nc][6]
   double* res;       // [hist][6]
+  double* respart;   // [256][6] partial sums of the residual
   int32_t* flag;     // [4]
 };
 
@@ -83,5 +94,6 @@ template <class T> void launch_micro(const Dev& d, const Bufs& b, const Work& w,
                                      int64_t n_colors, int n_micro, hipStream_t st);
 template <class T> void launch_update(const Dev& d, const Bufs& b, const Work& w, int64_t it, hipStream_t st);
 void launch_macro_flux_cells(const Dev& d, const Work& w, hipStream_t st);
+int max_velocities();
 
 }  // namespace cis

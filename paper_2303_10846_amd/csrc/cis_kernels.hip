@@ -1,27 +1,36 @@
 // gfx950 kernels of one implicit iteration of the conservative implicit scheme
 // (arXiv 2303.10846, Sec. 3.5, Steps 2-6).
 //
-// Layout: distributions are [cell][velocity] rows (velocity contiguous), so a
-// workgroup that owns one cell or one face streams whole rows with coalesced
-// 64-wide wavefront accesses.  Per-cell and per-face geometry is read through
-// uniform (scalar) loads.  DVS moment sums are FP64 wavefront reductions
-// (Neumaier-compensated in the mixed-precision mode).  The coloured
-// Gauss-Seidel sweeps launch one kernel per colour: cells of one colour share
-// no face, so they update independently.  Nothing here is a dense
-// contraction; the kernels are bound by HBM bandwidth, not by MFMA.
+// Layout: distributions are [cell][velocity] rows (velocity contiguous); the
+// discrete velocity set is stored as separate coalesced arrays.  Kernels that
+// read neighbour rows (reconstruction, micro residual, micro sweeps) run one
+// workgroup per (cell, chunk of 256 velocities) in chunk-major order, so one
+// velocity chunk of every row is touched within a short window.  Kernels that
+// reduce over the whole velocity set of one face or cell (face pass, update)
+// run one workgroup per face or cell, 4 independent loads per loop trip.  DVS moment sums
+// are FP64 wavefront reductions, Neumaier-compensated across threads in the
+// mixed-precision mode.  The coloured Gauss-Seidel sweeps update one colour at
+// a time: cells of one colour share no face.  Nothing here is a dense
+// contraction; the kernels are bound by HBM bandwidth (and latency), not MFMA.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "cis_internal.h"
 
 namespace cis {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
+constexpr int kBlock = 256;   // threads per workgroup
+// Velocities per thread in the (cell, chunk) kernels, chunk = kBlock * Vpt<T>: 4 in FP32, 1 in FP64 (measured
+// on the sphere workload; larger FP32 chunks amortise the per-cell set-up of each workgroup).
+template <class T> struct Vpt;
+template <> struct Vpt<double> { static constexpr int v = 1; };
+template <> struct Vpt<float> { static constexpr int v = 4; };
 
 // ---------------------------------------------------------------------------
-// Reductions over a 256-thread workgroup (4 wave64 wavefronts)
+// Reductions over a workgroup of NT threads (NT/64 wave64 wavefronts)
 // ---------------------------------------------------------------------------
 
 __device__ inline void two_sum_add(double& s, double& c, double x) {
@@ -30,26 +39,22 @@ __device__ inline void two_sum_add(double& s, double& c, double x) {
   s = t;
 }
 
-// N running sums per thread; Comp selects Neumaier compensation.
-template <int N, bool Comp> struct Acc {
+// N running FP64 sums per thread.  Per-thread partials add a handful of terms in plain FP64; when Comp is set
+// the merge of the partials across the workgroup is Neumaier-compensated.
+template <int N, bool Comp, int NT> struct Acc {
+  static constexpr int NW = NT / 64;
   double s[N];
-  double c[N];
   __device__ inline void zero() {
 #pragma unroll
-    for (int m = 0; m < N; ++m) s[m] = c[m] = 0.0;
+    for (int m = 0; m < N; ++m) s[m] = 0.0;
   }
-  __device__ inline void add(int m, double x) {
-    if (Comp)
-      two_sum_add(s[m], c[m], x);
-    else
-      s[m] += x;
-  }
-  // Block-wide total; every thread receives the same values. red: kWaves * 2N doubles of LDS.
+  __device__ inline void add(int m, double x) { s[m] += x; }
+  // Block-wide totals, identical in every thread.  red: NW * 2N doubles of LDS.
   __device__ inline void reduce(double* out, double* red) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      double a = s[m], b = c[m];
+      double a = s[m], b = 0.0;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         double a2 = __shfl_xor(a, o, 64);
@@ -70,7 +75,7 @@ template <int N, bool Comp> struct Acc {
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       double a = red[m], b = red[N + m];
-      for (int q = 1; q < kWaves; ++q) {
+      for (int q = 1; q < NW; ++q) {
         if (Comp) {
           two_sum_add(a, b, red[q * 2 * N + m]);
           b += red[q * 2 * N + N + m];
@@ -128,15 +133,15 @@ __device__ inline void eq_coeffs(const Prim& p, const double* q, const GasC& g, 
   e[15] = 1.0 / (2.0 * RTtr);
   e[16] = p.rho * pow(twopi * RT, -1.5);
   e[17] = 1.0 / (2.0 * RT);
-  e[18] = 1.0 / (15.0 * RTtr * ptr);                       // Eq. 19
-  e[19] = g.omega0 / (15.0 * RT * pp);                     // Eq. 20
-  e[20] = (1.0 - g.delta) / (RTtr * prot);                 // Eq. 21
-  e[21] = g.omega1 * (1.0 - g.delta) / (RT * pp);          // Eq. 22
+  e[18] = 1.0 / (15.0 * RTtr * ptr);               // Eq. 19
+  e[19] = g.omega0 / (15.0 * RT * pp);             // Eq. 20
+  e[20] = (1.0 - g.delta) / (RTtr * prot);         // Eq. 21
+  e[21] = g.omega1 * (1.0 - g.delta) / (RT * pp);  // Eq. 22
   e[22] = 1.0 / RTtr;
   e[23] = 1.0 / RT;
   e[24] = RTrot;
   e[25] = RT;
-  e[26] = 1.0 - 1.0 / g.Z;                                 // Eqs. 17-18
+  e[26] = 1.0 - 1.0 / g.Z;  // Eqs. 17-18
   e[27] = 1.0 / g.Z;
 }
 
@@ -185,10 +190,31 @@ template <class C> struct Eq {
   }
 };
 
+// One discrete velocity (structure-of-arrays DVS, see DVS_* in cis_internal.h)
+struct Vel {
+  double ux, uy, uz, w, um, h2;
+};
+__device__ inline Vel vel(const Dev& d, int64_t k) {
+  const double* v = d.dvs;
+  const int64_t n = d.nv;
+  return Vel{v[k], v[n + k], v[2 * n + k], v[3 * n + k], v[4 * n + k], v[5 * n + k]};
+}
+template <class T> __device__ inline void vel_t(const Dev& d, int64_t k, T& ux, T& uy, T& uz);
+template <> __device__ inline void vel_t<double>(const Dev& d, int64_t k, double& ux, double& uy, double& uz) {
+  ux = d.dvs[k];
+  uy = d.dvs[d.nv + k];
+  uz = d.dvs[2 * d.nv + k];
+}
+template <> __device__ inline void vel_t<float>(const Dev& d, int64_t k, float& ux, float& uy, float& uz) {
+  ux = d.dvs_f[k];
+  uy = d.dvs_f[d.nv + k];
+  uz = d.dvs_f[2 * d.nv + k];
+}
+
 // u.n with the tie rule (|u.n| <= snap |u| -> 0)
-__device__ inline double udotn(const double* dv, double nx, double ny, double nz, double snap) {
-  double un = dv[0] * nx + dv[1] * ny + dv[2] * nz;
-  return fabs(un) <= snap * dv[4] ? 0.0 : un;
+__device__ inline double udotn(const Vel& v, double nx, double ny, double nz, double snap) {
+  double un = v.ux * nx + v.uy * ny + v.uz * nz;
+  return fabs(un) <= snap * v.um ? 0.0 : un;
 }
 
 __device__ inline double inv_dt_cell(const Dev& d, double h) {
@@ -196,6 +222,23 @@ __device__ inline double inv_dt_cell(const Dev& d, double h) {
   if (d.cfl_imp > 0.0) v += d.umax / (d.cfl_imp * h);
   return v;
 }
+
+template <class T> static inline unsigned n_chunks(int64_t nv) {
+  constexpr int c = kBlock * Vpt<T>::v;
+  return (unsigned)((nv + c - 1) / c);
+}
+
+// Velocity loop of a (cell, chunk) workgroup: Vpt<T> coalesced velocities per thread.
+template <class T, class F> __device__ inline void chunk_loop(int64_t nv, F&& body) {
+  constexpr int U = Vpt<T>::v;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t k = (int64_t)blockIdx.y * (kBlock * U) + (int64_t)u * kBlock + threadIdx.x;
+    if (k < nv) body(k);
+  }
+}
+
+
 
 // ---------------------------------------------------------------------------
 // Step 1: equilibrium initial state
@@ -214,39 +257,39 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_fill_eq(Dev d, const double* eq, T* G, T* R, double* W, double* q,
                                                     const double* W0, int per_cell) {
   const int64_t i = blockIdx.x;
-  Eq<T> e;
-  e.load(eq + ER * i);
-  const double* dvs = d.dvs;
-  for (int64_t k = threadIdx.x; k < d.nv; k += kBlock) {
-    const double* dv = dvs + DV * k;
-    T gs, rs;
-    e.eval((T)dv[0], (T)dv[1], (T)dv[2], gs, rs);
-    G[i * d.nv + k] = gs;
-    R[i * d.nv + k] = rs;
-  }
-  if (threadIdx.x < 6) {
+  const int64_t nv = d.nv;
+  if (blockIdx.y == 0 && threadIdx.x < 6) {
     W[6 * i + threadIdx.x] = per_cell ? W0[6 * i + threadIdx.x] : W0[threadIdx.x];
     q[6 * i + threadIdx.x] = 0.0;
   }
+  Eq<T> e;
+  e.load(eq + ER * i);
+  chunk_loop<T>(nv, [&](int64_t k) {
+    T ux, uy, uz, gs, rs;
+    vel_t<T>(d, k, ux, uy, uz);
+    e.eval(ux, uy, uz, gs, rs);
+    G[i * nv + k] = gs;
+    R[i * nv + k] = rs;
+  });
 }
 
 template <class T>
 void launch_init_eq(const Dev& d, const Bufs& b, const double* W0, int per_cell, double* eqtmp, hipStream_t st) {
   int nb = (int)((d.nc + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_eq_from_W, dim3(nb), dim3(kBlock), 0, st, W0, per_cell, d.gas, d.nc, eqtmp);
-  hipLaunchKernelGGL(k_fill_eq<T>, dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, (const double*)eqtmp, (T*)b.G,
-                     (T*)b.R, b.W, b.q, W0, per_cell);
+  hipLaunchKernelGGL(k_fill_eq<T>, dim3((unsigned)d.nc, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, (const double*)eqtmp,
+                     (T*)b.G, (T*)b.R, b.W, b.q, W0, per_cell);
 }
 
 // ---------------------------------------------------------------------------
 // Step 2(a): least-squares gradient, Venkatakrishnan limiter and upwind reconstruction (Eq. 46).
-// One workgroup per cell; each (face, velocity) value phi_bar is written once, by its upwind cell.
+// Workgroup (cell, velocity chunk); each (face, velocity) value phi_bar is written once, by its upwind cell.
 // ---------------------------------------------------------------------------
 
 template <class T>
 __device__ inline void recon_one(const Dev& d, const T* __restrict__ src, T* __restrict__ dst, int64_t i, int64_t k,
-                                 const int32_t* nb, const int32_t* fc, const double* geo, double kh3,
-                                 const double* dv, const double* un) {
+                                 const int32_t* nb, const int32_t* fc, const double* geo, double kh3, const Vel& v,
+                                 const double* un) {
   const int64_t nv = d.nv;
   T phi = src[i * nv + k];
   T pn[4];
@@ -289,13 +332,14 @@ __device__ inline void recon_one(const Dev& d, const T* __restrict__ src, T* __r
     bool up = nb[a] >= 0 ? (s[0] > 0.0 ? un[a] > 0.0 : un[a] >= 0.0) : un[a] > 0.0;
     if (!up) continue;
     T sf = (T)s[8];
-    T v = phi + ((T)s[5] - (T)dv[0] * sf) * gx + ((T)s[6] - (T)dv[1] * sf) * gy + ((T)s[7] - (T)dv[2] * sf) * gz;
-    dst[(int64_t)fc[a] * nv + k] = v;
+    T val = phi + ((T)s[5] - (T)v.ux * sf) * gx + ((T)s[6] - (T)v.uy * sf) * gy + ((T)s[7] - (T)v.uz * sf) * gz;
+    dst[(int64_t)fc[a] * nv + k] = val;
   }
 }
 
 template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b) {
   const int64_t i = blockIdx.x;
+  const int64_t nv = d.nv;
   int32_t nb[4], fc[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -305,36 +349,55 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   const double* geo = d.cell_geo + CG * i;
   double kh3 = d.lim_K * geo[2];
   kh3 = kh3 * kh3 * kh3;
-  for (int64_t k = threadIdx.x; k < d.nv; k += kBlock) {
-    const double* dv = d.dvs + DV * k;
+  chunk_loop<T>(nv, [&](int64_t k) {
+    const Vel v = vel(d, k);
     double un[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const double* s = geo + CG_FACE + CG_SLOT * a;
-      un[a] = udotn(dv, s[2], s[3], s[4], d.snap);
+      un[a] = udotn(v, s[2], s[3], s[4], d.snap);
     }
-    recon_one<T>(d, (const T*)b.G, (T*)b.faceG, i, k, nb, fc, geo, kh3, dv, un);
-    recon_one<T>(d, (const T*)b.R, (T*)b.faceR, i, k, nb, fc, geo, kh3, dv, un);
-  }
+    recon_one<T>(d, (const T*)b.G, (T*)b.faceG, i, k, nb, fc, geo, kh3, v, un);
+    recon_one<T>(d, (const T*)b.R, (T*)b.faceR, i, k, nb, fc, geo, kh3, v, un);
+  });
 }
 
 template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_recon<T>, dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, b);
+  hipLaunchKernelGGL(k_recon<T>, dim3((unsigned)d.nc, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, b);
 }
 
 // ---------------------------------------------------------------------------
 // Steps 2(b)-(e) and 3 on one face per workgroup: face moments (Eqs. 47-52), face equilibrium,
 // collision-coupled face distribution (Eq. 45), micro flux A (u.n) phi_f (written in place over phi_bar)
 // and the face's macro flux A sum_k w (u.n) Phi phi_f (Eq. 37).  Boundary faces: diffuse wall with rho_w
-// from zero net mass flux, or far-field Maxwellian, for incoming velocities.
+// from zero net mass flux, or far-field Maxwellian, for incoming velocities.  phi_bar is staged in LDS
+// (UseLds) or re-read from global memory; every velocity loop issues kUnroll independent loads per trip.
 // ---------------------------------------------------------------------------
+
+#ifndef CIS_UNROLL
+#define CIS_UNROLL 4
+#endif
+constexpr int kUnroll = CIS_UNROLL;
+
+// Velocity loop of a per-face / per-cell workgroup over all nv velocities, kUnroll independent
+// velocities per trip.
+template <class F> __device__ inline void k_loop(int64_t nv, F&& body) {
+  for (int64_t k0 = threadIdx.x; k0 < nv; k0 += (int64_t)kUnroll * kBlock) {
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const int64_t k = k0 + (int64_t)q * kBlock;
+      if (k < nv) body(k);
+    }
+  }
+}
+
 
 template <class T, bool Comp, bool UseLds>
 __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   extern __shared__ unsigned char smem_raw[];
   T* sG = reinterpret_cast<T*>(smem_raw);
   T* sR = sG + d.nv;
-  __shared__ double red[kWaves * 2 * 6];
+  __shared__ double red[(kBlock / 64) * 2 * 6];
   const int64_t f = blockIdx.x;
   const int64_t nv = d.nv;
   const double* fg = d.face_geo + FGW * f;
@@ -343,27 +406,27 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   T* rowR = (T*)b.faceR + f * nv;
   const int32_t bcs = d.face_bc[f];
   const GasC& g = d.gas;
-  Acc<6, Comp> acc;
+  Acc<6, Comp, kBlock> acc;
   double tot[6];
 
   if (bcs < 0) {
     // pass 1: Eqs. 47-49 and sum_k w R_bar
     acc.zero();
-    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
-      T gb = rowG[k], rb = rowR[k];
+    k_loop(nv, [&](int64_t k) {
+      const T gb = rowG[k], rb = rowR[k];
       if (UseLds) {
         sG[k] = gb;
         sR[k] = rb;
       }
-      const double* dv = d.dvs + DV * k;
-      double wg = dv[3] * (double)gb, wr = dv[3] * (double)rb;
+      const Vel v = vel(d, k);
+      double wg = v.w * (double)gb, wr = v.w * (double)rb;
       acc.add(0, wg);
-      acc.add(1, dv[0] * wg);
-      acc.add(2, dv[1] * wg);
-      acc.add(3, dv[2] * wg);
-      acc.add(4, dv[5] * wg + wr);
+      acc.add(1, v.ux * wg);
+      acc.add(2, v.uy * wg);
+      acc.add(3, v.uz * wg);
+      acc.add(4, v.h2 * wg + wr);
       acc.add(5, wr);
-    }
+    });
     acc.reduce(tot, red);
     const double rho = tot[0];
     const double U[3] = {tot[1] / rho, tot[2] / rho, tot[3] / rho};
@@ -383,20 +446,20 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     p.Ttr = (2.0 / 3.0) * (E - ke - Erot) / rR;
     // pass 2: heat fluxes, Eqs. 51-52, c = u - U_f
     acc.zero();
-    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
-      T gb = UseLds ? sG[k] : rowG[k];
-      T rb = UseLds ? sR[k] : rowR[k];
-      const double* dv = d.dvs + DV * k;
-      double cx = dv[0] - U[0], cy = dv[1] - U[1], cz = dv[2] - U[2];
+    k_loop(nv, [&](int64_t k) {
+      const T gb = UseLds ? sG[k] : rowG[k];
+      const T rb = UseLds ? sR[k] : rowR[k];
+      const Vel v = vel(d, k);
+      double cx = v.ux - U[0], cy = v.uy - U[1], cz = v.uz - U[2];
       double c2 = cx * cx + cy * cy + cz * cz;
-      double wg = dv[3] * c2 * (double)gb, wr = dv[3] * (double)rb;
+      double wg = v.w * c2 * (double)gb, wr = v.w * (double)rb;
       acc.add(0, cx * wg);
       acc.add(1, cy * wg);
       acc.add(2, cz * wg);
       acc.add(3, cx * wr);
       acc.add(4, cy * wr);
       acc.add(5, cz * wr);
-    }
+    });
     acc.reduce(tot, red);
     const double den_tr = tau + s - (s / 3.0) * (1.0 - 1.0 / g.Z + g.omega0 / g.Z);
     const double den_rot = tau + s - s * (1.0 - g.delta) * (1.0 - 1.0 / g.Z + g.omega1 / g.Z);
@@ -412,25 +475,26 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     const T ct = (T)(tau / (tau + s)), cs = (T)(s / (tau + s));
     // pass 3: phi_f (Eq. 45), micro flux and macro flux
     acc.zero();
-    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
-      T gb = UseLds ? sG[k] : rowG[k];
-      T rb = UseLds ? sR[k] : rowR[k];
-      const double* dv = d.dvs + DV * k;
-      T gs, rs;
-      e.eval((T)dv[0], (T)dv[1], (T)dv[2], gs, rs);
-      T gf = ct * gb + cs * gs;
-      T rf = ct * rb + cs * rs;
-      double un = udotn(dv, nx, ny, nz, d.snap);
+    k_loop(nv, [&](int64_t k) {
+      const T gb = UseLds ? sG[k] : rowG[k];
+      const T rb = UseLds ? sR[k] : rowR[k];
+      const Vel v = vel(d, k);
+      T ux, uy, uz, gs, rs;
+      vel_t<T>(d, k, ux, uy, uz);
+      e.eval(ux, uy, uz, gs, rs);
+      const T gf = ct * gb + cs * gs;
+      const T rf = ct * rb + cs * rs;
+      const double un = udotn(v, nx, ny, nz, d.snap);
       rowG[k] = (T)(A * un) * gf;
       rowR[k] = (T)(A * un) * rf;
-      double wg = dv[3] * un * (double)gf, wr = dv[3] * un * (double)rf;
+      double wg = v.w * un * (double)gf, wr = v.w * un * (double)rf;
       acc.add(0, wg);
-      acc.add(1, dv[0] * wg);
-      acc.add(2, dv[1] * wg);
-      acc.add(3, dv[2] * wg);
-      acc.add(4, dv[5] * wg + wr);
+      acc.add(1, v.ux * wg);
+      acc.add(2, v.uy * wg);
+      acc.add(3, v.uz * wg);
+      acc.add(4, v.h2 * wg + wr);
       acc.add(5, wr);
-    }
+    });
     acc.reduce(tot, red);
   } else {
     const double* bc = d.bc + BCW * bcs;
@@ -440,19 +504,19 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     double rho_g = bc[1];
     if (wall) {
       // rho_w from zero net mass flux through the wall
-      Acc<2, Comp> a2;
+      Acc<2, Comp, kBlock> a2;
       a2.zero();
-      for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
-        const double* dv = d.dvs + DV * k;
-        double un = udotn(dv, nx, ny, nz, d.snap);
+      const double anorm = pow(6.283185307179586476925 * RTb, -1.5);
+      k_loop(nv, [&](int64_t k) {
+        const Vel v = vel(d, k);
+        const double un = udotn(v, nx, ny, nz, d.snap);
         if (un > 0.0) {
-          a2.add(0, dv[3] * un * (double)rowG[k]);
+          a2.add(0, v.w * un * (double)rowG[k]);
         } else {
-          double cx = dv[0] - Ub[0], cy = dv[1] - Ub[1], cz = dv[2] - Ub[2];
-          double mw = pow(6.283185307179586476925 * RTb, -1.5) * exp(-(cx * cx + cy * cy + cz * cz) / (2.0 * RTb));
-          a2.add(1, dv[3] * (-un) * mw);
+          double cx = v.ux - Ub[0], cy = v.uy - Ub[1], cz = v.uz - Ub[2];
+          a2.add(1, v.w * (-un) * anorm * exp(-(cx * cx + cy * cy + cz * cz) / (2.0 * RTb)));
         }
-      }
+      });
       double t2[2];
       a2.reduce(t2, red);
       rho_g = t2[0] / t2[1];
@@ -460,34 +524,48 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     const T amax = (T)(rho_g * pow(6.283185307179586476925 * RTb, -1.5));
     const T bmax = (T)(1.0 / (2.0 * RTb));
     acc.zero();
-    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
-      const double* dv = d.dvs + DV * k;
-      double un = udotn(dv, nx, ny, nz, d.snap);
+    k_loop(nv, [&](int64_t k) {
+      const Vel v = vel(d, k);
+      const double un = udotn(v, nx, ny, nz, d.snap);
       T gf, rf;
       if (un > 0.0) {
         gf = rowG[k];
         rf = rowR[k];
       } else {
-        T cx = (T)(dv[0] - Ub[0]), cy = (T)(dv[1] - Ub[1]), cz = (T)(dv[2] - Ub[2]);
+        T cx = (T)(v.ux - Ub[0]), cy = (T)(v.uy - Ub[1]), cz = (T)(v.uz - Ub[2]);
         gf = amax * exp(-(cx * cx + cy * cy + cz * cz) * bmax);
         rf = (T)RTb * gf;
       }
       rowG[k] = (T)(A * un) * gf;
       rowR[k] = (T)(A * un) * rf;
-      double wg = dv[3] * un * (double)gf, wr = dv[3] * un * (double)rf;
+      double wg = v.w * un * (double)gf, wr = v.w * un * (double)rf;
       acc.add(0, wg);
-      acc.add(1, dv[0] * wg);
-      acc.add(2, dv[1] * wg);
-      acc.add(3, dv[2] * wg);
-      acc.add(4, dv[5] * wg + wr);
+      acc.add(1, v.ux * wg);
+      acc.add(2, v.uy * wg);
+      acc.add(3, v.uz * wg);
+      acc.add(4, v.h2 * wg + wr);
       acc.add(5, wr);
-    }
+    });
     acc.reduce(tot, red);
   }
   if (threadIdx.x < 6) w.face_mac[6 * f + threadIdx.x] = A * tot[threadIdx.x];
 }
 
-template <class T> static bool face_lds_ok(int64_t nv) { return nv * 2 * (int64_t)sizeof(T) <= 64 * 1024; }
+// phi_bar of one face is staged in LDS when it fits (gfx950: 160 KB per workgroup; above 64 KB the
+// kernel's dynamic-LDS limit is raised once), else re-read from global memory in passes 2 and 3.
+constexpr int64_t kLdsDefault = 64 * 1024, kLdsMax = 160 * 1024 - 4096;
+
+template <class T> static bool face_lds_ok(int64_t nv) {
+  constexpr bool Comp = sizeof(T) == 4;
+  int64_t bytes = nv * 2 * (int64_t)sizeof(T);
+  if (bytes <= kLdsDefault) return true;
+  if (bytes > kLdsMax) return false;
+  static int raised = 0;  // 0 unknown, 1 raised, -1 refused
+  if (raised == 0)
+    raised = hipFuncSetAttribute((const void*)k_face<T, Comp, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kLdsMax) == hipSuccess ? 1 : -1;
+  return raised == 1;
+}
 
 template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
   constexpr bool Comp = sizeof(T) == 4;
@@ -554,6 +632,8 @@ __global__ __launch_bounds__(kBlock) void k_macro_prep(Dev d, const double* W, W
     double r = fabs(Un) + sqrt(g.gamma * g.R * T) + 2.0 * visc(Ttr, g) / (rho * d.face_geo[FGW * (int64_t)f + 5]);
     w.rcf[4 * i + a] = r;
     acc += 0.5 * s[1] * r;
+    // G_n(W_j^n) along the outward normal, constant during the sweeps
+    if (nb >= 0) euler_flux(W + 6 * (int64_t)nb, s[2], s[3], s[4], w.G0 + 24 * i + 6 * a);
     const double* fm = w.face_mac + 6 * (int64_t)f;
     for (int m = 0; m < 6; ++m) F[m] += s[0] * fm[m] * geo[1];
   }
@@ -569,28 +649,45 @@ __global__ __launch_bounds__(kBlock) void k_macro_prep(Dev d, const double* W, W
   w.mres[6 * i + 5] += (pa[0] * g.R * pa[4] - W[6 * i + 5]) / (g.Z * tau);
 }
 
-__global__ __launch_bounds__(kBlock) void k_macro_sweep(Dev d, const double* W, Work w, int64_t c0, int64_t c1) {
-  int64_t i = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c1) return;
+// One point relaxation of Eq. 43 at cell i (matrix-free increment G(W_j + dW_j) - G(W_j)).
+__device__ inline void macro_relax(const Dev& d, const double* W, const Work& w, int64_t i) {
   const double* geo = d.cell_geo + CG * i;
   double acc[6];
   for (int m = 0; m < 6; ++m) acc[m] = w.mres[6 * i + m];
+  // issue every neighbour load before any arithmetic: the sweep is latency bound
+  int32_t nb[4];
+  double Wj[4][6], dWj[4][6];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) nb[a] = d.cell_nb[4 * i + a];
+#pragma unroll
   for (int a = 0; a < 4; ++a) {
-    int32_t nb = d.cell_nb[4 * i + a];
-    if (nb < 0) continue;
+    const int64_t j = nb[a] >= 0 ? nb[a] : i;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      Wj[a][m] = W[6 * j + m];
+      dWj[a][m] = w.dW[6 * j + m];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (nb[a] < 0) continue;
     const double* s = geo + CG_FACE + CG_SLOT * a;
-    const double* Wj = W + 6 * (int64_t)nb;
-    const double* dWj = w.dW + 6 * (int64_t)nb;
-    double Wp[6], G1[6], G0[6];
-    for (int m = 0; m < 6; ++m) Wp[m] = Wj[m] + dWj[m];
+    double Wp[6], G1[6];
+    for (int m = 0; m < 6; ++m) Wp[m] = Wj[a][m] + dWj[a][m];
     euler_flux(Wp, s[2], s[3], s[4], G1);
-    euler_flux(Wj, s[2], s[3], s[4], G0);
+    const double* G0 = w.G0 + 24 * i + 6 * a;
     double r = w.rcf[4 * i + a];
-    for (int m = 0; m < 6; ++m) acc[m] -= 0.5 * s[1] * ((G1[m] - G0[m]) - r * dWj[m]);
+    for (int m = 0; m < 6; ++m) acc[m] -= 0.5 * s[1] * ((G1[m] - G0[m]) - r * dWj[a][m]);
   }
   double D = w.mD[2 * i], D5 = w.mD[2 * i + 1];
   for (int m = 0; m < 5; ++m) w.dW[6 * i + m] = acc[m] / D;
   w.dW[6 * i + 5] = acc[5] / D5;
+}
+
+__global__ __launch_bounds__(kBlock) void k_macro_sweep(Dev d, const double* W, Work w, int64_t c0, int64_t c1) {
+  int64_t i = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c1) return;
+  macro_relax(d, W, w, i);
 }
 
 // W~ = W^n + dW~; predicted equilibrium coefficients with q~ = q^n
@@ -651,7 +748,7 @@ void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
 
 // ---------------------------------------------------------------------------
 // Step 4-5: micro flux per cell (Eq. 31) and right-hand side of Eq. 33, Res = (phi~* - phi)/tau~ - F.
-// flux_only = 1 writes F instead (explicit operator).
+// flux_only = 1 writes F instead (explicit operator).  Workgroup (cell, velocity chunk).
 // ---------------------------------------------------------------------------
 
 template <class T>
@@ -669,10 +766,10 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
   const T* fG = (const T*)b.faceG;
   const T* fR = (const T*)b.faceR;
   if (flux_only) {
-    for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
+    chunk_loop<T>(nv, [&](int64_t k) {
       outG[i * nv + k] = sg[0] * fG[fr[0] + k] + sg[1] * fG[fr[1] + k] + sg[2] * fG[fr[2] + k] + sg[3] * fG[fr[3] + k];
       outR[i * nv + k] = sg[0] * fR[fr[0] + k] + sg[1] * fR[fr[1] + k] + sg[2] * fR[fr[2] + k] + sg[3] * fR[fr[3] + k];
-    }
+    });
     return;
   }
   const double* ec = w.eq + ER * i;
@@ -681,26 +778,27 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
   const T itau = (T)(1.0 / ec[7]);
   const T* G = (const T*)b.G;
   const T* R = (const T*)b.R;
-  for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
-    const double* dv = d.dvs + DV * k;
-    T FG = sg[0] * fG[fr[0] + k] + sg[1] * fG[fr[1] + k] + sg[2] * fG[fr[2] + k] + sg[3] * fG[fr[3] + k];
-    T FR = sg[0] * fR[fr[0] + k] + sg[1] * fR[fr[1] + k] + sg[2] * fR[fr[2] + k] + sg[3] * fR[fr[3] + k];
-    T gs, rs;
-    e.eval((T)dv[0], (T)dv[1], (T)dv[2], gs, rs);
+  chunk_loop<T>(nv, [&](int64_t k) {
+    const T FG = sg[0] * fG[fr[0] + k] + sg[1] * fG[fr[1] + k] + sg[2] * fG[fr[2] + k] + sg[3] * fG[fr[3] + k];
+    const T FR = sg[0] * fR[fr[0] + k] + sg[1] * fR[fr[1] + k] + sg[2] * fR[fr[2] + k] + sg[3] * fR[fr[3] + k];
+    T ux, uy, uz, gs, rs;
+    vel_t<T>(d, k, ux, uy, uz);
+    e.eval(ux, uy, uz, gs, rs);
     outG[i * nv + k] = (gs - G[i * nv + k]) * itau - FG;
     outR[i * nv + k] = (rs - R[i * nv + k]) * itau - FR;
-  }
+  });
 }
 
 template <class T>
 void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR, int flux_only, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, b, w, (T*)outG, (T*)outR, flux_only);
+  hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)d.nc, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, b, w, (T*)outG,
+                     (T*)outR, flux_only);
 }
 
 // ---------------------------------------------------------------------------
 // Step 5: PR-SGS sweep of Eq. 33 over one colour, first-order upwind increments (Eq. 32).
 // D_ik = 1/dt_i + 1/tau~_i + sum_f (A/V) max(u.n, 0) in FP64.  In the first forward sweep the
-// increments of later colours are still zero and are not read.
+// increments of later colours are still zero and are not read.  Workgroup (cell, velocity chunk).
 // ---------------------------------------------------------------------------
 
 template <class T>
@@ -721,14 +819,14 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, i
   const T* rR = (const T*)b.resR;
   T* dG = (T*)b.dG;
   T* dR = (T*)b.dR;
-  for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
-    const double* dv = d.dvs + DV * k;
+  chunk_loop<T>(nv, [&](int64_t k) {
+    const Vel v = vel(d, k);
     double D = base;
     double aG = (double)rG[i * nv + k], aR = (double)rR[i * nv + k];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const double* s = geo + CG_FACE + CG_SLOT * a;
-      double un = udotn(dv, s[2], s[3], s[4], d.snap);
+      double un = udotn(v, s[2], s[3], s[4], d.snap);
       double av = s[1];
       D += av * fmax(un, 0.0);
       if (use[a] && un < 0.0) {
@@ -736,9 +834,10 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, i
         aR -= av * un * (double)dR[nrow[a] + k];
       }
     }
-    dG[i * nv + k] = (T)(aG / D);
-    dR[i * nv + k] = (T)(aR / D);
-  }
+    const double iD = 1.0 / D;
+    dG[i * nv + k] = (T)(aG * iD);
+    dR[i * nv + k] = (T)(aR * iD);
+  });
 }
 
 template <class T>
@@ -748,55 +847,55 @@ void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
     for (int64_t c = 0; c < n_colors; ++c) {
       int64_t n = color_off[c + 1] - color_off[c];
       if (n <= 0) continue;
-      hipLaunchKernelGGL(k_micro_sweep<T>, dim3((unsigned)n), dim3(kBlock), 0, st, d, b, w, color_off[c],
-                         color_off[c + 1], it == 0 ? 1 : 0);
+      hipLaunchKernelGGL(k_micro_sweep<T>, dim3((unsigned)n, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, b, w,
+                         color_off[c], color_off[c + 1], it == 0 ? 1 : 0);
     }
     for (int64_t c = n_colors - 1; c >= 0; --c) {
       int64_t n = color_off[c + 1] - color_off[c];
       if (n <= 0) continue;
-      hipLaunchKernelGGL(k_micro_sweep<T>, dim3((unsigned)n), dim3(kBlock), 0, st, d, b, w, color_off[c],
-                         color_off[c + 1], 0);
+      hipLaunchKernelGGL(k_micro_sweep<T>, dim3((unsigned)n, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, b, w,
+                         color_off[c], color_off[c + 1], 0);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Step 6: phi^{n+1} = phi^n + dphi and the integral error compensation (Eqs. 62-67), c = u - U~;
-// Step 7: per-cell |W^{n+1} - W^n|, reduced by k_reduce_res.
+// Step 7: per-cell |W^{n+1} - W^n|, reduced by k_reduce_res.  One 1024-thread workgroup per cell.
 // ---------------------------------------------------------------------------
 
 template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update(Dev d, Bufs b, Work w) {
-  __shared__ double red[kWaves * 2 * 12];
+  __shared__ double red[(kBlock / 64) * 2 * 12];
   const int64_t i = blockIdx.x;
   const int64_t nv = d.nv;
   const double* ec = w.eq + ER * i;
   Eq<T> e;
   e.load(ec);
   const double Ux = ec[1], Uy = ec[2], Uz = ec[3];
-  T* G = (T*)b.G;
-  T* R = (T*)b.R;
-  const T* dG = (const T*)b.dG;
-  const T* dR = (const T*)b.dR;
-  Acc<12, Comp> acc;
+  T* G = (T*)b.G + i * nv;
+  T* R = (T*)b.R + i * nv;
+  const T* dG = (const T*)b.dG + i * nv;
+  const T* dR = (const T*)b.dR + i * nv;
+  Acc<12, Comp, kBlock> acc;
   acc.zero();
-  for (int64_t k = threadIdx.x; k < nv; k += kBlock) {
-    const double* dv = d.dvs + DV * k;
-    T g = G[i * nv + k] + dG[i * nv + k];
-    T r = R[i * nv + k] + dR[i * nv + k];
-    G[i * nv + k] = g;
-    R[i * nv + k] = r;
-    T gs, rs;
-    e.eval((T)dv[0], (T)dv[1], (T)dv[2], gs, rs);
+  k_loop(nv, [&](int64_t k) {
+    const T g = G[k] + dG[k];
+    const T r = R[k] + dR[k];
+    G[k] = g;
+    R[k] = r;
+    const Vel v = vel(d, k);
+    T ux, uy, uz, gs, rs;
+    vel_t<T>(d, k, ux, uy, uz);
+    e.eval(ux, uy, uz, gs, rs);
     double gd = (double)g - (double)gs, rd = (double)r - (double)rs;
-    double wk = dv[3];
-    double cx = dv[0] - Ux, cy = dv[1] - Uy, cz = dv[2] - Uz;
+    double cx = v.ux - Ux, cy = v.uy - Uy, cz = v.uz - Uz;
     double c2 = cx * cx + cy * cy + cz * cz;
-    double wg = wk * gd, wr = wk * rd;
+    double wg = v.w * gd, wr = v.w * rd;
     acc.add(0, wg);
-    acc.add(1, dv[0] * wg);
-    acc.add(2, dv[1] * wg);
-    acc.add(3, dv[2] * wg);
-    acc.add(4, dv[5] * wg + wr);
+    acc.add(1, v.ux * wg);
+    acc.add(2, v.uy * wg);
+    acc.add(3, v.uz * wg);
+    acc.add(4, v.h2 * wg + wr);
     acc.add(5, wr);
     double hc = 0.5 * c2 * wg;
     acc.add(6, cx * hc);
@@ -805,23 +904,23 @@ template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update
     acc.add(9, cx * wr);
     acc.add(10, cy * wr);
     acc.add(11, cz * wr);
-  }
+  });
   double s[12];
   acc.reduce(s, red);
   if (threadIdx.x == 0) {
-    const GasC& g = d.gas;
+    const GasC& gg = d.gas;
     const double* Wt = w.Wt + 6 * i;
     double* W = b.W + 6 * i;
     double* q = b.q + 6 * i;
     double Wn[6], qn[6];
-    Wn[0] = s[0] + Wt[0];                                                   // Eq. 62
-    Wn[1] = s[1] + Wt[1];                                                   // Eq. 63
+    Wn[0] = s[0] + Wt[0];                                                      // Eq. 62
+    Wn[1] = s[1] + Wt[1];                                                      // Eq. 63
     Wn[2] = s[2] + Wt[2];
     Wn[3] = s[3] + Wt[3];
-    Wn[4] = s[4] + Wt[4];                                                   // Eq. 64
-    Wn[5] = s[5] + ec[0] * g.R * ((1.0 - 1.0 / g.Z) * ec[6] + ec[4] / g.Z);  // Eq. 65
-    const double ctr = (1.0 / 3.0) * (1.0 - (1.0 - g.omega0) / g.Z);
-    const double crot = (1.0 - g.delta) * (1.0 - (1.0 - g.omega1) / g.Z);
+    Wn[4] = s[4] + Wt[4];                                                      // Eq. 64
+    Wn[5] = s[5] + ec[0] * gg.R * ((1.0 - 1.0 / gg.Z) * ec[6] + ec[4] / gg.Z);  // Eq. 65
+    const double ctr = (1.0 / 3.0) * (1.0 - (1.0 - gg.omega0) / gg.Z);
+    const double crot = (1.0 - gg.delta) * (1.0 - (1.0 - gg.omega1) / gg.Z);
     for (int m = 0; m < 3; ++m) {
       qn[m] = s[6 + m] + q[m] * ctr;          // Eq. 66
       qn[3 + m] = s[9 + m] + q[3 + m] * crot;  // Eq. 67
@@ -834,13 +933,16 @@ template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_res(int64_t nc, const double* cellres, double* res, int32_t* flag,
-                                                       const double* W) {
-  __shared__ double red[kWaves * 2 * 6];
-  Acc<6, false> acc;
+constexpr int kResParts = 256;
+
+// Step 7, stage 1: partial sums of |W^{n+1} - W^n| over a fixed cell partition (deterministic), positivity check
+__global__ __launch_bounds__(kBlock) void k_reduce_res_part(int64_t nc, const double* cellres, double* part,
+                                                            int32_t* flag, const double* W) {
+  __shared__ double red[(kBlock / 64) * 2 * 6];
+  Acc<6, false, kBlock> acc;
   acc.zero();
   int bad = 0;
-  for (int64_t i = threadIdx.x; i < nc; i += kBlock) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nc; i += (int64_t)kResParts * kBlock) {
     for (int m = 0; m < 6; ++m) acc.add(m, cellres[6 * i + m]);
     const double* Wi = W + 6 * i;
     double ke = 0.5 * (Wi[1] * Wi[1] + Wi[2] * Wi[2] + Wi[3] * Wi[3]) / Wi[0];
@@ -849,6 +951,18 @@ __global__ __launch_bounds__(kBlock) void k_reduce_res(int64_t nc, const double*
   double tot[6];
   acc.reduce(tot, red);
   if (bad) atomicOr(&flag[0], 2);
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = tot[threadIdx.x];
+}
+
+// stage 2: one workgroup adds the kResParts partials in a fixed order
+__global__ __launch_bounds__(kBlock) void k_reduce_res(int64_t nc, const double* part, double* res, int32_t* flag) {
+  __shared__ double red[(kBlock / 64) * 2 * 6];
+  Acc<6, false, kBlock> acc;
+  acc.zero();
+  for (int p = threadIdx.x; p < kResParts; p += kBlock)
+    for (int m = 0; m < 6; ++m) acc.add(m, part[6 * p + m]);
+  double tot[6];
+  acc.reduce(tot, red);
   if (threadIdx.x < 6) {
     double v = tot[threadIdx.x] / (double)nc;
     res[threadIdx.x] = v;
@@ -859,9 +973,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce_res(int64_t nc, const double*
 template <class T> void launch_update(const Dev& d, const Bufs& b, const Work& w, int64_t it, hipStream_t st) {
   constexpr bool Comp = sizeof(T) == 4;
   hipLaunchKernelGGL((k_update<T, Comp>), dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, b, w);
-  hipLaunchKernelGGL(k_reduce_res, dim3(1), dim3(kBlock), 0, st, d.nc, (const double*)w.cellres, w.res + 6 * it,
-                     w.flag, (const double*)b.W);
+  hipLaunchKernelGGL(k_reduce_res_part, dim3(kResParts), dim3(kBlock), 0, st, d.nc, (const double*)w.cellres,
+                     w.respart, w.flag, (const double*)b.W);
+  hipLaunchKernelGGL(k_reduce_res, dim3(1), dim3(kBlock), 0, st, d.nc, (const double*)w.respart, w.res + 6 * it,
+                     w.flag);
 }
+
+int max_velocities() { return 16384; }
 
 // explicit instantiations
 template void launch_init_eq<double>(const Dev&, const Bufs&, const double*, int, double*, hipStream_t);

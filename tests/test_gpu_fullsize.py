@@ -1,0 +1,101 @@
+"""Checks at the full sizes of the synthetic workloads, in the launch configuration bench.py times.
+
+* sphere (50k tets x 4k velocities, FP64): one iteration from rest against the oracle at full size;
+* capsule mesh (303k tets) with a coarse DVS from the same generator: mixed path against the FP64 oracle;
+* full capsule configuration (303k tets x 10.6k velocities, 3.2e9 pairs, mixed): the result must not depend on
+  the order of the discrete velocities (equivariance under a permutation of the DVS), a property that holds at
+  any size and would expose offset errors above 2^31 elements.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_10846_amd.cases import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def nrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def colrel(a, b):
+    return max(nrel(a[:, m], b[:, m]) for m in range(a.shape[1]))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_sphere_full_size_one_iteration_fp64():
+    from paper_2303_10846_amd.binding import Solver
+    c = configs.sphere_case(seed=0)
+    say("case", c["name"], len(c["mesh"]["tets"]), "x", len(c["u"]))
+    s = Solver(c, precision="fp64")
+    s.init_equilibrium(c["W0"])
+    hs = s.iterate(1)
+    W, q = s.moments()
+    dW = s.debug_stage("dW")
+    Gs, _, _, _ = s.get_state()
+    del s
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    ho = o.iterate(1)
+    Go, _, Wo, qo = o.get_state()
+    say(f"W {colrel(W, Wo):.2e} q {colrel(q, qo):.2e} dW {colrel(dW, o.stage('dW')):.2e} G {nrel(Gs, Go):.2e}")
+    assert colrel(W, Wo) < 1e-11
+    assert colrel(dW, o.stage("dW")) < 1e-11
+    assert colrel(q, qo) < 1e-10
+    assert nrel(Gs, Go) < 1e-11
+    assert np.max(np.abs(hs - ho) / np.abs(ho)) < 1e-9
+
+
+def test_capsule_mesh_full_size_coarse_dvs_mixed_vs_oracle():
+    from paper_2303_10846_amd.binding import Solver
+    c = configs.capsule_case(seed=0, nv_target=700)
+    say("case", c["name"], len(c["mesh"]["tets"]), "x", len(c["u"]))
+    s = Solver(c, precision="mixed")
+    s.init_equilibrium(c["W0"])
+    s.iterate(2)
+    W, q = s.moments()
+    del s
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(2)
+    _, _, Wo, _ = o.get_state()
+    e = colrel(W, Wo)
+    say(f"mixed vs FP64 oracle after 2 iterations: W {e:.2e}")
+    assert e < 1e-5
+
+
+def test_capsule_full_config_mixed_dvs_permutation_equivariance():
+    import torch
+
+    from paper_2303_10846_amd.binding import Solver
+    c = configs.capsule_case(seed=0)
+    pairs = len(c["mesh"]["tets"]) * len(c["u"])
+    say("case", c["name"], len(c["mesh"]["tets"]), "x", len(c["u"]), f"pairs {pairs:.3g}")
+    assert pairs > 2 ** 31
+    res = []
+    perm = np.random.default_rng(5).permutation(len(c["u"]))
+    for cc in (c, dict(c, u=c["u"][perm], w=c["w"][perm])):
+        s = Solver(cc, precision="mixed")
+        s.init_equilibrium(cc["W0"])
+        h = s.iterate(2)
+        W, q = s.moments()
+        Q = s.wall_heat_flux(1)
+        say(f"  residual {h[-1].max():.3e} Q_w {Q:.6e}")
+        assert np.all(np.isfinite(h)) and np.all(np.isfinite(W))
+        res.append((W, q, Q))
+        del s
+        torch.cuda.empty_cache()
+    (W1, q1, Q1), (W2, q2, Q2) = res
+    say(f"W {colrel(W2, W1):.2e} q {colrel(q2, q1):.2e} Q {abs(Q2 - Q1) / abs(Q1):.2e}")
+    # the same velocities in another order: equal up to FP32 summation-order rounding
+    assert colrel(W2, W1) < 1e-5
+    assert abs(Q2 - Q1) < 1e-5 * abs(Q1)
