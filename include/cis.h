@@ -177,6 +177,61 @@ cis_status cis_debug_stage(cis_state* s, int32_t which, double* out_host);
 cis_status cis_profile_enable(cis_state* s, int32_t enable);
 cis_status cis_profile_read(cis_state* s, double* ms, int64_t* launches);
 
+/* Replace the boundary-condition values of a state (same count, order, tags and kinds as at creation).
+   Used to move the parameters p of the adjoint (wall temperature, free-stream density and speed). */
+cis_status cis_state_set_bc(cis_state* s, const cis_bc* bc, int32_t n_bc);
+
+/* ---- Steady residual, its vector-Jacobian product and the discrete adjoint (FP64 states only;
+   CIS_E_UNSUPPORTED in CIS_MIXED).  Not in the paper: this is the derivative of its steady scheme.
+
+   The state x = (G, R, W, q) is steady when one implicit iteration (Sec. 3.5, Steps 2-6) with the
+   predicted state equal to the current one leaves it unchanged, i.e. R(x; p) = 0 with
+     R_phi = (phi*(W, q) - phi)/tau(W) - F(phi; p)              (right-hand side of Eq. 33, Eq. 31)
+     R_W   = W - [sum_k w_k Phi_k (phi_k - phi*_k) + M(W)]      (Eqs. 62-65, M = analytic moments of phi*)
+     R_q   = q - [heat-flux sums of phi - phi* + a q]            (Eqs. 66-67)
+   The parameters are p = (T_w of the wall with tag wall_tag, rho_inf and |U_inf| of the far field with
+   tag ff_tag; |U_inf| moves along the fixed direction of U_inf).  The objective is the heat flux into the
+   wall of wall_tag, J = sum_f A_f sum_k w_k (u_k.n_f)(|u_k|^2/2 G_f,k + R_f,k) (Eq. 72 numerator).
+   The DVS and the mesh are held fixed.
+
+   These calls overwrite the state's face buffers (faceG, faceR) and internal macro arrays; G, R, W, q are
+   not modified.  All array arguments below are device pointers with the layouts of the state
+   ([n_cells][n_vel] FP64 for G-like arrays, [n_cells][6] FP64 for W-like arrays) unless marked host. */
+
+/* R(x; p) at the current state into rG, rR, rW, rq; J (host, or NULL) = heat flux into wall_tag. */
+cis_status cis_steady_residual(cis_state* s, int32_t wall_tag, double* rG, double* rR, double* rW, double* rq,
+                               double* J);
+
+/* g = v^T dR/dx + cJ dJ/dx into gG, gR, gW, gq and gp (host [3], or NULL) = v^T dR/dp + cJ dJ/dp.
+   vG, vR, vW, vq are all set or all NULL (v = 0, e.g. for dJ/dx alone with cJ = 1).  Outputs must not
+   overlap the inputs.  Faces whose tag is not wall_tag / ff_tag contribute nothing to gp; a tag of -1
+   means none (wall_tag must exist when cJ != 0).  The limiter (Eq. 46) is differentiated on the branch
+   that the current state takes. */
+cis_status cis_residual_vjp(cis_state* s, const double* vG, const double* vR, const double* vW, const double* vq,
+                            double cJ, int32_t wall_tag, int32_t ff_tag, double* gG, double* gR, double* gW,
+                            double* gq, double* gp);
+
+typedef struct {
+  int32_t iterations; /* Krylov iterations (VJP applications) */
+  int32_t converged;  /* 1 when |(dR/dx)^T lam - dJ/dx| <= rtol |dJ/dx| */
+  double rel_residual;
+} cis_adjoint_info;
+
+/* Device workspace of cis_adjoint_solve for GMRES(restart), in bytes: (restart + 3) vectors of
+   2 n_cells n_vel + 12 n_cells doubles, plus reduction scratch. */
+cis_status cis_adjoint_required_bytes(const cis_state* s, int32_t restart, int64_t* bytes);
+
+/* Discrete adjoint at the current (steady) state: solves (dR/dx)^T lam = (dJ/dx)^T by restarted GMRES
+   with a diagonal right preconditioner, then dJdp (host [3]) = dJ/dp - lam^T dR/dp for
+   p = (T_w, rho_inf, |U_inf|).  lam: device [2 n_cells n_vel + 12 n_cells] FP64, laid out as
+   [lam_G | lam_R | lam_W | lam_q].  work: caller-owned device memory of at least
+   cis_adjoint_required_bytes(restart).  J (host, or NULL) receives the objective.  Stops after max_iter
+   Krylov iterations or when the true residual is below rtol relative to |dJ/dx|; info (or NULL) reports
+   which.  dJdp is only the steady-state derivative when R(x; p) is near zero. */
+cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int32_t restart, int32_t max_iter,
+                             double rtol, void* work, int64_t work_bytes, double* lam, double* dJdp, double* J,
+                             cis_adjoint_info* info);
+
 #ifdef __cplusplus
 }
 #endif

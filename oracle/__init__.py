@@ -62,6 +62,8 @@ def _load():
     lib.orc_iterate.restype = C.c_int32
     lib.orc_iterate.argtypes = [P, C.c_int32, d]
     lib.orc_explicit.argtypes = [P]
+    lib.orc_steady_residual.argtypes = [P, C.c_int32, d, d, d, d, d]
+    lib.orc_steady_residual_jvp.argtypes = [P, C.c_int32, C.c_int32, d, d, d, d, d, C.c_double, d, d, d, d, d]
     lib.orc_set_num.argtypes = [P, d]
     lib.orc_stage.restype = C.c_int64
     lib.orc_stage.argtypes = [P, C.c_int32, d]
@@ -242,6 +244,28 @@ class Oracle:
                       Gs=(self.nc, self.nv), Rs=(self.nc, self.nv), Qface=(self.nf,), Wt=(self.nc, 6),
                       ffG=(self.nf, self.nv), ffR=(self.nf, self.nv), ffmac=(self.nf, 6), tau_t=(self.nc,))
         return out.reshape(shapes[name]) if n else out
+
+    def steady_residual(self, wall_tag: int = 1):
+        """Residual of the fixed point at the current state: (R_G, R_R, R_W, R_q, J)."""
+        rG = np.empty((self.nc, self.nv))
+        rR = np.empty((self.nc, self.nv))
+        rW = np.empty((self.nc, 6))
+        rq = np.empty((self.nc, 6))
+        J = C.c_double(0.0)
+        self.lib.orc_steady_residual(self.sol, int(wall_tag), _dp(rG), _dp(rR), _dp(rW), _dp(rq), C.byref(J))
+        return rG, rR, rW, rq, J.value
+
+    def steady_residual_jvp(self, uG, uR, uW, uq, up, wall_tag: int = 1, ff_tag: int = 2, h: float = 1e-30):
+        """Complex-step derivative of (R, J) along the state direction u and parameter direction up."""
+        jG = np.empty((self.nc, self.nv))
+        jR = np.empty((self.nc, self.nv))
+        jW = np.empty((self.nc, 6))
+        jq = np.empty((self.nc, 6))
+        jJ = C.c_double(0.0)
+        self.lib.orc_steady_residual_jvp(self.sol, int(wall_tag), int(ff_tag), _dp(_f64(uG)), _dp(_f64(uR)),
+                                         _dp(_f64(uW)), _dp(_f64(uq)), _dp(_f64(up)), float(h), _dp(jG), _dp(jR),
+                                         _dp(jW), _dp(jq), C.byref(jJ))
+        return jG, jR, jW, jq, jJ.value
 
     def wall_heat_flux(self, tag: int) -> float:
         """Eq. 72 numerator summed over the faces of ``tag`` for the current state."""

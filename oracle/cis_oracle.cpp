@@ -549,8 +549,9 @@ template <class S> struct Solver {
           S L = 1.0;
           // reading: eps^2 = (K h)^3 applied to phi scaled by its largest magnitude on the stencil,
           // i.e. eps^2 = (K h)^3 max(|phi_max|, |phi_min|)^2 (distribution values are far from O(1))
-          double scale = std::max(std::fabs(re(pmax)), std::fabs(re(pmin)));
-          double eps2 = kh3 * scale * scale;
+          // eps^2 is a function of phi: it carries the derivative of max(|phi_max|, |phi_min|)^2
+          S scale = std::fabs(re(pmax)) >= std::fabs(re(pmin)) ? pmax : pmin;
+          S eps2 = kh3 * scale * scale;
           if (num.limiter) {
             for (int a = 0; a < 4; ++a) {
               int64_t f = geo.cf[4 * i + a];
@@ -875,6 +876,57 @@ template <class S> struct Solver {
       if (geo.fn[f] < 0 && geo.ftag[f] == tag) acc += Qface[f];
     return acc;
   }
+
+  // Steady residual of the fixed point of Steps 2-6 (reading: the adjoint's residual, not in the paper).
+  // With W~ = W and q~ = q, a fixed point of the iteration satisfies
+  //   R_phi = (phi*(W, q) - phi)/tau(W) - F(phi)                    (right-hand side of Eq. 33)
+  //   R_W   = W - [sum_k w Phi (phi - phi*(W, q)) + M(W)]           (Eqs. 62-65 at W^{n+1} = W^n)
+  //   R_q   = q - [1/2 sum w c|c|^2 (G - G*) + a0 q_tr ; sum w c (R - R*) + a1 q_rot]   (Eqs. 66-67)
+  // where M(W) holds the analytic moments of phi*(W, q).
+  void steady_residual(std::vector<S>& rG, std::vector<S>& rR, std::vector<S>& rW, std::vector<S>& rq) {
+    explicit_pass();
+    size_t P = size_t(nc) * nv;
+    rG.assign(P, 0.0);
+    rR.assign(P, 0.0);
+    rW.assign(6 * nc, 0.0);
+    rq.assign(6 * nc, 0.0);
+    const double Z = gas.Z;
+    for (int64_t i = 0; i < nc; ++i) {
+      Prim<S> p = primitives(&W[6 * i], gas);
+      S tau = relax_time(p, gas);
+      S s[12];
+      for (auto& x : s) x = 0.0;
+      for (int64_t k = 0; k < nv; ++k) {
+        size_t x = size_t(i) * nv + k;
+        S Gs, Rs;
+        rykov_equilibrium(p, &q[6 * i], &q[6 * i + 3], &geo.u[3 * k], gas, Gs, Rs);
+        rG[x] = (Gs - G[x]) / tau - FG[x];
+        rR[x] = (Rs - R[x]) / tau - FR[x];
+        const double* u = &geo.u[3 * k];
+        double wk = geo.w[k];
+        double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        S gd = G[x] - Gs, rd = R[x] - Rs;
+        S c[3] = {u[0] - p.U[0], u[1] - p.U[1], u[2] - p.U[2]};
+        S c2 = sq(c[0]) + sq(c[1]) + sq(c[2]);
+        s[0] += wk * gd;
+        for (int d = 0; d < 3; ++d) s[1 + d] += wk * u[d] * gd;
+        s[4] += wk * (0.5 * u2 * gd + rd);
+        s[5] += wk * rd;
+        for (int d = 0; d < 3; ++d) {
+          s[6 + d] += wk * 0.5 * c[d] * c2 * gd;
+          s[9 + d] += wk * c[d] * rd;
+        }
+      }
+      const S* w = &W[6 * i];
+      for (int d = 0; d < 5; ++d) rW[6 * i + d] = w[d] - (s[d] + w[d]);
+      rW[6 * i + 5] = w[5] - (s[5] + p.rho * gas.R * ((1.0 - 1.0 / Z) * p.Trot + p.T / Z));
+      for (int d = 0; d < 3; ++d) {
+        rq[6 * i + d] = q[6 * i + d] - (s[6 + d] + q[6 * i + d] * (1.0 / 3.0) * (1.0 - (1.0 - gas.omega0) / Z));
+        rq[6 * i + 3 + d] =
+            q[6 * i + 3 + d] - (s[9 + d] + q[6 * i + 3 + d] * (1.0 - gas.delta) * (1.0 - (1.0 - gas.omega1) / Z));
+      }
+    }
+  }
 };
 
 struct Handle {
@@ -1057,6 +1109,68 @@ int32_t orc_cs_gradient(void* sp, int32_t param, int32_t wall_tag, int32_t ff_ta
   *dJ = Jc.imag() / hstep;
   if (J) *J = Jc.real();
   return 0;
+}
+
+// Steady residual at the current state (reading of the adjoint's residual, see steady_residual) and
+// J = wall heat flux of `wall_tag`.
+void orc_steady_residual(void* sp, int32_t wall_tag, double* rG, double* rR, double* rW, double* rq, double* J) {
+  auto* s = static_cast<Solver<double>*>(sp);
+  std::vector<double> a, b, c, d;
+  s->steady_residual(a, b, c, d);
+  copy_out(a, rG);
+  copy_out(b, rR);
+  copy_out(c, rW);
+  copy_out(d, rq);
+  if (J) *J = s->wall_heat_flux(wall_tag);
+}
+
+// Complex-step directional derivative of the steady residual and of J at the current state along
+// (uG, uR, uW, uq) in the state and up = (dT_w, drho_inf, d|U_inf|) in the parameters.
+void orc_steady_residual_jvp(void* sp, int32_t wall_tag, int32_t ff_tag, const double* uG, const double* uR,
+                             const double* uW, const double* uq, const double* up, double hstep, double* jG,
+                             double* jR, double* jW, double* jq, double* jJ) {
+  auto* s = static_cast<Solver<double>*>(sp);
+  std::vector<double> bcflat;
+  for (auto& b : s->bcs) {
+    bcflat.push_back(b.tag);
+    bcflat.push_back(b.kind);
+    bcflat.push_back(b.rho);
+    for (int d = 0; d < 3; ++d) bcflat.push_back(b.U[d]);
+    bcflat.push_back(b.T);
+  }
+  double gas[G_COUNT] = {s->gas.R, s->gas.gamma, s->gas.Z, s->gas.delta, s->gas.omega0,
+                         s->gas.omega1, s->gas.mu_ref, s->gas.omega_v, s->gas.T_ref};
+  double num[N_COUNT] = {s->num.cfl, s->num.inv_dt, s->num.cfl_imp, s->num.lim_K, double(s->num.limiter),
+                         double(s->num.n_macro), double(s->num.n_micro), s->num.snap, double(s->num.exact_jvp)};
+  Solver<cplx> c(s->geo, gas, num, bcflat.data(), int(s->bcs.size()));
+  const cplx ih(0.0, hstep);
+  for (auto& b : c.bcs) {
+    if (b.tag == wall_tag) b.T += ih * up[0];
+    if (b.tag == ff_tag) {
+      b.rho += ih * up[1];
+      double m = std::sqrt(sq(b.U[0].real()) + sq(b.U[1].real()) + sq(b.U[2].real()));
+      for (int d = 0; d < 3; ++d) b.U[d] *= (m + ih * up[2]) / m;
+    }
+  }
+  for (size_t x = 0; x < c.G.size(); ++x) {
+    c.G[x] = s->G[x] + ih * uG[x];
+    c.R[x] = s->R[x] + ih * uR[x];
+  }
+  for (size_t x = 0; x < c.W.size(); ++x) {
+    c.W[x] = s->W[x] + ih * uW[x];
+    c.q[x] = s->q[x] + ih * uq[x];
+  }
+  std::vector<cplx> a, b, cc, d;
+  c.steady_residual(a, b, cc, d);
+  for (size_t x = 0; x < a.size(); ++x) {
+    jG[x] = a[x].imag() / hstep;
+    jR[x] = b[x].imag() / hstep;
+  }
+  for (size_t x = 0; x < cc.size(); ++x) {
+    jW[x] = cc[x].imag() / hstep;
+    jq[x] = d[x].imag() / hstep;
+  }
+  if (jJ) *jJ = c.wall_heat_flux(wall_tag).imag() / hstep;
 }
 
 // Rykov equilibrium at nv velocities for prim = (rho, U0, U1, U2, T, T_tr, T_rot) and q = (q_tr, q_rot).

@@ -26,7 +26,8 @@ EXPORTS = [
     "cis_last_error", "cis_mesh_create", "cis_mesh_info", "cis_mesh_destroy", "cis_dvs_create", "cis_dvs_destroy",
     "cis_state_required_bytes", "cis_state_create", "cis_state_set_numerics", "cis_state_destroy",
     "cis_state_init_equilibrium", "cis_state_set", "cis_state_get", "cis_iterate", "cis_residual", "cis_moments",
-    "cis_wall_heat_flux", "cis_debug_stage", "cis_profile_enable", "cis_profile_read",
+    "cis_wall_heat_flux", "cis_debug_stage", "cis_profile_enable", "cis_profile_read", "cis_state_set_bc",
+    "cis_steady_residual", "cis_residual_vjp", "cis_adjoint_required_bytes", "cis_adjoint_solve",
 ]
 STAGE_NAMES = ["recon", "face", "macro", "residual", "micro", "update"]
 
@@ -59,6 +60,10 @@ class MeshInfo(C.Structure):
 
 class BufferSizes(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("phi_bytes", "face_bytes", "cell6_bytes", "total_bytes")]
+
+
+class AdjointInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double)]
 
 
 class DeviceBuffers(C.Structure):
@@ -131,6 +136,17 @@ def load(allow_build: bool = True):
     lib.cis_profile_enable.argtypes = [P, C.c_int32]
     lib.cis_profile_read.restype = st
     lib.cis_profile_read.argtypes = [P, d, i64]
+    lib.cis_state_set_bc.restype = st
+    lib.cis_state_set_bc.argtypes = [P, C.POINTER(Bc), C.c_int32]
+    lib.cis_steady_residual.restype = st
+    lib.cis_steady_residual.argtypes = [P, C.c_int32, P, P, P, P, d]
+    lib.cis_residual_vjp.restype = st
+    lib.cis_residual_vjp.argtypes = [P, P, P, P, P, C.c_double, C.c_int32, C.c_int32, P, P, P, P, d]
+    lib.cis_adjoint_required_bytes.restype = st
+    lib.cis_adjoint_required_bytes.argtypes = [P, C.c_int32, i64]
+    lib.cis_adjoint_solve.restype = st
+    lib.cis_adjoint_solve.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, P, C.c_int64, P, d,
+                                      d, C.POINTER(AdjointInfo)]
     _lib = lib
     return lib
 
@@ -142,6 +158,15 @@ def _check(status: int):
 
 def _dp(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _bc_array(bcs):
+    return (Bc * len(bcs))(*[Bc(int(b["tag"]), int(b["kind"]), float(b["rho"]), (C.c_double * 3)(*map(float, b["U"])),
+                               float(b["T"])) for b in bcs])
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
 def gas_struct(gas: dict) -> Gas:
@@ -234,8 +259,7 @@ class Solver:
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         bufs = DeviceBuffers(*(t.data_ptr() for t in (self.G, self.R, self.dG, self.dR, self.resG, self.resR,
                                                       self.faceG, self.faceR, self.W, self.q)))
-        bc_arr = (Bc * len(self.bcs))(*[Bc(b["tag"], b["kind"], b["rho"], (C.c_double * 3)(*b["U"]), b["T"])
-                                        for b in self.bcs])
+        bc_arr = _bc_array(self.bcs)
         self._gas_s = gas_struct(self.gas)
         self._num_s = numerics_struct(self.num)
         h = C.c_void_p()
@@ -317,3 +341,131 @@ class Solver:
         out = np.empty(self.nc if name == "tau_t" else (self.nc, 6))
         _check(self.lib.cis_debug_stage(self.h, which, _dp(out)))
         return out
+
+    # -- steady residual, VJP and adjoint (FP64) ------------------------------
+    def set_bc(self, bcs):
+        """Replace the boundary-condition values (same tags and kinds, same order)."""
+        bcs = [dict(b) for b in bcs]
+        _check(self.lib.cis_state_set_bc(self.h, _bc_array(bcs), len(bcs)))
+        self.bcs = bcs
+
+    def params(self, wall_tag: int, ff_tag: int) -> np.ndarray:
+        """p = (T_w of wall_tag, rho_inf and |U_inf| of ff_tag); 0 where the tag is absent."""
+        p = np.zeros(3)
+        for b in self.bcs:
+            if b["tag"] == wall_tag and b["kind"] == BC_WALL:
+                p[0] = b["T"]
+            if b["tag"] == ff_tag and b["kind"] == BC_FARFIELD:
+                p[1] = b["rho"]
+                p[2] = float(np.linalg.norm(b["U"]))
+        return p
+
+    def set_params(self, p, wall_tag: int, ff_tag: int):
+        """Move p = (T_w, rho_inf, |U_inf|); U_inf keeps its direction."""
+        bcs = [dict(b) for b in self.bcs]
+        for b in bcs:
+            if b["tag"] == wall_tag and b["kind"] == BC_WALL:
+                b["T"] = float(p[0])
+            if b["tag"] == ff_tag and b["kind"] == BC_FARFIELD:
+                b["rho"] = float(p[1])
+                m = float(np.linalg.norm(b["U"]))
+                b["U"] = [u * float(p[2]) / m for u in b["U"]] if m > 0 else list(b["U"])
+        self.set_bc(bcs)
+
+    def _fp64_only(self):
+        if self.precision != FP64:
+            raise CisError(-6, "the steady residual, VJP and adjoint need an FP64 state")
+
+    def steady_residual(self, wall_tag: int = -1):
+        """R(x; p) at the current state: (rG, rR, rW, rq) device tensors and J (heat flux into wall_tag)."""
+        t = self.torch
+        rG, rR = t.empty_like(self.G), t.empty_like(self.R)
+        rW, rq = t.empty_like(self.W), t.empty_like(self.q)
+        J = C.c_double(0.0)
+        _check(self.lib.cis_steady_residual(self.h, int(wall_tag), _ptr(rG), _ptr(rR), _ptr(rW), _ptr(rq),
+                                            C.byref(J)))
+        return rG, rR, rW, rq, J.value
+
+    def residual_vjp(self, vG=None, vR=None, vW=None, vq=None, cJ: float = 0.0, wall_tag: int = -1,
+                     ff_tag: int = -1):
+        """(gG, gR, gW, gq) device tensors and gp (numpy [3]) = v^T dR/d(x, p) + cJ dJ/d(x, p)."""
+        t = self.torch
+        gG, gR = t.empty_like(self.G), t.empty_like(self.R)
+        gW, gq = t.empty_like(self.W), t.empty_like(self.q)
+        vs = [vG, vR, vW, vq]
+        if any(v is not None for v in vs):
+            ref = [self.G, self.R, self.W, self.q]
+            vs = [(t.zeros_like(r) if v is None else v.to(device=r.device, dtype=t.float64).contiguous())
+                  for v, r in zip(vs, ref)]
+        gp = np.zeros(3)
+        _check(self.lib.cis_residual_vjp(self.h, *[_ptr(v) for v in vs], float(cJ), int(wall_tag), int(ff_tag),
+                                         _ptr(gG), _ptr(gR), _ptr(gW), _ptr(gq), _dp(gp)))
+        return gG, gR, gW, gq, gp
+
+    def adjoint(self, wall_tag: int, ff_tag: int = -1, restart: int = 60, max_iter: int = 3000,
+                rtol: float = 1e-11) -> dict:
+        """Discrete adjoint at the current state: dJ/dp for p = (T_w, rho_inf, |U_inf|), J and lambda."""
+        t = self.torch
+        nb = C.c_int64(0)
+        _check(self.lib.cis_adjoint_required_bytes(self.h, int(restart), C.byref(nb)))
+        work = t.empty(nb.value // 8, dtype=t.float64, device=self.device)
+        lam = t.empty(2 * self.nc * self.nv + 12 * self.nc, dtype=t.float64, device=self.device)
+        dJdp = np.zeros(3)
+        J = C.c_double(0.0)
+        info = AdjointInfo()
+        _check(self.lib.cis_adjoint_solve(self.h, int(wall_tag), int(ff_tag), int(restart), int(max_iter),
+                                          float(rtol), _ptr(work), nb.value, _ptr(lam), _dp(dJdp), C.byref(J),
+                                          C.byref(info)))
+        return dict(dJdp=dJdp, J=J.value, lam=lam, iterations=info.iterations, converged=bool(info.converged),
+                    rel_residual=info.rel_residual)
+
+
+def _steady_residual_function():
+    import torch
+
+    class SteadyResidual(torch.autograd.Function):
+        """R(x; p) and J as a differentiable function of (p, G, R, W, q); backward is cis_residual_vjp.
+
+        forward copies G, R, W, q into the solver's state buffers and moves its boundary conditions to p
+        (CPU float64 [3]: T_w of wall_tag, rho_inf and |U_inf| of ff_tag)."""
+
+        @staticmethod
+        def forward(ctx, solver, wall_tag, ff_tag, p, G, R, W, q):
+            solver._fp64_only()
+            solver.set_params(p.detach().cpu().numpy(), wall_tag, ff_tag)
+            with torch.no_grad():
+                solver.G.copy_(G)
+                solver.R.copy_(R)
+                solver.W.copy_(W)
+                solver.q.copy_(q)
+            rG, rR, rW, rq, J = solver.steady_residual(wall_tag)
+            ctx.solver, ctx.tags = solver, (wall_tag, ff_tag)
+            ctx.save_for_backward(G, R, W, q)
+            return rG, rR, rW, rq, torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, vG, vR, vW, vq, vJ):
+            solver = ctx.solver
+            G, R, W, q = ctx.saved_tensors
+            with torch.no_grad():
+                solver.G.copy_(G)
+                solver.R.copy_(R)
+                solver.W.copy_(W)
+                solver.q.copy_(q)
+            cJ = float(vJ) if vJ is not None else 0.0
+            vs = (vG, vR, vW, vq)
+            gG, gR, gW, gq, gp = solver.residual_vjp(*vs, cJ=cJ, wall_tag=ctx.tags[0], ff_tag=ctx.tags[1])
+            return None, None, None, torch.from_numpy(gp), gG, gR, gW, gq
+
+    return SteadyResidual
+
+
+_SR = None
+
+
+def steady_residual_fn(solver, wall_tag, ff_tag, p, G, R, W, q):
+    """Differentiable R(x; p), J (torch.autograd.Function around cis_steady_residual / cis_residual_vjp)."""
+    global _SR
+    if _SR is None:
+        _SR = _steady_residual_function()
+    return _SR.apply(solver, wall_tag, ff_tag, p, G, R, W, q)

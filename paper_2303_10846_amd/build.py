@@ -9,8 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libcis.so")
-SOURCES = [os.path.join(CSRC, "cis_api.hip"), os.path.join(CSRC, "cis_kernels.hip")]
-HEADERS = [os.path.join(CSRC, "cis_internal.h"), os.path.join(os.path.dirname(HERE), "include", "cis.h")]
+SOURCES = [os.path.join(CSRC, n) for n in ("cis_api.hip", "cis_kernels.hip", "cis_adjoint.hip")]
+HEADERS = [os.path.join(CSRC, n) for n in ("cis_internal.h", "cis_device.h", "cis_adjoint_math.h")] + [
+    os.path.join(os.path.dirname(HERE), "include", "cis.h")]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

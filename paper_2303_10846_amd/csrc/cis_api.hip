@@ -156,6 +156,75 @@ cis_status device_check(const char* what) {
   return CIS_OK;
 }
 
+// bc slot of `tag` (the last entry with that tag, as in the face table), -1 if none
+int slot_of(const cis_state* s, int32_t tag) {
+  int slot = -1;
+  for (size_t b = 0; b < s->bcs.size(); ++b)
+    if (s->bcs[b].tag == tag) slot = (int)b;
+  return slot;
+}
+
+struct AdjSlots {
+  int j = -1, w = -1, f = -1;
+};
+
+cis_status adj_slots(const cis_state* s, int32_t wall_tag, int32_t ff_tag, bool need_wall, AdjSlots* out) {
+  AdjSlots a;
+  a.j = slot_of(s, wall_tag);
+  if (need_wall && a.j < 0) return fail(CIS_E_INVALID_ARG, "no boundary condition with the objective's wall tag");
+  if (a.j >= 0 && s->bcs[a.j].kind == CIS_BC_WALL) a.w = a.j;
+  const int f = slot_of(s, ff_tag);
+  if (f >= 0 && s->bcs[f].kind == CIS_BC_FARFIELD) a.f = f;
+  *out = a;
+  return CIS_OK;
+}
+
+// g = v^T dR/dx + cJ dJ/dx for flat vectors x = [G | R | W | q] (v may be NULL: zero seed)
+void run_vjp(cis_state* s, const double* v, double cJ, const AdjSlots& sl, double* g) {
+  const int64_t P = s->mesh->nc * s->dvs->n, nc = s->mesh->nc;
+  AdjArgs a{v, v ? v + P : nullptr, v ? v + 2 * P : nullptr, v ? v + 2 * P + 6 * nc : nullptr, cJ, sl.j, sl.w, sl.f,
+            g, g + P, g + 2 * P, g + 2 * P + 6 * nc, s->work.gpf};
+  launch_vjp(s->dev, s->buf, a, s->stream);
+}
+
+cis_status sum_gp(cis_state* s, double* gp) {
+  std::vector<double> h(3 * (size_t)s->mesh->nf);
+  HIP_TRY(hipMemcpyAsync(h.data(), s->work.gpf, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  double a[3] = {0.0, 0.0, 0.0};
+  for (size_t f = 0; f < h.size() / 3; ++f)
+    for (int m = 0; m < 3; ++m) a[m] += h[3 * f + m];
+  for (int m = 0; m < 3; ++m) gp[m] = a[m];
+  return CIS_OK;
+}
+
+// J = sum over the boundary faces of bc slot `slot` of A sum_k w (u.n)(|u|^2/2 G_f + R_f), from the face pass
+cis_status objective_from_faces(cis_state* s, int slot, double* J) {
+  const cis_mesh* m = s->mesh;
+  std::vector<double> fm(6 * m->nf);
+  HIP_TRY(hipMemcpyAsync(fm.data(), s->work.face_mac, fm.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const int32_t tag = slot >= 0 ? s->bcs[slot].tag : INT32_MIN;
+  double acc = 0.0;
+  for (int64_t f = 0; f < m->nf; ++f)
+    if (m->face_cell[2 * f + 1] < 0 && m->face_tag[f] == tag) acc += fm[6 * f + 4];
+  *J = acc;
+  return CIS_OK;
+}
+
+cis_status dev_dots(cis_state* s, const double* V, int64_t n, int nvec, const double* w, double* part, double* hdev,
+                    double* host) {
+  launch_dots(V, n, nvec, w, part, hdev, s->stream);
+  HIP_TRY(hipMemcpyAsync(host, hdev, nvec * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CIS_OK;
+}
+
+int64_t adjoint_doubles(const cis_state* s, int32_t restart) {
+  const int64_t N = 2 * s->mesh->nc * s->dvs->n + 12 * s->mesh->nc;
+  return ((int64_t)restart + 3) * N + ((int64_t)restart + 2) * (dot_partials() + 1);
+}
+
 }  // namespace
 
 extern "C" {
@@ -516,6 +585,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   chk(own_alloc(s, &w.cellres, 6 * nc));
   chk(own_alloc(s, &w.flag, 4));
   chk(own_alloc(s, &w.respart, 6 * 256));
+  chk(own_alloc(s, &w.gpf, 3 * nf));
   s->res_cap = 64;
   chk(own_alloc(s, &w.res, 6 * s->res_cap));
   if (e != CIS_OK) {
@@ -758,6 +828,183 @@ cis_status cis_debug_stage(cis_state* s, int32_t which, double* out) {
     return CIS_OK;
   }
   return fail(CIS_E_INVALID_ARG, "unknown stage");
+}
+
+cis_status cis_state_set_bc(cis_state* s, const cis_bc* bc, int32_t n_bc) {
+  if (!s || (n_bc > 0 && !bc)) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  if ((size_t)n_bc != s->bcs.size()) return fail(CIS_E_INVALID_ARG, "n_bc differs from the state's");
+  for (int b = 0; b < n_bc; ++b) {
+    if (bc[b].tag != s->bcs[b].tag || bc[b].kind != s->bcs[b].kind)
+      return fail(CIS_E_INVALID_ARG, "tags and kinds must match the state's");
+    if (!(bc[b].T > 0.0) || (bc[b].kind == CIS_BC_FARFIELD && !(bc[b].rho > 0.0)) || !finite_all(bc[b].U, 3))
+      return fail(CIS_E_INVALID_ARG, "bc values out of range");
+  }
+  std::vector<double> bct(BCW * std::max(n_bc, 1), 0.0);
+  for (int b = 0; b < n_bc; ++b) {
+    double* p = &bct[BCW * b];
+    p[0] = bc[b].kind;
+    p[1] = bc[b].rho;
+    for (int d = 0; d < 3; ++d) p[2 + d] = bc[b].U[d];
+    p[5] = bc[b].T;
+  }
+  HIP_TRY(hipMemcpyAsync(s->d_bc, bct.data(), bct.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->bcs.assign(bc, bc + n_bc);
+  return CIS_OK;
+}
+
+cis_status cis_steady_residual(cis_state* s, int32_t wall_tag, double* rG, double* rR, double* rW, double* rq,
+                               double* J) {
+  if (!s || !rG || !rR || !rW || !rq) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the steady residual is FP64 only");
+  launch_recon<double>(s->dev, s->buf, s->stream);
+  launch_face<double>(s->dev, s->buf, s->work, s->stream);
+  launch_residual<double>(s->dev, s->buf, s->work, rG, rR, 1, s->stream);
+  launch_cell_steady(s->dev, s->buf, rG, rR, rW, rq, s->stream);
+  cis_status st = device_check("steady_residual");
+  if (st != CIS_OK) return st;
+  if (J) return objective_from_faces(s, slot_of(s, wall_tag), J);
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CIS_OK;
+}
+
+cis_status cis_residual_vjp(cis_state* s, const double* vG, const double* vR, const double* vW, const double* vq,
+                            double cJ, int32_t wall_tag, int32_t ff_tag, double* gG, double* gR, double* gW,
+                            double* gq, double* gp) {
+  if (!s || !gG || !gR || !gW || !gq) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  const bool anyv = vG || vR || vW || vq, allv = vG && vR && vW && vq;
+  if (anyv && !allv) return fail(CIS_E_INVALID_ARG, "vG, vR, vW, vq must be all set or all NULL");
+  if (!std::isfinite(cJ)) return fail(CIS_E_INVALID_ARG, "non-finite cJ");
+  if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the VJP is FP64 only");
+  AdjSlots sl;
+  cis_status st = adj_slots(s, wall_tag, ff_tag, cJ != 0.0, &sl);
+  if (st != CIS_OK) return st;
+  AdjArgs a{vG, vR, vW, vq, cJ, sl.j, sl.w, sl.f, gG, gR, gW, gq, s->work.gpf};
+  launch_vjp(s->dev, s->buf, a, s->stream);
+  st = device_check("residual_vjp");
+  if (st != CIS_OK) return st;
+  if (gp) return sum_gp(s, gp);
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return CIS_OK;
+}
+
+cis_status cis_adjoint_required_bytes(const cis_state* s, int32_t restart, int64_t* bytes) {
+  if (!s || !bytes) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  if (restart < 1 || restart > 1000) return fail(CIS_E_INVALID_ARG, "restart must be in 1..1000");
+  *bytes = adjoint_doubles(s, restart) * (int64_t)sizeof(double);
+  return CIS_OK;
+}
+
+cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int32_t restart, int32_t max_iter,
+                             double rtol, void* work, int64_t work_bytes, double* lam, double* dJdp, double* J,
+                             cis_adjoint_info* info) {
+  if (!s || !work || !lam || !dJdp) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the adjoint is FP64 only");
+  if (restart < 1 || restart > 1000 || max_iter < 0 || !(rtol > 0.0))
+    return fail(CIS_E_INVALID_ARG, "restart, max_iter or rtol out of range");
+  if (work_bytes < adjoint_doubles(s, restart) * (int64_t)sizeof(double))
+    return fail(CIS_E_INVALID_ARG, "work buffer smaller than cis_adjoint_required_bytes");
+  AdjSlots sl;
+  cis_status st = adj_slots(s, wall_tag, ff_tag, true, &sl);
+  if (st != CIS_OK) return st;
+  const int m = restart;
+  const int64_t N = 2 * s->mesh->nc * s->dvs->n + 12 * s->mesh->nc;
+  double* V = (double*)work;               // [m+1][N] Krylov basis
+  double* b = V + (int64_t)(m + 1) * N;    // right-hand side dJ/dx
+  double* z = b + N;                       // preconditioned vector / update
+  double* part = z + N;                    // [m+1][dot_partials()]
+  double* hdev = part + (int64_t)(m + 2) * dot_partials();
+  hipStream_t q = s->stream;
+  auto dots = [&](const double* Vb, int nvec, const double* w, double* host) {
+    return dev_dots(s, Vb, N, nvec, w, part, hdev, host);
+  };
+  // right-hand side and the explicit parameter dependence of J
+  double gpJ[3], gpL[3] = {0.0, 0.0, 0.0};
+  run_vjp(s, nullptr, 1.0, sl, b);
+  if ((st = device_check("adjoint rhs")) != CIS_OK) return st;
+  if ((st = sum_gp(s, gpJ)) != CIS_OK) return st;
+  double bn2;
+  if ((st = dots(b, 1, b, &bn2)) != CIS_OK) return st;
+  const double bnorm = std::sqrt(bn2);
+  launch_axpby(N, 0.0, b, 0.0, lam, q);
+  int32_t iters = 0;
+  double beta = bnorm;
+  launch_axpby(N, 1.0, b, 0.0, V, q);  // r = b - A*0
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), h(m + 1), h2(m + 1);
+  bool done = bnorm == 0.0;
+  while (!done && iters < max_iter) {
+    launch_axpby(N, 1.0 / beta, V, 0.0, V, q);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m && iters < max_iter; ++j) {
+      double* vj = V + (int64_t)j * N;
+      double* w = V + (int64_t)(j + 1) * N;
+      launch_precond(s->dev, s->buf, vj, z, q);
+      run_vjp(s, z, 0.0, sl, w);
+      // classical Gram-Schmidt, twice
+      if ((st = dots(V, j + 1, w, h.data())) != CIS_OK) return st;
+      launch_gemv_sub(V, N, j + 1, hdev, w, q);
+      if ((st = dots(V, j + 1, w, h2.data())) != CIS_OK) return st;
+      launch_gemv_sub(V, N, j + 1, hdev, w, q);
+      for (int i = 0; i <= j; ++i) h[i] += h2[i];
+      double hn2;
+      if ((st = dots(w, 1, w, &hn2)) != CIS_OK) return st;
+      const double hn = std::sqrt(hn2);
+      if (hn > 0.0) launch_axpby(N, 1.0 / hn, w, 0.0, w, q);
+      // Givens rotations on column j
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      const double r = std::hypot(h[j], hn);
+      cs[j] = r > 0.0 ? h[j] / r : 1.0;
+      sn[j] = r > 0.0 ? hn / r : 0.0;
+      h[j] = r;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      ++iters;
+      jend = j + 1;
+      if (std::fabs(gv[j + 1]) <= rtol * bnorm || hn == 0.0) break;
+    }
+    // y = H^-1 g, lam += M^-1 (V y)
+    for (int i = jend - 1; i >= 0; --i) {
+      double t = gv[i];
+      for (int k = i + 1; k < jend; ++k) t -= H[(size_t)i * m + k] * y[k];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    for (int i = 0; i < jend; ++i) y[i] = -y[i];
+    HIP_TRY(hipMemcpyAsync(hdev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, q));
+    launch_axpby(N, 0.0, z, 0.0, z, q);
+    launch_gemv_sub(V, N, jend, hdev, z, q);
+    launch_precond(s->dev, s->buf, z, V + (int64_t)m * N, q);
+    launch_axpby(N, 1.0, V + (int64_t)m * N, 1.0, lam, q);
+    // true residual r = b - A lam, and lam^T dR/dp
+    run_vjp(s, lam, 0.0, sl, V);
+    if ((st = device_check("adjoint iteration")) != CIS_OK) return st;
+    if ((st = sum_gp(s, gpL)) != CIS_OK) return st;
+    launch_axpby(N, 1.0, b, -1.0, V, q);
+    double r2;
+    if ((st = dots(V, 1, V, &r2)) != CIS_OK) return st;
+    beta = std::sqrt(r2);
+    done = beta <= rtol * bnorm || beta == 0.0;
+  }
+  for (int k = 0; k < 3; ++k) dJdp[k] = gpJ[k] - gpL[k];
+  if (info) {
+    info->iterations = iters;
+    info->converged = done ? 1 : 0;
+    info->rel_residual = bnorm > 0.0 ? beta / bnorm : 0.0;
+  }
+  if (J) {
+    launch_recon<double>(s->dev, s->buf, q);
+    launch_face<double>(s->dev, s->buf, s->work, q);
+    if ((st = device_check("objective")) != CIS_OK) return st;
+    return objective_from_faces(s, sl.j, J);
+  }
+  HIP_TRY(hipStreamSynchronize(q));
+  return CIS_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,222 @@
+// Device helpers shared by the kernels of one iteration and the adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "cis_internal.h"
+
+namespace cis {
+
+constexpr int kBlock = 256;  // threads per workgroup
+
+// ---------------------------------------------------------------------------
+// Reductions over a workgroup of NT threads (NT/64 wave64 wavefronts)
+// ---------------------------------------------------------------------------
+
+__device__ inline void two_sum_add(double& s, double& c, double x) {
+  double t = s + x;
+  c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+  s = t;
+}
+
+// N running FP64 sums per thread.  Per-thread partials add a handful of terms in plain FP64; when Comp is set
+// the merge of the partials across the workgroup is Neumaier-compensated.
+template <int N, bool Comp, int NT> struct Acc {
+  static constexpr int NW = NT / 64;
+  double s[N];
+  __device__ inline void zero() {
+#pragma unroll
+    for (int m = 0; m < N; ++m) s[m] = 0.0;
+  }
+  __device__ inline void add(int m, double x) { s[m] += x; }
+  // Block-wide totals, identical in every thread.  red: NW * 2N doubles of LDS.
+  __device__ inline void reduce(double* out, double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      double a = s[m], b = 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        double a2 = __shfl_xor(a, o, 64);
+        if (Comp) {
+          double b2 = __shfl_xor(b, o, 64);
+          two_sum_add(a, b, a2);
+          b += b2;
+        } else {
+          a += a2;
+        }
+      }
+      if (lane == 0) {
+        red[wid * 2 * N + m] = a;
+        red[wid * 2 * N + N + m] = b;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      double a = red[m], b = red[N + m];
+      for (int q = 1; q < NW; ++q) {
+        if (Comp) {
+          two_sum_add(a, b, red[q * 2 * N + m]);
+          b += red[q * 2 * N + N + m];
+        } else {
+          a += red[q * 2 * N + m];
+        }
+      }
+      out[m] = Comp ? a + b : a;
+    }
+    __syncthreads();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Gas model (Sec. 2)
+// ---------------------------------------------------------------------------
+
+struct Prim {
+  double rho, U[3], T, Ttr, Trot;
+};
+
+// Eqs. 1-5 with K_tr = 3, K_rot = 2
+__device__ inline Prim prim_of(const double* W, double R) {
+  Prim p;
+  p.rho = W[0];
+  double ir = 1.0 / W[0];
+  p.U[0] = W[1] * ir;
+  p.U[1] = W[2] * ir;
+  p.U[2] = W[3] * ir;
+  double ke = 0.5 * W[0] * (p.U[0] * p.U[0] + p.U[1] * p.U[1] + p.U[2] * p.U[2]);
+  double irR = ir / R;
+  p.T = 0.4 * (W[4] - ke) * irR;
+  p.Trot = W[5] * irR;
+  p.Ttr = (2.0 / 3.0) * (W[4] - ke - W[5]) * irR;
+  return p;
+}
+
+// Eq. 13
+__device__ inline double visc(double Ttr, const GasC& g) { return g.mu_ref * pow(Ttr / g.T_ref, g.omega_v); }
+
+// Coefficients of the reduced Rykov equilibria (Eqs. 17-23) for one macroscopic state.
+__device__ inline void eq_coeffs(const Prim& p, const double* q, const GasC& g, double* e) {
+  const double R = g.R, twopi = 6.283185307179586476925;
+  double RTtr = R * p.Ttr, RT = R * p.T, RTrot = R * p.Trot;
+  double ptr = p.rho * RTtr, pp = p.rho * RT, prot = p.rho * RTrot;
+  e[0] = p.rho;
+  e[1] = p.U[0];
+  e[2] = p.U[1];
+  e[3] = p.U[2];
+  e[4] = p.T;
+  e[5] = p.Ttr;
+  e[6] = p.Trot;
+  for (int d = 0; d < 6; ++d) e[8 + d] = q[d];
+  e[14] = p.rho * pow(twopi * RTtr, -1.5);
+  e[15] = 1.0 / (2.0 * RTtr);
+  e[16] = p.rho * pow(twopi * RT, -1.5);
+  e[17] = 1.0 / (2.0 * RT);
+  e[18] = 1.0 / (15.0 * RTtr * ptr);               // Eq. 19
+  e[19] = g.omega0 / (15.0 * RT * pp);             // Eq. 20
+  e[20] = (1.0 - g.delta) / (RTtr * prot);         // Eq. 21
+  e[21] = g.omega1 * (1.0 - g.delta) / (RT * pp);  // Eq. 22
+  e[22] = 1.0 / RTtr;
+  e[23] = 1.0 / RT;
+  e[24] = RTrot;
+  e[25] = RT;
+  e[26] = 1.0 - 1.0 / g.Z;  // Eqs. 17-18
+  e[27] = 1.0 / g.Z;
+}
+
+template <class C> struct Eq {
+  C Ux, Uy, Uz, qtx, qty, qtz, qrx, qry, qrz, a_tr, b_tr, a_T, b_T, ktr, kT, ktr_r, kT_r, iRTtr, iRT, RTrot, RT, z1,
+      z2;
+  __device__ inline void load(const double* e) {
+    Ux = (C)e[1];
+    Uy = (C)e[2];
+    Uz = (C)e[3];
+    qtx = (C)e[8];
+    qty = (C)e[9];
+    qtz = (C)e[10];
+    qrx = (C)e[11];
+    qry = (C)e[12];
+    qrz = (C)e[13];
+    a_tr = (C)e[14];
+    b_tr = (C)e[15];
+    a_T = (C)e[16];
+    b_T = (C)e[17];
+    ktr = (C)e[18];
+    kT = (C)e[19];
+    ktr_r = (C)e[20];
+    kT_r = (C)e[21];
+    iRTtr = (C)e[22];
+    iRT = (C)e[23];
+    RTrot = (C)e[24];
+    RT = (C)e[25];
+    z1 = (C)e[26];
+    z2 = (C)e[27];
+  }
+  // G*, R* at velocity u (Eqs. 17-23)
+  __device__ inline void eval(C ux, C uy, C uz, C& Gs, C& Rs) const {
+    C cx = ux - Ux, cy = uy - Uy, cz = uz - Uz;
+    C c2 = cx * cx + cy * cy + cz * cz;
+    C cqt = cx * qtx + cy * qty + cz * qtz;
+    C cqr = cx * qrx + cy * qry + cz * qrz;
+    C gtr = a_tr * exp(-c2 * b_tr);
+    C gT = a_T * exp(-c2 * b_T);
+    C Gtr = gtr * (C(1) + cqt * ktr * (c2 * iRTtr - C(5)));
+    C Grot = gT * (C(1) + cqt * kT * (c2 * iRT - C(5)));
+    C Rtr = RTrot * (Gtr + cqr * ktr_r * gtr);
+    C Rrot = RT * (Grot + cqr * kT_r * gT);
+    Gs = z1 * Gtr + z2 * Grot;
+    Rs = z1 * Rtr + z2 * Rrot;
+  }
+};
+
+// One discrete velocity (structure-of-arrays DVS, see DVS_* in cis_internal.h)
+struct Vel {
+  double ux, uy, uz, w, um, h2;
+};
+__device__ inline Vel vel(const Dev& d, int64_t k) {
+  const double* v = d.dvs;
+  const int64_t n = d.nv;
+  return Vel{v[k], v[n + k], v[2 * n + k], v[3 * n + k], v[4 * n + k], v[5 * n + k]};
+}
+template <class T> __device__ inline void vel_t(const Dev& d, int64_t k, T& ux, T& uy, T& uz);
+template <> __device__ inline void vel_t<double>(const Dev& d, int64_t k, double& ux, double& uy, double& uz) {
+  ux = d.dvs[k];
+  uy = d.dvs[d.nv + k];
+  uz = d.dvs[2 * d.nv + k];
+}
+template <> __device__ inline void vel_t<float>(const Dev& d, int64_t k, float& ux, float& uy, float& uz) {
+  ux = d.dvs_f[k];
+  uy = d.dvs_f[d.nv + k];
+  uz = d.dvs_f[2 * d.nv + k];
+}
+
+// u.n with the tie rule (|u.n| <= snap |u| -> 0)
+__device__ inline double udotn(const Vel& v, double nx, double ny, double nz, double snap) {
+  double un = v.ux * nx + v.uy * ny + v.uz * nz;
+  return fabs(un) <= snap * v.um ? 0.0 : un;
+}
+
+__device__ inline double inv_dt_cell(const Dev& d, double h) {
+  double v = d.inv_dt;
+  if (d.cfl_imp > 0.0) v += d.umax / (d.cfl_imp * h);
+  return v;
+}
+
+// Euler flux with the rotational-energy row (Eq. 40), p = rho R T
+__device__ inline void euler_flux(const double* W, double nx, double ny, double nz, double* out) {
+  double ir = 1.0 / W[0];
+  double Ux = W[1] * ir, Uy = W[2] * ir, Uz = W[3] * ir;
+  double p = 0.4 * (W[4] - 0.5 * W[0] * (Ux * Ux + Uy * Uy + Uz * Uz));
+  double Un = Ux * nx + Uy * ny + Uz * nz;
+  out[0] = W[0] * Un;
+  out[1] = W[1] * Un + p * nx;
+  out[2] = W[2] * Un + p * ny;
+  out[3] = W[3] * Un + p * nz;
+  out[4] = (W[4] + p) * Un;
+  out[5] = W[5] * Un;
+}
+
+}  // namespace cis

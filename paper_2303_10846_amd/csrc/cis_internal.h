@@ -74,6 +74,7 @@ struct Work {
   double* res;       // [hist][6]
   double* respart;   // [256][6] partial sums of the residual
   int32_t* flag;     // [4]
+  double* gpf;       // [nf][3] per-face parameter adjoints of the VJP
 };
 
 struct Bufs {
@@ -95,5 +96,21 @@ template <class T> void launch_micro(const Dev& d, const Bufs& b, const Work& w,
 template <class T> void launch_update(const Dev& d, const Bufs& b, const Work& w, int64_t it, hipStream_t st);
 void launch_macro_flux_cells(const Dev& d, const Work& w, hipStream_t st);
 int max_velocities();
+
+// Steady residual and its vector-Jacobian product (FP64 only).
+struct AdjArgs {
+  const double *vG, *vR, *vW, *vq;  // seed v (all NULL: zero)
+  double cJ;                        // seed of the objective
+  int32_t jslot, wslot, fslot;      // bc slots: objective faces, wall temperature, far-field state (-1: none)
+  double *gG, *gR, *gW, *gq;        // v^T dR/dx + cJ dJ/dx
+  double* gpf;                      // [nf][3] per-face parts of v^T dR/dp + cJ dJ/dp
+};
+void launch_cell_steady(const Dev& d, const Bufs& b, double* rG, double* rR, double* rW, double* rq, hipStream_t st);
+void launch_vjp(const Dev& d, const Bufs& b, const AdjArgs& a, hipStream_t st);
+void launch_precond(const Dev& d, const Bufs& b, const double* in, double* out, hipStream_t st);
+void launch_dots(const double* V, int64_t n, int nvec, const double* w, double* part, double* out, hipStream_t st);
+void launch_gemv_sub(const double* V, int64_t n, int nvec, const double* h, double* w, hipStream_t st);
+void launch_axpby(int64_t n, double a, const double* x, double c, double* y, hipStream_t st);
+int dot_partials();
 
 }  // namespace cis

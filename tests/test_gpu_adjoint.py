@@ -1,0 +1,195 @@
+"""Parity of the steady residual, its vector-Jacobian product and the discrete adjoint (HIP path, FP64).
+
+The VJP is checked against the oracle's complex-step JVP by the dot-product identity
+<v, (dR/dx) u + (dR/dp) up> + cJ (dJ/dx u + dJ/dp up) = <VJP_x(v, cJ), u> + VJP_p(v, cJ) . up,
+block by block, with the limiter on and off.  dJ/dp from the adjoint solve is checked against the oracle's
+complex step through the converged iteration and against central differences of the converged heat flux.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_10846_amd.cases import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def nrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def solver(case, precision="fp64"):
+    from paper_2303_10846_amd.binding import Solver
+    return Solver(case, precision=precision)
+
+
+def _open_box(limiter):
+    c = configs.open_box_case(n=3, nv_side=6)
+    c["num"] = dict(c["num"], limiter=limiter)
+    return c
+
+
+# (case factory, objective wall tag, far-field tag; 99 = none)
+CASES = {
+    "open_box_lim0": (lambda: _open_box(0), 1, 2),
+    "open_box_lim1": (lambda: _open_box(1), 1, 2),
+    "cavity_lid": (lambda: configs.cavity_case(n=2, nv_side=5), 2, 99),       # moving hot-side wall, nv = 125
+    "small_sphere": (lambda: configs.small_sphere_case(), 1, 2),
+}
+
+
+def _pair(case, warm):
+    o = oracle.Oracle(case)
+    o.init_equilibrium(case["W0"])
+    o.iterate(warm)
+    G, R, W, q = o.get_state()
+    s = solver(case)
+    s.set_state(G, R, W, q)
+    return o, s, (G, R, W, q)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_steady_residual_matches_oracle(name):
+    say("case", name)
+    make, wt, ft = CASES[name]
+    o, s, _ = _pair(make(), 4)
+    ro = o.steady_residual(wt)
+    rG, rR, rW, rq, J = s.steady_residual(wt)
+    assert nrel(rG.cpu().numpy(), ro[0]) < 1e-10
+    assert nrel(rR.cpu().numpy(), ro[1]) < 1e-10
+    assert nrel(rW.cpu().numpy(), ro[2]) < 1e-10
+    assert nrel(rq.cpu().numpy(), ro[3]) < 1e-10
+    assert abs(J - ro[4]) <= 1e-11 * abs(ro[4])
+
+
+BLOCKS = ["G", "R", "W", "q", "p", "all"]
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+@pytest.mark.parametrize("name", list(CASES))
+def test_vjp_dot_product_with_oracle_jvp(name, block):
+    say("case", name, "block", block)
+    import torch
+    make, wt, ft = CASES[name]
+    o, s, (G, R, W, q) = _pair(make(), 4)
+    rng = np.random.default_rng(11)
+    # directions in the state scaled elementwise (finite values everywhere), seeds of unit size
+    u = [rng.standard_normal(G.shape) * np.abs(G), rng.standard_normal(R.shape) * np.abs(R),
+         rng.standard_normal(W.shape) * np.abs(W).max(axis=0), rng.standard_normal(q.shape) * 1e-2]
+    up = rng.standard_normal(3)
+    keep = {"G": [0], "R": [1], "W": [2], "q": [3], "p": [], "all": [0, 1, 2, 3]}[block]
+    u = [x if i in keep else np.zeros_like(x) for i, x in enumerate(u)]
+    if block not in ("p", "all"):
+        up = np.zeros(3)
+    if ft == 99:
+        up[1:] = 0.0
+    v = [rng.standard_normal(G.shape), rng.standard_normal(R.shape), rng.standard_normal(W.shape),
+         rng.standard_normal(q.shape)]
+    cJ = 0.7
+    jac = o.steady_residual_jvp(*u, up, wall_tag=wt, ff_tag=ft)
+    terms = [np.sum(v[m] * jac[m]) for m in range(4)] + [cJ * jac[4]]
+    lhs = sum(terms)
+    vt = [torch.from_numpy(x).to(s.device) for x in v]
+    gG, gR, gW, gq, gp = s.residual_vjp(*vt, cJ=cJ, wall_tag=wt, ff_tag=ft)
+    g = [gG.cpu().numpy(), gR.cpu().numpy(), gW.cpu().numpy(), gq.cpu().numpy()]
+    rterms = [np.sum(g[m] * u[m]) for m in range(4)] + [float(gp @ up)]
+    rhs = sum(rterms)
+    scale = sum(abs(t) for t in terms) + sum(abs(t) for t in rterms)
+    say("lhs", lhs, "rhs", rhs, "scale", scale)
+    assert scale > 0.0
+    assert abs(lhs - rhs) <= 1e-10 * scale
+
+
+def test_objective_vjp_matches_oracle_jvp_per_parameter():
+    """cJ = 1, v = 0: dJ/dp explicit part and dJ/dx against the oracle, parameter by parameter."""
+    make, wt, ft = CASES["small_sphere"]
+    o, s, (G, R, W, q) = _pair(make(), 4)
+    gG, gR, gW, gq, gp = s.residual_vjp(cJ=1.0, wall_tag=wt, ff_tag=ft)
+    z = [np.zeros_like(G), np.zeros_like(R), np.zeros_like(W), np.zeros_like(q)]
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        jJ = o.steady_residual_jvp(*z, e, wall_tag=wt, ff_tag=ft)[4]
+        say("param", k, "gpu", gp[k], "oracle", jJ)
+        assert abs(gp[k] - jJ) <= 1e-11 * max(abs(jJ), 1e-300)
+    assert float(np.abs(gW.cpu().numpy()).max()) == 0.0     # J depends on phi only
+    assert float(np.abs(gq.cpu().numpy()).max()) == 0.0
+
+
+def test_adjoint_gradient_matches_complex_step_and_finite_differences():
+    c = _open_box(0)
+    s = solver(c)
+    s.init_equilibrium(c["W0"])
+    hist = s.iterate(140)
+    say("primal residual", hist[-1].max())
+    assert hist[-1].max() < 1e-12
+    base = s.get_state()
+    a = s.adjoint(1, 2, restart=60, max_iter=3000, rtol=1e-12)
+    say("adjoint iterations", a["iterations"], "rel residual", a["rel_residual"], "dJdp", a["dJdp"])
+    assert a["converged"]
+    # oracle: complex step through the iteration from the converged state
+    o = oracle.Oracle(c)
+    o.set_state(*base)
+    for k in range(3):
+        dJ, J0 = o.cs_gradient(k, 1, 2, 140)
+        say("param", k, "adjoint", a["dJdp"][k], "oracle cs", dJ)
+        assert abs(a["dJdp"][k] - dJ) <= 1e-6 * abs(dJ)
+        assert abs(a["J"] - J0) <= 1e-10 * abs(J0)
+    # central differences of the converged heat flux on the GPU (cis_state_set_bc)
+    p0 = s.params(1, 2)
+    for k in range(3):
+        h = 1e-5
+        Js = []
+        for sgn in (1, -1):
+            p = p0.copy()
+            p[k] += sgn * h
+            s.set_params(p, 1, 2)
+            s.set_state(*base)
+            hk = s.iterate(140)
+            assert hk[-1].max() < 1e-12
+            Js.append(s.steady_residual(1)[4])
+        fd = (Js[0] - Js[1]) / (2 * h)
+        say("param", k, "adjoint", a["dJdp"][k], "fd", fd)
+        assert abs(a["dJdp"][k] - fd) <= 1e-6 * abs(fd)
+    s.set_params(p0, 1, 2)
+
+
+def test_steady_residual_autograd_function():
+    import torch
+    from paper_2303_10846_amd.binding import steady_residual_fn
+    make, wt, ft = CASES["open_box_lim1"]
+    o, s, (G, R, W, q) = _pair(make(), 4)
+    dev = s.device
+    xs = [torch.from_numpy(x).to(dev).requires_grad_(True) for x in (G, R, W, q)]
+    p = torch.tensor(s.params(wt, ft), dtype=torch.float64, requires_grad=True)
+    rG, rR, rW, rq, J = steady_residual_fn(s, wt, ft, p, *xs)
+    ro = o.steady_residual(wt)
+    assert nrel(rG.detach().cpu().numpy(), ro[0]) < 1e-10
+    assert abs(float(J) - ro[4]) <= 1e-11 * abs(ro[4])
+    rng = np.random.default_rng(5)
+    v = [torch.from_numpy(rng.standard_normal(t.shape)).to(dev) for t in (rG, rR, rW, rq)]
+    loss = sum((a * b).sum() for a, b in zip(v, (rG, rR, rW, rq))) + 0.3 * J.to(dev)
+    loss.backward()
+    gG, gR, gW, gq, gp = s.residual_vjp(*v, cJ=0.3, wall_tag=wt, ff_tag=ft)
+    for t, g in zip(xs, (gG, gR, gW, gq)):
+        assert nrel(t.grad.cpu().numpy(), g.cpu().numpy()) < 1e-12
+    assert np.allclose(p.grad.numpy(), gp, rtol=1e-12, atol=0.0)
+
+
+def test_mixed_precision_state_rejects_the_adjoint():
+    from paper_2303_10846_amd.binding import CisError
+    c = configs.cavity_case(n=2, nv_side=4)
+    s = solver(c, precision="mixed")
+    s.init_equilibrium(c["W0"])
+    with pytest.raises(CisError) as e:
+        s.residual_vjp(cJ=1.0, wall_tag=2, ff_tag=99)
+    assert e.value.status == -6

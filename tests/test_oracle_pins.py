@@ -455,3 +455,95 @@ def test_p12_sphere_free_stream_speed_and_p13_dvs_count():
     T = 3.0
     r = 3 * math.sqrt(0.5 * T)
     assert abs((4 / 3) * math.pi * r ** 3 / dvs.refine_weight(T) - dvs.refine_count(T)) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# P11: the steady residual and the derivatives used by the adjoint
+# ---------------------------------------------------------------------------
+
+def _open_box(limiter):
+    c = configs.open_box_case(n=3, nv_side=6)
+    c["num"] = dict(c["num"], limiter=limiter)
+    return c
+
+
+def _state_vec(o):
+    G, R, W, q = o.get_state()
+    return G, R, W, q
+
+
+def test_p11_steady_residual_vanishes_at_the_fixed_point():
+    """At the converged state of Steps 2-6 the steady residual is zero, and it is not zero before."""
+    c = _open_box(0)
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(3)
+    r0 = o.steady_residual(1)
+    o.iterate(130)
+    r1 = o.steady_residual(1)
+    G, R, W, q = o.get_state()
+    scale = [np.abs(G).max() / o.geometry()["h"].min(), np.abs(R).max() / o.geometry()["h"].min(),
+             np.abs(W).max(), np.abs(W).max()]
+    for a, b, s in zip(r0[:4], r1[:4], scale):
+        assert np.abs(a).max() > 1e-4 * s
+        assert np.abs(b).max() < 1e-10 * s
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_p11_complex_step_jvp_matches_central_differences(limiter):
+    """The complex-step derivative of R and J agrees with central differences (limiter on: eps^2 moves)."""
+    c = _open_box(limiter)
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(6)
+    G, R, W, q = o.get_state()
+    rng = np.random.default_rng(3)
+    # directions scaled elementwise: the limiter is strongly nonlinear where phi is tiny (DVS tails)
+    u = [rng.standard_normal(G.shape) * np.abs(G), rng.standard_normal(R.shape) * np.abs(R),
+         rng.standard_normal(W.shape) * 1e-2, rng.standard_normal(q.shape) * 1e-3]
+    up = np.array([0.3, 0.2, 0.1])
+    jac = o.steady_residual_jvp(*u, up, wall_tag=1, ff_tag=2)
+    eps = 1e-7
+    out = []
+    for sgn in (1, -1):
+        ob = oracle.Oracle(c, bcs=[dict(b, T=b["T"] + sgn * eps * up[0]) if b["tag"] == 1 else
+                                   dict(b, rho=b["rho"] + sgn * eps * up[1],
+                                        U=list(np.asarray(b["U"]) * (1 + sgn * eps * up[2] / np.linalg.norm(b["U"]))))
+                                   for b in c["bcs"]])
+        ob.set_state(G + sgn * eps * u[0], R + sgn * eps * u[1], W + sgn * eps * u[2], q + sgn * eps * u[3])
+        out.append(ob.steady_residual(1))
+    for m in range(5):
+        fd = (np.asarray(out[0][m]) - np.asarray(out[1][m])) / (2 * eps)
+        an = np.asarray(jac[m])
+        assert rel(an, fd) < 1e-7, (m, rel(an, fd))
+
+
+def test_p11_complex_step_gradient_matches_fd_of_converged_heat_flux():
+    """dJ/dp of the steady state: complex step through the iteration vs central differences of converged J."""
+    c = _open_box(0)
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(130)
+    base = _state_vec(o)
+    n_iter = 130
+    for param, h in ((0, 1e-5), (1, 1e-5), (2, 1e-5)):
+        dJ, J0 = o.cs_gradient(param, 1, 2, n_iter)
+        Js = []
+        for sgn in (1, -1):
+            bcs = []
+            for b in c["bcs"]:
+                b = dict(b)
+                if param == 0 and b["tag"] == 1:
+                    b["T"] += sgn * h
+                if param == 1 and b["tag"] == 2:
+                    b["rho"] += sgn * h
+                if param == 2 and b["tag"] == 2:
+                    m = np.linalg.norm(b["U"])
+                    b["U"] = list(np.asarray(b["U"]) * (m + sgn * h) / m)
+                bcs.append(b)
+            ob = oracle.Oracle(c, bcs=bcs)
+            ob.set_state(*base)
+            ob.iterate(n_iter)
+            Js.append(ob.steady_residual(1)[4])
+        fd = (Js[0] - Js[1]) / (2 * h)
+        assert abs(dJ - fd) < 1e-6 * max(abs(fd), abs(J0) * 1e-3), (param, dJ, fd)
