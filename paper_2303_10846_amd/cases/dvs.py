@@ -94,6 +94,31 @@ def octree_dvs(center, radius: float, h_outer: float, refine=(), root_scale: flo
     return u[order], w[order]
 
 
+def direction_order(u, bits: int = 5):
+    """Permutation sorting velocities by direction, then by speed.
+
+    Directions u/|u| are mapped to the plane by the octahedral projection and ordered along a Morton
+    curve of 2^bits x 2^bits cells.  Consecutive velocities then point roughly the same way, so for any
+    face normal the sign of u.n changes rarely along the set: whole wavefronts of the upwind kernels take
+    the same branch and skip the same neighbour loads.  The order changes no result beyond rounding.
+    """
+    u = np.asarray(u, dtype=float)
+    speed = np.linalg.norm(u, axis=1)
+    d = u / np.maximum(speed, 1e-300)[:, None]
+    l1 = np.maximum(np.abs(d).sum(axis=1), 1e-300)
+    px, py = d[:, 0] / l1, d[:, 1] / l1
+    lower = d[:, 2] < 0
+    qx = np.where(lower, (1.0 - np.abs(py)) * np.sign(px), px)
+    qy = np.where(lower, (1.0 - np.abs(px)) * np.sign(py), py)
+    n = 1 << bits
+    ix = np.clip(((qx + 1.0) * 0.5 * n).astype(np.int64), 0, n - 1)
+    iy = np.clip(((qy + 1.0) * 0.5 * n).astype(np.int64), 0, n - 1)
+    key = np.zeros(len(u), dtype=np.int64)
+    for b in range(bits):
+        key |= ((ix >> b) & 1) << (2 * b) | ((iy >> b) & 1) << (2 * b + 1)
+    return np.lexsort((speed, key))
+
+
 def paper_unstructured_dvs(U_inf, T_inf: float, T_w: float, mach: float, outer_radius_factor: float = 5.0,
                            h_outer: float = None, target: int = None, R: float = 0.5, gamma: float = 1.4,
                            refine_scale: float = 1.0):
@@ -112,13 +137,16 @@ def paper_unstructured_dvs(U_inf, T_inf: float, T_w: float, mach: float, outer_r
               (np.zeros(3), 3.0 * math.sqrt(R * T_w), refine_scale * refine_weight(T_w, R) ** (1.0 / 3.0))]
     center = 0.4 * U_inf
     if h_outer is not None:
-        return octree_dvs(center, radius, h_outer, refine)
-    # scan the root cube size and the outer level; keep the count closest to target
-    best = None
-    for scale in np.linspace(1.0, 1.95, 20):
-        for lvl in range(2, 7):
-            h = 2.0 * radius * scale / 2 ** lvl
-            u, w = octree_dvs(center, radius, h, refine, root_scale=scale)
-            if best is None or abs(len(u) - target) < abs(len(best[0]) - target):
-                best = (u, w)
-    return best
+        u, w = octree_dvs(center, radius, h_outer, refine)
+    else:
+        # scan the root cube size and the outer level; keep the count closest to target
+        best = None
+        for scale in np.linspace(1.0, 1.95, 20):
+            for lvl in range(2, 7):
+                h = 2.0 * radius * scale / 2 ** lvl
+                u, w = octree_dvs(center, radius, h, refine, root_scale=scale)
+                if best is None or abs(len(u) - target) < abs(len(best[0]) - target):
+                    best = (u, w)
+        u, w = best
+    o = direction_order(u)
+    return u[o], w[o]

@@ -731,9 +731,9 @@ cis_status cis_iterate(cis_state* s, int32_t n_iter, double* res_hist) {
   });
   if (s->profile) {
     (void)hipStreamSynchronize(s->stream);
-    int64_t nonempty = 0;
-    for (int64_t c = 0; c < m->n_colors; ++c) nonempty += (m->color_off[c + 1] > m->color_off[c]);
-    const int64_t per_it[6] = {1, 1, 3 + 2 * (int64_t)s->num.n_macro * nonempty, 1, 2 * (int64_t)s->num.n_micro * nonempty, 3};
+    const int64_t nmac = (int64_t)sweep_sequence(m->color_off.data(), m->n_colors, s->num.n_macro).size();
+    const int64_t nmic = (int64_t)sweep_sequence(m->color_off.data(), m->n_colors, s->num.n_micro).size();
+    const int64_t per_it[6] = {1, 1, 3 + nmac, 1, nmic, 3};
     for (int32_t it = 0; it < n_iter; ++it)
       for (int k = 0; k < 6; ++k) {
         float ms = 0.0f;

@@ -10,6 +10,16 @@
 namespace cis {
 
 constexpr int kBlock = 256;  // threads per workgroup
+constexpr int kXcd = 8;      // accelerator complex dies, each with its own L2
+
+// Logical index of workgroup w among n.  The dispatcher deals workgroups to the XCDs round-robin
+// (w -> XCD w % 8); this bijection on [0, n) gives every XCD one contiguous range of logical blocks, so
+// that workgroups of neighbouring cells share that XCD's L2.
+__device__ inline int64_t xcd_block(int64_t w, int64_t n) {
+  const int64_t q = n / kXcd, r = n % kXcd;
+  const int64_t x = w % kXcd, j = w / kXcd;
+  return x * q + (x < r ? x : r) + j;
+}
 
 // ---------------------------------------------------------------------------
 // Reductions over a workgroup of NT threads (NT/64 wave64 wavefronts)

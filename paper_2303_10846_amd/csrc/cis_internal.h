@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace cis {
 
 // Per-cell geometry record, FP64, CG doubles per cell:
@@ -96,6 +98,7 @@ template <class T> void launch_micro(const Dev& d, const Bufs& b, const Work& w,
 template <class T> void launch_update(const Dev& d, const Bufs& b, const Work& w, int64_t it, hipStream_t st);
 void launch_macro_flux_cells(const Dev& d, const Work& w, hipStream_t st);
 int max_velocities();
+std::vector<int64_t> sweep_sequence(const int64_t* color_off, int64_t n_colors, int n_pairs);
 
 // Steady residual and its vector-Jacobian product (FP64 only).
 struct AdjArgs {

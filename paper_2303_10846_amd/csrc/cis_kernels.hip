@@ -17,31 +17,50 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "cis_device.h"
 #include "cis_internal.h"
 
 namespace cis {
 
-// Velocities per thread in the (cell, chunk) kernels, chunk = kBlock * Vpt<T>: 4 in FP32, 1 in FP64 (measured
-// on the sphere workload; larger FP32 chunks amortise the per-cell set-up of each workgroup).
+// Velocities per thread in the (cell, chunk) kernels, chunk = kBlock * Vpt<T>: 2 in FP32, 1 in FP64 (measured
+// on the sphere workload: more velocities per thread raise the loads in flight but cost occupancy).
 template <class T> struct Vpt;
 template <> struct Vpt<double> { static constexpr int v = 1; };
-template <> struct Vpt<float> { static constexpr int v = 4; };
+template <> struct Vpt<float> { static constexpr int v = 2; };
 
 template <class T> static inline unsigned n_chunks(int64_t nv) {
   constexpr int c = kBlock * Vpt<T>::v;
   return (unsigned)((nv + c - 1) / c);
 }
 
+// (cell, chunk) workgroups run on a 1-D grid in chunk-major order: all cells of chunk 0, then of chunk 1, ...,
+// so that at any time the whole GPU works on one velocity chunk of every row (a slice that stays in the
+// last-level cache).  Within a chunk the cells are padded to a multiple of the XCD count and dealt out so
+// that every XCD gets one contiguous range of the (Morton-ordered) cells.
+struct CellChunk {
+  int64_t cell, chunk;
+};
+__host__ __device__ inline int64_t padded_cells(int64_t ncells) { return (ncells + kXcd - 1) / kXcd * kXcd; }
+__device__ inline CellChunk cell_chunk(int64_t ncells) {
+  const int64_t np = padded_cells(ncells);
+  const int64_t r = (int64_t)blockIdx.x % np;
+  return CellChunk{xcd_block(r, np), (int64_t)blockIdx.x / np};
+}
+
 // Velocity loop of a (cell, chunk) workgroup: Vpt<T> coalesced velocities per thread.
-template <class T, class F> __device__ inline void chunk_loop(int64_t nv, F&& body) {
+template <class T, class F> __device__ inline void chunk_loop(int64_t nv, int64_t chunk, F&& body) {
   constexpr int U = Vpt<T>::v;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int64_t k = (int64_t)blockIdx.y * (kBlock * U) + (int64_t)u * kBlock + threadIdx.x;
+    const int64_t k = chunk * (kBlock * U) + (int64_t)u * kBlock + threadIdx.x;
     if (k < nv) body(k);
   }
+}
+
+template <class T> static inline dim3 cell_chunk_grid(int64_t ncells, int64_t nv) {
+  return dim3((unsigned)(padded_cells(ncells) * (int64_t)n_chunks<T>(nv)));
 }
 
 
@@ -62,15 +81,17 @@ __global__ __launch_bounds__(kBlock) void k_eq_from_W(const double* W0, int per_
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_fill_eq(Dev d, const double* eq, T* G, T* R, double* W, double* q,
                                                     const double* W0, int per_cell) {
-  const int64_t i = blockIdx.x;
+  const CellChunk cc = cell_chunk(d.nc);
+  if (cc.cell >= d.nc) return;
+  const int64_t i = cc.cell;
   const int64_t nv = d.nv;
-  if (blockIdx.y == 0 && threadIdx.x < 6) {
+  if (cc.chunk == 0 && threadIdx.x < 6) {
     W[6 * i + threadIdx.x] = per_cell ? W0[6 * i + threadIdx.x] : W0[threadIdx.x];
     q[6 * i + threadIdx.x] = 0.0;
   }
   Eq<T> e;
   e.load(eq + ER * i);
-  chunk_loop<T>(nv, [&](int64_t k) {
+  chunk_loop<T>(nv, cc.chunk, [&](int64_t k) {
     T ux, uy, uz, gs, rs;
     vel_t<T>(d, k, ux, uy, uz);
     e.eval(ux, uy, uz, gs, rs);
@@ -83,7 +104,7 @@ template <class T>
 void launch_init_eq(const Dev& d, const Bufs& b, const double* W0, int per_cell, double* eqtmp, hipStream_t st) {
   int nb = (int)((d.nc + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_eq_from_W, dim3(nb), dim3(kBlock), 0, st, W0, per_cell, d.gas, d.nc, eqtmp);
-  hipLaunchKernelGGL(k_fill_eq<T>, dim3((unsigned)d.nc, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, (const double*)eqtmp,
+  hipLaunchKernelGGL(k_fill_eq<T>, cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, (const double*)eqtmp,
                      (T*)b.G, (T*)b.R, b.W, b.q, W0, per_cell);
 }
 
@@ -92,38 +113,32 @@ void launch_init_eq(const Dev& d, const Bufs& b, const double* W0, int per_cell,
 // Workgroup (cell, velocity chunk); each (face, velocity) value phi_bar is written once, by its upwind cell.
 // ---------------------------------------------------------------------------
 
+// One distribution at one velocity: limited least-squares gradient of the cell and the upwind face values.
 template <class T>
-__device__ inline void recon_one(const Dev& d, const T* __restrict__ src, T* __restrict__ dst, int64_t i, int64_t k,
-                                 const int32_t* nb, const int32_t* fc, const double* geo, double kh3, const Vel& v,
-                                 const double* un) {
-  const int64_t nv = d.nv;
-  T phi = src[i * nv + k];
-  T pn[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) pn[a] = nb[a] >= 0 ? src[(int64_t)nb[a] * nv + k] : phi;
+__device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const T* wx, const T* wy, const T* wz,
+                                   const T* fx, const T* fy, const T* fz, const T* sf, T kh3, int limiter,
+                                   const bool* up, T ux, T uy, T uz, T* const* dst, int k) {
   T gx = 0, gy = 0, gz = 0, pmax = phi, pmin = phi;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     if (nb[a] < 0) continue;
-    const double* s = geo + CG_FACE + CG_SLOT * a;
-    T dphi = pn[a] - phi;
-    gx += (T)s[9] * dphi;
-    gy += (T)s[10] * dphi;
-    gz += (T)s[11] * dphi;
+    const T dphi = pn[a] - phi;
+    gx += wx[a] * dphi;
+    gy += wy[a] * dphi;
+    gz += wz[a] * dphi;
     pmax = pn[a] > pmax ? pn[a] : pmax;
     pmin = pn[a] < pmin ? pn[a] : pmin;
   }
   T L = 1;
-  if (d.limiter) {
-    T scale = fabs(pmax) > fabs(pmin) ? fabs(pmax) : fabs(pmin);
-    T eps2 = (T)kh3 * scale * scale;
+  if (limiter) {
+    const T scale = fabs(pmax) > fabs(pmin) ? fabs(pmax) : fabs(pmin);
+    const T eps2 = kh3 * scale * scale;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const double* s = geo + CG_FACE + CG_SLOT * a;
-      T d2 = gx * (T)s[5] + gy * (T)s[6] + gz * (T)s[7];
+      const T d2 = gx * fx[a] + gy * fy[a] + gz * fz[a];
       if (d2 != T(0)) {
-        T d1 = d2 > T(0) ? pmax - phi : pmin - phi;
-        T psi = ((d1 * d1 + eps2) * d2 + T(2) * d2 * d2 * d1) / (d2 * (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2));
+        const T d1 = d2 > T(0) ? pmax - phi : pmin - phi;
+        const T psi = ((d1 * d1 + eps2) * d2 + T(2) * d2 * d2 * d1) / (d2 * (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2));
         L = psi < L ? psi : L;
       }
     }
@@ -133,43 +148,97 @@ __device__ inline void recon_one(const Dev& d, const T* __restrict__ src, T* __r
   gz *= L;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const double* s = geo + CG_FACE + CG_SLOT * a;
-    // upwind cell of the face for this velocity: the owner when u.n_face > 0, else the neighbour
-    bool up = nb[a] >= 0 ? (s[0] > 0.0 ? un[a] > 0.0 : un[a] >= 0.0) : un[a] > 0.0;
-    if (!up) continue;
-    T sf = (T)s[8];
-    T val = phi + ((T)s[5] - (T)v.ux * sf) * gx + ((T)s[6] - (T)v.uy * sf) * gy + ((T)s[7] - (T)v.uz * sf) * gz;
-    dst[(int64_t)fc[a] * nv + k] = val;
+    if (!up[a]) continue;
+    dst[a][k] = phi + (fx[a] - ux * sf[a]) * gx + (fy[a] - uy * sf[a]) * gy + (fz[a] - uz * sf[a]) * gz;
   }
 }
 
+// Every load of a thread's velocities is issued before its first store (the stores could alias later loads
+// as far as the compiler knows); per-cell geometry is converted once into registers.
 template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b) {
-  const int64_t i = blockIdx.x;
+  constexpr int U = Vpt<T>::v;
+  const CellChunk cc = cell_chunk(d.nc);
+  if (cc.cell >= d.nc) return;
+  const int64_t i = cc.cell;
   const int64_t nv = d.nv;
-  int32_t nb[4], fc[4];
+  const double* geo = d.cell_geo + CG * i;
+  const T* G = (const T*)b.G;
+  const T* R = (const T*)b.R;
+  int32_t nb[4];
+  const T *sG[4], *sR[4];
+  T *dG[4], *dR[4];
+  double nx[4], ny[4], nz[4];
+  bool own[4];
+  T wx[4], wy[4], wz[4], fx[4], fy[4], fz[4], sf[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     nb[a] = d.cell_nb[4 * i + a];
-    fc[a] = d.cell_face[4 * i + a];
+    const int64_t f = d.cell_face[4 * i + a];
+    const int64_t src = nb[a] >= 0 ? nb[a] : i;
+    sG[a] = G + src * nv;
+    sR[a] = R + src * nv;
+    dG[a] = (T*)b.faceG + f * nv;
+    dR[a] = (T*)b.faceR + f * nv;
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    own[a] = s[0] > 0.0;
+    nx[a] = s[2];
+    ny[a] = s[3];
+    nz[a] = s[4];
+    fx[a] = (T)s[5];
+    fy[a] = (T)s[6];
+    fz[a] = (T)s[7];
+    sf[a] = (T)s[8];
+    wx[a] = (T)s[9];
+    wy[a] = (T)s[10];
+    wz[a] = (T)s[11];
   }
-  const double* geo = d.cell_geo + CG * i;
-  double kh3 = d.lim_K * geo[2];
-  kh3 = kh3 * kh3 * kh3;
-  chunk_loop<T>(nv, [&](int64_t k) {
-    const Vel v = vel(d, k);
-    double un[4];
+  double kh3d = d.lim_K * geo[2];
+  kh3d = kh3d * kh3d * kh3d;
+  const T kh3 = (T)kh3d;
+  const int limiter = d.limiter;
+  const double snap = d.snap;
+  const T* selfG = G + i * nv;
+  const T* selfR = R + i * nv;
+  const int nvi = (int)nv;
+  const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
+  T pG[U], pR[U], nG[U][4], nR[U][4];
+  double ux[U], uy[U], uz[U], um[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * kBlock;
+    if (k >= nvi) continue;
+    ux[u] = d.dvs[k];
+    uy[u] = d.dvs[nv + k];
+    uz[u] = d.dvs[2 * nv + k];
+    um[u] = d.dvs[4 * nv + k];
+    pG[u] = selfG[k];
+    pR[u] = selfR[k];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const double* s = geo + CG_FACE + CG_SLOT * a;
-      un[a] = udotn(v, s[2], s[3], s[4], d.snap);
+      nG[u][a] = sG[a][k];
+      nR[u][a] = sR[a][k];
     }
-    recon_one<T>(d, (const T*)b.G, (T*)b.faceG, i, k, nb, fc, geo, kh3, v, un);
-    recon_one<T>(d, (const T*)b.R, (T*)b.faceR, i, k, nb, fc, geo, kh3, v, un);
-  });
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * kBlock;
+    if (k >= nvi) continue;
+    bool up[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      double un = ux[u] * nx[a] + uy[u] * ny[a] + uz[u] * nz[a];
+      un = fabs(un) <= snap * um[u] ? 0.0 : un;
+      // upwind cell of the face for this velocity: the owner when u.n_face > 0, else the neighbour
+      up[a] = nb[a] >= 0 ? (own[a] ? un > 0.0 : un >= 0.0) : un > 0.0;
+    }
+    const T tx = (T)ux[u], ty = (T)uy[u], tz = (T)uz[u];
+    recon_write<T>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up, tx, ty, tz, dG, k);
+    recon_write<T>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up, tx, ty, tz, dR, k);
+  }
 }
 
 template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_recon<T>, dim3((unsigned)d.nc, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, b);
+  hipLaunchKernelGGL(k_recon<T>, cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -516,24 +585,32 @@ void launch_macro_flux_cells(const Dev& d, const Work& w, hipStream_t st) {
   hipLaunchKernelGGL(k_macro_flux_cells, dim3(nb), dim3(kBlock), 0, st, d, w);
 }
 
+// Colour order of n_pairs forward + backward Gauss-Seidel passes over the non-empty colours.  A colour that
+// follows itself (at each turn of direction) is relaxed only once: its neighbours, all of other colours, have
+// not changed in between, so a second relaxation would reproduce the first bit for bit.
+std::vector<int64_t> sweep_sequence(const int64_t* color_off, int64_t n_colors, int n_pairs) {
+  std::vector<int64_t> seq;
+  auto push = [&](int64_t c) {
+    if (color_off[c + 1] <= color_off[c]) return;
+    if (!seq.empty() && seq.back() == c) return;
+    seq.push_back(c);
+  };
+  for (int it = 0; it < n_pairs; ++it) {
+    for (int64_t c = 0; c < n_colors; ++c) push(c);
+    for (int64_t c = n_colors - 1; c >= 0; --c) push(c);
+  }
+  return seq;
+}
+
 void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_macro,
                   hipStream_t st) {
   int nb = (int)((d.nc + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_cell_prim, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, w);
   hipLaunchKernelGGL(k_macro_prep, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, w);
-  for (int it = 0; it < n_macro; ++it) {
-    for (int64_t c = 0; c < n_colors; ++c) {
-      int64_t n = color_off[c + 1] - color_off[c];
-      if (n <= 0) continue;
-      hipLaunchKernelGGL(k_macro_sweep, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d,
-                         (const double*)b.W, w, color_off[c], color_off[c + 1]);
-    }
-    for (int64_t c = n_colors - 1; c >= 0; --c) {
-      int64_t n = color_off[c + 1] - color_off[c];
-      if (n <= 0) continue;
-      hipLaunchKernelGGL(k_macro_sweep, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d,
-                         (const double*)b.W, w, color_off[c], color_off[c + 1]);
-    }
+  for (const int64_t c : sweep_sequence(color_off, n_colors, n_macro)) {
+    const int64_t n = color_off[c + 1] - color_off[c];
+    hipLaunchKernelGGL(k_macro_sweep, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d,
+                       (const double*)b.W, w, color_off[c], color_off[c + 1]);
   }
   hipLaunchKernelGGL(k_cell_eq, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, (const double*)b.q, w);
 }
@@ -545,45 +622,82 @@ void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* outG, T* outR, int flux_only) {
-  const int64_t i = blockIdx.x;
+  constexpr int U = Vpt<T>::v;
+  const CellChunk cc = cell_chunk(d.nc);
+  if (cc.cell >= d.nc) return;
+  const int64_t i = cc.cell;
   const int64_t nv = d.nv;
   const double* geo = d.cell_geo + CG * i;
-  int64_t fr[4];
+  const T *fG[4], *fR[4];
   T sg[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    fr[a] = (int64_t)d.cell_face[4 * i + a] * nv;
+    const int64_t f = d.cell_face[4 * i + a];
+    fG[a] = (const T*)b.faceG + f * nv;
+    fR[a] = (const T*)b.faceR + f * nv;
     sg[a] = (T)(geo[CG_FACE + CG_SLOT * a] * geo[1]);
   }
-  const T* fG = (const T*)b.faceG;
-  const T* fR = (const T*)b.faceR;
+  const int nvi = (int)nv;
+  const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
+  T* oG = outG + i * nv;
+  T* oR = outR + i * nv;
+  T xG[U][4], xR[U][4];
   if (flux_only) {
-    chunk_loop<T>(nv, [&](int64_t k) {
-      outG[i * nv + k] = sg[0] * fG[fr[0] + k] + sg[1] * fG[fr[1] + k] + sg[2] * fG[fr[2] + k] + sg[3] * fG[fr[3] + k];
-      outR[i * nv + k] = sg[0] * fR[fr[0] + k] + sg[1] * fR[fr[1] + k] + sg[2] * fR[fr[2] + k] + sg[3] * fR[fr[3] + k];
-    });
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * kBlock;
+      if (k >= nvi) continue;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        xG[u][a] = fG[a][k];
+        xR[u][a] = fR[a][k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * kBlock;
+      if (k >= nvi) continue;
+      oG[k] = sg[0] * xG[u][0] + sg[1] * xG[u][1] + sg[2] * xG[u][2] + sg[3] * xG[u][3];
+      oR[k] = sg[0] * xR[u][0] + sg[1] * xR[u][1] + sg[2] * xR[u][2] + sg[3] * xR[u][3];
+    }
     return;
   }
   const double* ec = w.eq + ER * i;
   Eq<T> e;
   e.load(ec);
   const T itau = (T)(1.0 / ec[7]);
-  const T* G = (const T*)b.G;
-  const T* R = (const T*)b.R;
-  chunk_loop<T>(nv, [&](int64_t k) {
-    const T FG = sg[0] * fG[fr[0] + k] + sg[1] * fG[fr[1] + k] + sg[2] * fG[fr[2] + k] + sg[3] * fG[fr[3] + k];
-    const T FR = sg[0] * fR[fr[0] + k] + sg[1] * fR[fr[1] + k] + sg[2] * fR[fr[2] + k] + sg[3] * fR[fr[3] + k];
-    T ux, uy, uz, gs, rs;
-    vel_t<T>(d, k, ux, uy, uz);
-    e.eval(ux, uy, uz, gs, rs);
-    outG[i * nv + k] = (gs - G[i * nv + k]) * itau - FG;
-    outR[i * nv + k] = (rs - R[i * nv + k]) * itau - FR;
-  });
+  const T* G = (const T*)b.G + i * nv;
+  const T* R = (const T*)b.R + i * nv;
+  T pG[U], pR[U], ux[U], uy[U], uz[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * kBlock;
+    if (k >= nvi) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      xG[u][a] = fG[a][k];
+      xR[u][a] = fR[a][k];
+    }
+    pG[u] = G[k];
+    pR[u] = R[k];
+    vel_t<T>(d, k, ux[u], uy[u], uz[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * kBlock;
+    if (k >= nvi) continue;
+    const T FG = sg[0] * xG[u][0] + sg[1] * xG[u][1] + sg[2] * xG[u][2] + sg[3] * xG[u][3];
+    const T FR = sg[0] * xR[u][0] + sg[1] * xR[u][1] + sg[2] * xR[u][2] + sg[3] * xR[u][3];
+    T gs, rs;
+    e.eval(ux[u], uy[u], uz[u], gs, rs);
+    oG[k] = (gs - pG[u]) * itau - FG;
+    oR[k] = (rs - pR[u]) * itau - FR;
+  }
 }
 
 template <class T>
 void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR, int flux_only, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)d.nc, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, b, w, (T*)outG,
+  hipLaunchKernelGGL(k_residual<T>, cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w, (T*)outG,
                      (T*)outR, flux_only);
 }
 
@@ -595,59 +709,89 @@ void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, voi
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, int64_t c0, int64_t cnext, int first) {
-  const int64_t i = c0 + blockIdx.x;
+  constexpr int U = Vpt<T>::v;
+  const CellChunk cc = cell_chunk(cnext - c0);
+  if (cc.cell >= cnext - c0) return;
+  const int64_t i = c0 + cc.cell;
   const int64_t nv = d.nv;
   const double* geo = d.cell_geo + CG * i;
-  int64_t nrow[4];
+  const T *nG[4], *nR[4];
   bool use[4];
+  double nx[4], ny[4], nz[4], av[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    int32_t nb = d.cell_nb[4 * i + a];
+    const int32_t nb = d.cell_nb[4 * i + a];
     use[a] = nb >= 0 && !(first && nb >= cnext);
-    nrow[a] = nb >= 0 ? (int64_t)nb * nv : 0;
+    const int64_t row = (nb >= 0 ? nb : i) * nv;
+    nG[a] = (const T*)b.dG + row;
+    nR[a] = (const T*)b.dR + row;
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    nx[a] = s[2];
+    ny[a] = s[3];
+    nz[a] = s[4];
+    av[a] = s[1];
   }
   const double base = inv_dt_cell(d, geo[2]) + 1.0 / w.eq[ER * i + 7];
-  const T* rG = (const T*)b.resG;
-  const T* rR = (const T*)b.resR;
-  T* dG = (T*)b.dG;
-  T* dR = (T*)b.dR;
-  chunk_loop<T>(nv, [&](int64_t k) {
-    const Vel v = vel(d, k);
-    double D = base;
-    double aG = (double)rG[i * nv + k], aR = (double)rR[i * nv + k];
+  const double snap = d.snap;
+  const T* rG = (const T*)b.resG + i * nv;
+  const T* rR = (const T*)b.resR + i * nv;
+  T* oG = (T*)b.dG + i * nv;
+  T* oR = (T*)b.dR + i * nv;
+  const int nvi = (int)nv;
+  const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
+  // loads: velocities, right-hand sides and the upstream neighbours' increments
+  double un[U][4];
+  T xG[U], xR[U], yG[U][4], yR[U][4];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * kBlock;
+    if (k >= nvi) continue;
+    const double ux = d.dvs[k], uy = d.dvs[nv + k], uz = d.dvs[2 * nv + k], um = d.dvs[4 * nv + k];
+    xG[u] = rG[k];
+    xR[u] = rR[k];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const double* s = geo + CG_FACE + CG_SLOT * a;
-      double un = udotn(v, s[2], s[3], s[4], d.snap);
-      double av = s[1];
-      D += av * fmax(un, 0.0);
-      if (use[a] && un < 0.0) {
-        aG -= av * un * (double)dG[nrow[a] + k];
-        aR -= av * un * (double)dR[nrow[a] + k];
+      double t = ux * nx[a] + uy * ny[a] + uz * nz[a];
+      t = fabs(t) <= snap * um ? 0.0 : t;
+      un[u][a] = t;
+      if (use[a] && t < 0.0) {
+        yG[u][a] = nG[a][k];
+        yR[u][a] = nR[a][k];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * kBlock;
+    if (k >= nvi) continue;
+    double D = base;
+    double aG = (double)xG[u], aR = (double)xR[u];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double t = un[u][a];
+      D += av[a] * fmax(t, 0.0);
+      if (use[a] && t < 0.0) {
+        aG -= av[a] * t * (double)yG[u][a];
+        aR -= av[a] * t * (double)yR[u][a];
       }
     }
     const double iD = 1.0 / D;
-    dG[i * nv + k] = (T)(aG * iD);
-    dR[i * nv + k] = (T)(aR * iD);
-  });
+    oG[k] = (T)(aG * iD);
+    oR[k] = (T)(aR * iD);
+  }
 }
 
 template <class T>
 void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_micro,
                   hipStream_t st) {
-  for (int it = 0; it < n_micro; ++it) {
-    for (int64_t c = 0; c < n_colors; ++c) {
-      int64_t n = color_off[c + 1] - color_off[c];
-      if (n <= 0) continue;
-      hipLaunchKernelGGL(k_micro_sweep<T>, dim3((unsigned)n, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, b, w,
-                         color_off[c], color_off[c + 1], it == 0 ? 1 : 0);
-    }
-    for (int64_t c = n_colors - 1; c >= 0; --c) {
-      int64_t n = color_off[c + 1] - color_off[c];
-      if (n <= 0) continue;
-      hipLaunchKernelGGL(k_micro_sweep<T>, dim3((unsigned)n, n_chunks<T>(d.nv)), dim3(kBlock), 0, st, d, b, w,
-                         color_off[c], color_off[c + 1], 0);
-    }
+  const std::vector<int64_t> seq = sweep_sequence(color_off, n_colors, n_micro);
+  int64_t nonempty = 0;
+  for (int64_t c = 0; c < n_colors; ++c) nonempty += color_off[c + 1] > color_off[c];
+  for (size_t p = 0; p < seq.size(); ++p) {
+    const int64_t c = seq[p];
+    const int64_t n = color_off[c + 1] - color_off[c];
+    hipLaunchKernelGGL(k_micro_sweep<T>, cell_chunk_grid<T>(n, d.nv), dim3(kBlock), 0, st, d, b, w, color_off[c],
+                       color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
   }
 }
 
