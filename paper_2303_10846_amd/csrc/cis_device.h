@@ -31,48 +31,46 @@ __device__ inline void two_sum_add(double& s, double& c, double x) {
   s = t;
 }
 
-// N running FP64 sums per thread.  Per-thread partials add a handful of terms in plain FP64; when Comp is set
-// the merge of the partials across the workgroup is Neumaier-compensated.
+// N running FP64 sums per thread.  With Comp, every thread's running sum is Neumaier-compensated (the long
+// sequential part of the summation); the 64 lanes of a wavefront are combined by a pairwise shuffle tree
+// (error O(log2(64) eps)) and the wavefronts' results again with Neumaier compensation.  Without Comp the
+// running sums and the merge are plain FP64.
 template <int N, bool Comp, int NT> struct Acc {
   static constexpr int NW = NT / 64;
-  double s[N];
+  double s[N], c[Comp ? N : 1];
   __device__ inline void zero() {
 #pragma unroll
-    for (int m = 0; m < N; ++m) s[m] = 0.0;
+    for (int m = 0; m < N; ++m) {
+      s[m] = 0.0;
+      if (Comp) c[m] = 0.0;
+    }
   }
-  __device__ inline void add(int m, double x) { s[m] += x; }
-  // Block-wide totals, identical in every thread.  red: NW * 2N doubles of LDS.
+  __device__ inline void add(int m, double x) {
+    if (Comp) {
+      two_sum_add(s[m], c[m], x);
+    } else {
+      s[m] += x;
+    }
+  }
+  // Block-wide totals, identical in every thread.  red: NW * N doubles of LDS.
   __device__ inline void reduce(double* out, double* red) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      double a = s[m], b = 0.0;
+      double a = Comp ? s[m] + c[m] : s[m];
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        double a2 = __shfl_xor(a, o, 64);
-        if (Comp) {
-          double b2 = __shfl_xor(b, o, 64);
-          two_sum_add(a, b, a2);
-          b += b2;
-        } else {
-          a += a2;
-        }
-      }
-      if (lane == 0) {
-        red[wid * 2 * N + m] = a;
-        red[wid * 2 * N + N + m] = b;
-      }
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      if (lane == 0) red[wid * N + m] = a;
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      double a = red[m], b = red[N + m];
+      double a = red[m], b = 0.0;
       for (int q = 1; q < NW; ++q) {
         if (Comp) {
-          two_sum_add(a, b, red[q * 2 * N + m]);
-          b += red[q * 2 * N + N + m];
+          two_sum_add(a, b, red[q * N + m]);
         } else {
-          a += red[q * 2 * N + m];
+          a += red[q * N + m];
         }
       }
       out[m] = Comp ? a + b : a;

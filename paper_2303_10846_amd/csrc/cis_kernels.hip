@@ -4,14 +4,16 @@
 // Layout: distributions are [cell][velocity] rows (velocity contiguous); the
 // discrete velocity set is stored as separate coalesced arrays.  Kernels that
 // read neighbour rows (reconstruction, micro residual, micro sweeps) run one
-// workgroup per (cell, chunk of 256 velocities) in chunk-major order, so one
-// velocity chunk of every row is touched within a short window.  Kernels that
-// reduce over the whole velocity set of one face or cell (face pass, update)
-// run one workgroup per face or cell, 4 independent loads per loop trip.  DVS moment sums
-// are FP64 wavefront reductions, Neumaier-compensated across threads in the
-// mixed-precision mode.  The coloured Gauss-Seidel sweeps update one colour at
-// a time: cells of one colour share no face.  Nothing here is a dense
-// contraction; the kernels are bound by HBM bandwidth (and latency), not MFMA.
+// workgroup per (cell, velocity chunk) in chunk-major order, so one velocity
+// chunk of every row is touched within a short window; each thread issues all
+// its loads before its first store.  Kernels that reduce over the whole
+// velocity set of one face or cell (face pass, update) run one workgroup per
+// face or cell.  DVS moment sums are FP64: per-thread running sums, a pairwise
+// shuffle tree per wavefront, and a merge of the wavefronts; in the mixed mode
+// the sums of the conservative update are Neumaier-compensated.  The coloured
+// Gauss-Seidel sweeps update one colour at a time: cells of one colour share no
+// face.  Nothing here is a dense contraction; the kernels are bound by HBM
+// bandwidth, latency and (face pass) vector ALU, not MFMA.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -247,6 +249,8 @@ template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st
 // and the face's macro flux A sum_k w (u.n) Phi phi_f (Eq. 37).  Boundary faces: diffuse wall with rho_w
 // from zero net mass flux, or far-field Maxwellian, for incoming velocities.  phi_bar is staged in LDS
 // (UseLds) or re-read from global memory; every velocity loop issues kUnroll independent loads per trip.
+// The face sums are plain FP64 (each face flux is computed once and applied with opposite signs to its two
+// cells, so conservation does not depend on their rounding; compensating them was measured at +40% face time).
 // ---------------------------------------------------------------------------
 
 #ifndef CIS_UNROLL
@@ -257,17 +261,29 @@ constexpr int kUnroll = CIS_UNROLL;
 // Velocity loop of a per-face / per-cell workgroup over all nv velocities, kUnroll independent
 // velocities per trip.
 template <class F> __device__ inline void k_loop(int64_t nv, F&& body) {
-  for (int64_t k0 = threadIdx.x; k0 < nv; k0 += (int64_t)kUnroll * kBlock) {
+  const int n = (int)nv;
+  for (int k0 = threadIdx.x; k0 < n; k0 += kUnroll * kBlock) {
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
-      const int64_t k = k0 + (int64_t)q * kBlock;
-      if (k < nv) body(k);
+      const int k = k0 + q * kBlock;
+      if (k < n) body(k);
     }
   }
 }
 
+// The DVS arrays as uniform row pointers (32-bit velocity offsets)
+struct DvsRows {
+  const double *ux, *uy, *uz, *w, *um, *h2;
+};
+__device__ inline DvsRows dvs_rows(const Dev& d) {
+  const double* v = d.dvs;
+  const int64_t n = d.nv;
+  return DvsRows{v, v + n, v + 2 * n, v + 3 * n, v + 4 * n, v + 5 * n};
+}
+__device__ inline Vel vel(const DvsRows& V, int k) { return Vel{V.ux[k], V.uy[k], V.uz[k], V.w[k], V.um[k], V.h2[k]}; }
 
-template <class T, bool Comp, bool UseLds>
+
+template <class T, bool UseLds>
 __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   extern __shared__ unsigned char smem_raw[];
   T* sG = reinterpret_cast<T*>(smem_raw);
@@ -281,19 +297,20 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   T* rowR = (T*)b.faceR + f * nv;
   const int32_t bcs = d.face_bc[f];
   const GasC& g = d.gas;
-  Acc<6, Comp, kBlock> acc;
+  const DvsRows V = dvs_rows(d);
+  Acc<6, false, kBlock> acc;
   double tot[6];
 
   if (bcs < 0) {
     // pass 1: Eqs. 47-49 and sum_k w R_bar
     acc.zero();
-    k_loop(nv, [&](int64_t k) {
+    k_loop(nv, [&](int k) {
       const T gb = rowG[k], rb = rowR[k];
       if (UseLds) {
         sG[k] = gb;
         sR[k] = rb;
       }
-      const Vel v = vel(d, k);
+      const Vel v = vel(V, k);
       double wg = v.w * (double)gb, wr = v.w * (double)rb;
       acc.add(0, wg);
       acc.add(1, v.ux * wg);
@@ -321,10 +338,10 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     p.Ttr = (2.0 / 3.0) * (E - ke - Erot) / rR;
     // pass 2: heat fluxes, Eqs. 51-52, c = u - U_f
     acc.zero();
-    k_loop(nv, [&](int64_t k) {
+    k_loop(nv, [&](int k) {
       const T gb = UseLds ? sG[k] : rowG[k];
       const T rb = UseLds ? sR[k] : rowR[k];
-      const Vel v = vel(d, k);
+      const Vel v = vel(V, k);
       double cx = v.ux - U[0], cy = v.uy - U[1], cz = v.uz - U[2];
       double c2 = cx * cx + cy * cy + cz * cz;
       double wg = v.w * c2 * (double)gb, wr = v.w * (double)rb;
@@ -343,20 +360,21 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       q[m] = tau * 0.5 * tot[m] / den_tr;
       q[3 + m] = tau * tot[3 + m] / den_rot;
     }
-    double ec[ER];
-    eq_coeffs(p, q, g, ec);
+    // the face equilibrium's coefficients, computed once per face and shared through LDS
+    __shared__ double sh_ec[ER];
+    if (threadIdx.x == 0) eq_coeffs(p, q, g, sh_ec);
+    __syncthreads();
     Eq<T> e;
-    e.load(ec);
+    e.load(sh_ec);
     const T ct = (T)(tau / (tau + s)), cs = (T)(s / (tau + s));
     // pass 3: phi_f (Eq. 45), micro flux and macro flux
     acc.zero();
-    k_loop(nv, [&](int64_t k) {
+    k_loop(nv, [&](int k) {
       const T gb = UseLds ? sG[k] : rowG[k];
       const T rb = UseLds ? sR[k] : rowR[k];
-      const Vel v = vel(d, k);
-      T ux, uy, uz, gs, rs;
-      vel_t<T>(d, k, ux, uy, uz);
-      e.eval(ux, uy, uz, gs, rs);
+      const Vel v = vel(V, k);
+      T gs, rs;
+      e.eval((T)v.ux, (T)v.uy, (T)v.uz, gs, rs);
       const T gf = ct * gb + cs * gs;
       const T rf = ct * rb + cs * rs;
       const double un = udotn(v, nx, ny, nz, d.snap);
@@ -379,11 +397,11 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     double rho_g = bc[1];
     if (wall) {
       // rho_w from zero net mass flux through the wall
-      Acc<2, Comp, kBlock> a2;
+      Acc<2, false, kBlock> a2;
       a2.zero();
       const double anorm = pow(6.283185307179586476925 * RTb, -1.5);
-      k_loop(nv, [&](int64_t k) {
-        const Vel v = vel(d, k);
+      k_loop(nv, [&](int k) {
+        const Vel v = vel(V, k);
         const double un = udotn(v, nx, ny, nz, d.snap);
         if (un > 0.0) {
           a2.add(0, v.w * un * (double)rowG[k]);
@@ -399,8 +417,8 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     const T amax = (T)(rho_g * pow(6.283185307179586476925 * RTb, -1.5));
     const T bmax = (T)(1.0 / (2.0 * RTb));
     acc.zero();
-    k_loop(nv, [&](int64_t k) {
-      const Vel v = vel(d, k);
+    k_loop(nv, [&](int k) {
+      const Vel v = vel(V, k);
       const double un = udotn(v, nx, ny, nz, d.snap);
       T gf, rf;
       if (un > 0.0) {
@@ -431,24 +449,22 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
 constexpr int64_t kLdsDefault = 64 * 1024, kLdsMax = 160 * 1024 - 4096;
 
 template <class T> static bool face_lds_ok(int64_t nv) {
-  constexpr bool Comp = sizeof(T) == 4;
   int64_t bytes = nv * 2 * (int64_t)sizeof(T);
   if (bytes <= kLdsDefault) return true;
   if (bytes > kLdsMax) return false;
   static int raised = 0;  // 0 unknown, 1 raised, -1 refused
   if (raised == 0)
-    raised = hipFuncSetAttribute((const void*)k_face<T, Comp, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    raised = hipFuncSetAttribute((const void*)k_face<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kLdsMax) == hipSuccess ? 1 : -1;
   return raised == 1;
 }
 
 template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
-  constexpr bool Comp = sizeof(T) == 4;
   if (face_lds_ok<T>(d.nv)) {
     size_t lds = (size_t)d.nv * 2 * sizeof(T);
-    hipLaunchKernelGGL((k_face<T, Comp, true>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
+    hipLaunchKernelGGL((k_face<T, true>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
   } else {
-    hipLaunchKernelGGL((k_face<T, Comp, false>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, w);
+    hipLaunchKernelGGL((k_face<T, false>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, w);
   }
 }
 
@@ -707,78 +723,113 @@ void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, voi
 // increments of later colours are still zero and are not read.  Workgroup (cell, velocity chunk).
 // ---------------------------------------------------------------------------
 
+// Per-cell operands of one relaxation
+template <class T> struct MicroCell {
+  const T *nG[4], *nR[4], *rG, *rR;
+  T *oG, *oR;
+  double nx[4], ny[4], nz[4], av[4], base;
+  bool use[4];
+};
+
+template <class T>
+__device__ inline void micro_setup(const Dev& d, const Bufs& b, const Work& w, int64_t i, int64_t cnext, int first,
+                                   MicroCell<T>& c) {
+  const int64_t nv = d.nv;
+  const double* geo = d.cell_geo + CG * i;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int32_t nb = d.cell_nb[4 * i + a];
+    c.use[a] = nb >= 0 && !(first && nb >= cnext);
+    const int64_t row = (nb >= 0 ? nb : i) * nv;
+    c.nG[a] = (const T*)b.dG + row;
+    c.nR[a] = (const T*)b.dR + row;
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    c.nx[a] = s[2];
+    c.ny[a] = s[3];
+    c.nz[a] = s[4];
+    c.av[a] = s[1];
+  }
+  c.base = inv_dt_cell(d, geo[2]) + 1.0 / w.eq[ER * i + 7];
+  c.rG = (const T*)b.resG + i * nv;
+  c.rR = (const T*)b.resR + i * nv;
+  c.oG = (T*)b.dG + i * nv;
+  c.oR = (T*)b.dR + i * nv;
+}
+
+// Values a relaxation reads: u.n per face, the right-hand sides and the upstream neighbours' increments
+template <class T, int U> struct MicroIn {
+  double un[U][4];
+  T xG[U], xR[U], yG[U][4], yR[U][4];
+};
+
+template <class T, int U>
+__device__ inline void micro_load(const MicroCell<T>& c, const double (*uv)[4], const int* k, int nvi, double snap,
+                                  MicroIn<T, U>& in) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (k[u] >= nvi) continue;
+    in.xG[u] = c.rG[k[u]];
+    in.xR[u] = c.rR[k[u]];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      double t = uv[u][0] * c.nx[a] + uv[u][1] * c.ny[a] + uv[u][2] * c.nz[a];
+      t = fabs(t) <= snap * uv[u][3] ? 0.0 : t;
+      in.un[u][a] = t;
+      if (c.use[a] && t < 0.0) {
+        in.yG[u][a] = c.nG[a][k[u]];
+        in.yR[u][a] = c.nR[a][k[u]];
+      }
+    }
+  }
+}
+
+template <class T, int U>
+__device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& in, const int* k, int nvi) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (k[u] >= nvi) continue;
+    double D = c.base;
+    double aG = (double)in.xG[u], aR = (double)in.xR[u];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double t = in.un[u][a];
+      D += c.av[a] * fmax(t, 0.0);
+      if (c.use[a] && t < 0.0) {
+        aG -= c.av[a] * t * (double)in.yG[u][a];
+        aR -= c.av[a] * t * (double)in.yR[u][a];
+      }
+    }
+    const double iD = 1.0 / D;
+    c.oG[k[u]] = (T)(aG * iD);
+    c.oR[k[u]] = (T)(aR * iD);
+  }
+}
+
+// Workgroup (cell, velocity chunk): velocities first, then every load of the relaxation, then the stores.
+// (Relaxing several cells per workgroup with the next cell's loads issued ahead was measured slower.)
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, int64_t c0, int64_t cnext, int first) {
   constexpr int U = Vpt<T>::v;
   const CellChunk cc = cell_chunk(cnext - c0);
   if (cc.cell >= cnext - c0) return;
-  const int64_t i = c0 + cc.cell;
   const int64_t nv = d.nv;
-  const double* geo = d.cell_geo + CG * i;
-  const T *nG[4], *nR[4];
-  bool use[4];
-  double nx[4], ny[4], nz[4], av[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int32_t nb = d.cell_nb[4 * i + a];
-    use[a] = nb >= 0 && !(first && nb >= cnext);
-    const int64_t row = (nb >= 0 ? nb : i) * nv;
-    nG[a] = (const T*)b.dG + row;
-    nR[a] = (const T*)b.dR + row;
-    const double* s = geo + CG_FACE + CG_SLOT * a;
-    nx[a] = s[2];
-    ny[a] = s[3];
-    nz[a] = s[4];
-    av[a] = s[1];
-  }
-  const double base = inv_dt_cell(d, geo[2]) + 1.0 / w.eq[ER * i + 7];
-  const double snap = d.snap;
-  const T* rG = (const T*)b.resG + i * nv;
-  const T* rR = (const T*)b.resR + i * nv;
-  T* oG = (T*)b.dG + i * nv;
-  T* oR = (T*)b.dR + i * nv;
   const int nvi = (int)nv;
-  const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
-  // loads: velocities, right-hand sides and the upstream neighbours' increments
-  double un[U][4];
-  T xG[U], xR[U], yG[U][4], yR[U][4];
+  int k[U];
+  double uv[U][4];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int k = k0 + u * kBlock;
-    if (k >= nvi) continue;
-    const double ux = d.dvs[k], uy = d.dvs[nv + k], uz = d.dvs[2 * nv + k], um = d.dvs[4 * nv + k];
-    xG[u] = rG[k];
-    xR[u] = rR[k];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      double t = ux * nx[a] + uy * ny[a] + uz * nz[a];
-      t = fabs(t) <= snap * um ? 0.0 : t;
-      un[u][a] = t;
-      if (use[a] && t < 0.0) {
-        yG[u][a] = nG[a][k];
-        yR[u][a] = nR[a][k];
-      }
-    }
+    k[u] = (int)cc.chunk * (kBlock * U) + u * kBlock + (int)threadIdx.x;
+    if (k[u] >= nvi) continue;
+    uv[u][0] = d.dvs[k[u]];
+    uv[u][1] = d.dvs[nv + k[u]];
+    uv[u][2] = d.dvs[2 * nv + k[u]];
+    uv[u][3] = d.dvs[4 * nv + k[u]];
   }
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int k = k0 + u * kBlock;
-    if (k >= nvi) continue;
-    double D = base;
-    double aG = (double)xG[u], aR = (double)xR[u];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const double t = un[u][a];
-      D += av[a] * fmax(t, 0.0);
-      if (use[a] && t < 0.0) {
-        aG -= av[a] * t * (double)yG[u][a];
-        aR -= av[a] * t * (double)yR[u][a];
-      }
-    }
-    const double iD = 1.0 / D;
-    oG[k] = (T)(aG * iD);
-    oR[k] = (T)(aR * iD);
-  }
+  MicroCell<T> c;
+  MicroIn<T, U> in;
+  micro_setup<T>(d, b, w, c0 + cc.cell, cnext, first, c);
+  micro_load<T, U>(c, uv, k, nvi, d.snap, in);
+  micro_store<T, U>(c, in, k, nvi);
 }
 
 template <class T>
@@ -812,17 +863,17 @@ template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update
   T* R = (T*)b.R + i * nv;
   const T* dG = (const T*)b.dG + i * nv;
   const T* dR = (const T*)b.dR + i * nv;
+  const DvsRows V = dvs_rows(d);
   Acc<12, Comp, kBlock> acc;
   acc.zero();
-  k_loop(nv, [&](int64_t k) {
+  k_loop(nv, [&](int k) {
     const T g = G[k] + dG[k];
     const T r = R[k] + dR[k];
     G[k] = g;
     R[k] = r;
-    const Vel v = vel(d, k);
-    T ux, uy, uz, gs, rs;
-    vel_t<T>(d, k, ux, uy, uz);
-    e.eval(ux, uy, uz, gs, rs);
+    const Vel v = vel(V, k);
+    T gs, rs;
+    e.eval((T)v.ux, (T)v.uy, (T)v.uz, gs, rs);
     double gd = (double)g - (double)gs, rd = (double)r - (double)rs;
     double cx = v.ux - Ux, cy = v.uy - Uy, cz = v.uz - Uz;
     double c2 = cx * cx + cy * cy + cz * cz;
