@@ -248,8 +248,8 @@ template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st
 // collision-coupled face distribution (Eq. 45), micro flux A (u.n) phi_f (written in place over phi_bar)
 // and the face's macro flux A sum_k w (u.n) Phi phi_f (Eq. 37).  Boundary faces: diffuse wall with rho_w
 // from zero net mass flux, or far-field Maxwellian, for incoming velocities.  phi_bar is staged in LDS
-// (UseLds) or re-read from global memory; every velocity loop issues kUnroll independent loads per trip.
-// The face sums are plain FP64 (each face flux is computed once and applied with opposite signs to its two
+// (UseLds) or re-read from global memory in pass 2; every velocity loop issues kUnroll independent loads per
+// trip.  The face sums are plain FP64 (each face flux is computed once and applied with opposite signs to its two
 // cells, so conservation does not depend on their rounding; compensating them was measured at +40% face time).
 // ---------------------------------------------------------------------------
 
@@ -283,12 +283,54 @@ __device__ inline DvsRows dvs_rows(const Dev& d) {
 __device__ inline Vel vel(const DvsRows& V, int k) { return Vel{V.ux[k], V.uy[k], V.uz[k], V.w[k], V.um[k], V.h2[k]}; }
 
 
+// Face state after the collision coupling (Eqs. 47-52) from the 17 moment sums of pass 1 about U0, and the
+// coefficients of its equilibrium: ec[0..27] as eq_coeffs, ec[28] = tau/(tau+s), ec[29] = s/(tau+s).
+// (Its FP64 temporaries set the face kernel's register peak; an out-of-line call was measured slower.)
+__device__ inline void face_state_coeffs(const double* m, const double* U0, double s, const GasC& g, double* ec) {
+  const double rho = m[0];
+  const double dl[3] = {m[1] / rho, m[2] / rho, m[3] / rho};
+  const double U[3] = {U0[0] + dl[0], U0[1] + dl[1], U0[2] + dl[2]};
+  const double trM = m[4] + m[5] + m[6];
+  const double mdl = m[1] * dl[0] + m[2] * dl[1] + m[3] * dl[2];
+  const double eint = 0.5 * (trM - mdl) + m[13];  // rho E - rho |U|^2 / 2
+  const double Er = m[13];
+  const double rR = rho * g.R;
+  Prim p;
+  p.rho = rho;
+  p.U[0] = U[0];
+  p.U[1] = U[1];
+  p.U[2] = U[2];
+  p.T = 0.4 * eint / rR;
+  const double Ttr_bar = (2.0 / 3.0) * (eint - Er) / rR;
+  const double tau = visc(Ttr_bar, g) / (rR * Ttr_bar);
+  const double Erot = (g.Z * tau * Er + s * rR * p.T) / (g.Z * tau + s);  // Eq. 50
+  p.Trot = Erot / rR;
+  p.Ttr = (2.0 / 3.0) * (eint - Erot) / rR;
+  // heat fluxes, Eqs. 51-52
+  const double Mx[3] = {m[4] * dl[0] + m[7] * dl[1] + m[8] * dl[2], m[7] * dl[0] + m[5] * dl[1] + m[9] * dl[2],
+                        m[8] * dl[0] + m[9] * dl[1] + m[6] * dl[2]};
+  const double d2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+  const double den_tr = tau + s - (s / 3.0) * (1.0 - 1.0 / g.Z + g.omega0 / g.Z);
+  const double den_rot = tau + s - s * (1.0 - g.delta) * (1.0 - 1.0 / g.Z + g.omega1 / g.Z);
+  double q[6];
+  for (int e2 = 0; e2 < 3; ++e2) {
+    const double sq3 = m[10 + e2] - 2.0 * Mx[e2] - dl[e2] * trM + 2.0 * rho * d2 * dl[e2];
+    const double sr = m[14 + e2] - dl[e2] * m[13];
+    q[e2] = tau * 0.5 * sq3 / den_tr;
+    q[3 + e2] = tau * sr / den_rot;
+  }
+  eq_coeffs(p, q, g, ec);
+  ec[28] = tau / (tau + s);
+  ec[29] = s / (tau + s);
+}
+
 template <class T, bool UseLds>
 __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   extern __shared__ unsigned char smem_raw[];
   T* sG = reinterpret_cast<T*>(smem_raw);
   T* sR = sG + d.nv;
-  __shared__ double red[(kBlock / 64) * 2 * 6];
+  __shared__ double red[(kBlock / 64) * 6];
+  __shared__ double red17[(kBlock / 64) * 17];
   const int64_t f = blockIdx.x;
   const int64_t nv = d.nv;
   const double* fg = d.face_geo + FGW * f;
@@ -302,72 +344,54 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   double tot[6];
 
   if (bcs < 0) {
-    // pass 1: Eqs. 47-49 and sum_k w R_bar
-    acc.zero();
+    // pass 1: the moments of Eqs. 47-49 and 51-52 in one sweep, taken about a reference velocity U0 (the mean
+    // of the two cells' velocities), v = u - U0: m0 = sum w G, m = sum w v G, M = sum w v v G,
+    // T3 = sum w v|v|^2 G, r0 = sum w R, r = sum w v R.  With delta = U_f - U0 = m/m0 the sums about the face
+    // velocity follow exactly:  sum w c|c|^2 G = T3 - 2 M delta - delta tr(M) + 2 m0 |delta|^2 delta,
+    // sum w c R = r - delta r0,  and the internal energy rho E - rho|U|^2/2 = tr(M)/2 - m.delta/2 + r0.
+    const double* Wo = b.W + 6 * (int64_t)d.face_cell[2 * f];
+    const double* Wn = b.W + 6 * (int64_t)d.face_cell[2 * f + 1];
+    const double U0[3] = {0.5 * (Wo[1] / Wo[0] + Wn[1] / Wn[0]), 0.5 * (Wo[2] / Wo[0] + Wn[2] / Wn[0]),
+                          0.5 * (Wo[3] / Wo[0] + Wn[3] / Wn[0])};
+    Acc<17, false, kBlock> a17;
+    a17.zero();
     k_loop(nv, [&](int k) {
       const T gb = rowG[k], rb = rowR[k];
       if (UseLds) {
         sG[k] = gb;
         sR[k] = rb;
       }
-      const Vel v = vel(V, k);
-      double wg = v.w * (double)gb, wr = v.w * (double)rb;
-      acc.add(0, wg);
-      acc.add(1, v.ux * wg);
-      acc.add(2, v.uy * wg);
-      acc.add(3, v.uz * wg);
-      acc.add(4, v.h2 * wg + wr);
-      acc.add(5, wr);
+      const double vx = V.ux[k] - U0[0], vy = V.uy[k] - U0[1], vz = V.uz[k] - U0[2], w = V.w[k];
+      const double wg = w * (double)gb, wr = w * (double)rb;
+      const double gx = wg * vx, gy = wg * vy, gz = wg * vz, v2 = vx * vx + vy * vy + vz * vz;
+      a17.add(0, wg);
+      a17.add(1, gx);
+      a17.add(2, gy);
+      a17.add(3, gz);
+      a17.add(4, gx * vx);
+      a17.add(5, gy * vy);
+      a17.add(6, gz * vz);
+      a17.add(7, gx * vy);
+      a17.add(8, gx * vz);
+      a17.add(9, gy * vz);
+      a17.add(10, gx * v2);
+      a17.add(11, gy * v2);
+      a17.add(12, gz * v2);
+      a17.add(13, wr);
+      a17.add(14, wr * vx);
+      a17.add(15, wr * vy);
+      a17.add(16, wr * vz);
     });
-    acc.reduce(tot, red);
-    const double rho = tot[0];
-    const double U[3] = {tot[1] / rho, tot[2] / rho, tot[3] / rho};
-    const double ke = 0.5 * rho * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
-    const double E = tot[4], Er = tot[5];
-    const double rR = rho * g.R;
-    Prim p;
-    p.rho = rho;
-    p.U[0] = U[0];
-    p.U[1] = U[1];
-    p.U[2] = U[2];
-    p.T = 0.4 * (E - ke) / rR;
-    const double Ttr_bar = (2.0 / 3.0) * (E - ke - Er) / rR;
-    const double tau = visc(Ttr_bar, g) / (rR * Ttr_bar);
-    const double Erot = (g.Z * tau * Er + s * rR * p.T) / (g.Z * tau + s);  // Eq. 50
-    p.Trot = Erot / rR;
-    p.Ttr = (2.0 / 3.0) * (E - ke - Erot) / rR;
-    // pass 2: heat fluxes, Eqs. 51-52, c = u - U_f
-    acc.zero();
-    k_loop(nv, [&](int k) {
-      const T gb = UseLds ? sG[k] : rowG[k];
-      const T rb = UseLds ? sR[k] : rowR[k];
-      const Vel v = vel(V, k);
-      double cx = v.ux - U[0], cy = v.uy - U[1], cz = v.uz - U[2];
-      double c2 = cx * cx + cy * cy + cz * cz;
-      double wg = v.w * c2 * (double)gb, wr = v.w * (double)rb;
-      acc.add(0, cx * wg);
-      acc.add(1, cy * wg);
-      acc.add(2, cz * wg);
-      acc.add(3, cx * wr);
-      acc.add(4, cy * wr);
-      acc.add(5, cz * wr);
-    });
-    acc.reduce(tot, red);
-    const double den_tr = tau + s - (s / 3.0) * (1.0 - 1.0 / g.Z + g.omega0 / g.Z);
-    const double den_rot = tau + s - s * (1.0 - g.delta) * (1.0 - 1.0 / g.Z + g.omega1 / g.Z);
-    double q[6];
-    for (int m = 0; m < 3; ++m) {
-      q[m] = tau * 0.5 * tot[m] / den_tr;
-      q[3 + m] = tau * tot[3 + m] / den_rot;
-    }
-    // the face equilibrium's coefficients, computed once per face and shared through LDS
+    double m[17];
+    a17.reduce(m, red17);
+    // the face state (Eqs. 47-52) and its equilibrium coefficients, computed by one thread, shared through LDS
     __shared__ double sh_ec[ER];
-    if (threadIdx.x == 0) eq_coeffs(p, q, g, sh_ec);
+    if (threadIdx.x == 0) face_state_coeffs(m, U0, s, g, sh_ec);
     __syncthreads();
     Eq<T> e;
     e.load(sh_ec);
-    const T ct = (T)(tau / (tau + s)), cs = (T)(s / (tau + s));
-    // pass 3: phi_f (Eq. 45), micro flux and macro flux
+    const T ct = (T)sh_ec[28], cs = (T)sh_ec[29];
+    // pass 2: phi_f (Eq. 45), micro flux and macro flux
     acc.zero();
     k_loop(nv, [&](int k) {
       const T gb = UseLds ? sG[k] : rowG[k];
@@ -399,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       // rho_w from zero net mass flux through the wall
       Acc<2, false, kBlock> a2;
       a2.zero();
-      const double anorm = pow(6.283185307179586476925 * RTb, -1.5);
+      const double anorm = maxwell_norm(RTb);
       k_loop(nv, [&](int k) {
         const Vel v = vel(V, k);
         const double un = udotn(v, nx, ny, nz, d.snap);
@@ -414,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       a2.reduce(t2, red);
       rho_g = t2[0] / t2[1];
     }
-    const T amax = (T)(rho_g * pow(6.283185307179586476925 * RTb, -1.5));
+    const T amax = (T)(rho_g * maxwell_norm(RTb));
     const T bmax = (T)(1.0 / (2.0 * RTb));
     acc.zero();
     k_loop(nv, [&](int k) {
@@ -426,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
         rf = rowR[k];
       } else {
         T cx = (T)(v.ux - Ub[0]), cy = (T)(v.uy - Ub[1]), cz = (T)(v.uz - Ub[2]);
-        gf = amax * exp(-(cx * cx + cy * cy + cz * cz) * bmax);
+        gf = amax * eq_exp(-(cx * cx + cy * cy + cz * cz) * bmax);
         rf = (T)RTb * gf;
       }
       rowG[k] = (T)(A * un) * gf;
