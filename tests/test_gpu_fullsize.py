@@ -4,7 +4,14 @@
 * capsule mesh (303k tets) with a coarse DVS from the same generator: mixed path against the FP64 oracle;
 * full capsule configuration (303k tets x 10.6k velocities, 3.2e9 pairs, mixed): the result must not depend on
   the order of the discrete velocities (equivariance under a permutation of the DVS), a property that holds at
-  any size and would expose offset errors above 2^31 elements.
+  any size and would expose offset errors above 2^31 elements;
+* the VJP of the steady residual at the sphere's full size against central differences of the GPU steady
+  residual along a random direction (state and parameters): <v, R(x + e u) - R(x - e u)>/2e + cJ (J+ - J-)/2e
+  = <VJP(v, cJ), u>.  With the limiter off the residual is smooth and the two agree to 1e-9.  With it on, the
+  limiter's switching points (min over faces, extremum neighbours) crossed by the perturbation make the
+  difference quotient a poor reference (4e-3 measured at step 1e-8, falling only linearly with the step), so
+  that check only guards against gross errors; the limiter branch of the VJP is checked exactly against the
+  oracle's complex-step JVP, which follows the same branches, in test_gpu_adjoint.py.
 """
 import sys
 
@@ -99,3 +106,43 @@ def test_capsule_full_config_mixed_dvs_permutation_equivariance():
     # the same velocities in another order: equal up to FP32 summation-order rounding
     assert colrel(W2, W1) < 1e-5
     assert abs(Q2 - Q1) < 1e-5 * abs(Q1)
+
+
+def _sphere_vjp_fd(limiter, eps, tol):
+    import torch
+    from paper_2303_10846_amd.binding import Solver
+    c = configs.sphere_case(seed=0)
+    s = Solver(c, precision="fp64")
+    s.init_equilibrium(c["W0"])
+    s.iterate(20)                       # a developed, non-steady state (limiter on, as the case runs)
+    s.set_numerics(limiter=limiter)
+    gen = torch.Generator(device=s.device).manual_seed(7)
+    rnd = lambda t: torch.randn(t.shape, generator=gen, device=s.device, dtype=t.dtype)  # noqa: E731
+    v = [rnd(s.G), rnd(s.R), rnd(s.W), rnd(s.q)]
+    u = [rnd(s.G) * s.G.abs(), rnd(s.R) * s.R.abs(), rnd(s.W) * 1e-3, rnd(s.q) * 1e-4]
+    up = np.array([0.3, 0.2, 0.1])
+    cJ = 0.5
+    gG, gR, gW, gq, gp = s.residual_vjp(*v, cJ=cJ, wall_tag=1, ff_tag=2)
+    rhs = sum(float((g * du).sum()) for g, du in zip((gG, gR, gW, gq), u)) + float(gp @ up)
+    del gG, gR, gW, gq
+    x0 = [t.clone() for t in (s.G, s.R, s.W, s.q)]
+    p0 = s.params(1, 2)
+    out = []
+    for sg in (1, -1):
+        for t, b, du in zip((s.G, s.R, s.W, s.q), x0, u):
+            t.copy_(b + sg * eps * du)
+        s.set_params(p0 + sg * eps * up, 1, 2)
+        rG, rR, rW, rq, J = s.steady_residual(1)
+        out.append((sum(float((vv * r).sum()) for vv, r in zip(v, (rG, rR, rW, rq))), J))
+        del rG, rR, rW, rq
+    lhs = (out[0][0] - out[1][0]) / (2 * eps) + cJ * (out[0][1] - out[1][1]) / (2 * eps)
+    say(f"limiter {limiter}: lhs {lhs:.12e} rhs {rhs:.12e} rel {abs(lhs - rhs) / abs(rhs):.3e}")
+    assert abs(lhs - rhs) <= tol * abs(rhs)
+
+
+def test_sphere_full_size_vjp_smooth_residual():
+    _sphere_vjp_fd(limiter=0, eps=1e-6, tol=1e-8)
+
+
+def test_sphere_full_size_vjp_limited_residual():
+    _sphere_vjp_fd(limiter=1, eps=1e-8, tol=2e-2)
