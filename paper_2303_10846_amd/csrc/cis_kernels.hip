@@ -115,11 +115,17 @@ void launch_init_eq(const Dev& d, const Bufs& b, const double* W0, int per_cell,
 // Workgroup (cell, velocity chunk); each (face, velocity) value phi_bar is written once, by its upwind cell.
 // ---------------------------------------------------------------------------
 
-// One distribution at one velocity: limited least-squares gradient of the cell and the upwind face values.
+// Division in the limiter function: exact in FP64; in FP32 the fast reciprocal form (a few ulp on a value that
+// only scales a slope).
+__device__ inline double lim_div(double a, double b) { return a / b; }
+__device__ inline float lim_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// One distribution at one velocity: limited least-squares gradient of the cell and the upwind face values
+// (written at dst + frow[a] + k).
 template <class T>
 __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const T* wx, const T* wy, const T* wz,
                                    const T* fx, const T* fy, const T* fz, const T* sf, T kh3, int limiter,
-                                   const bool* up, T ux, T uy, T uz, T* const* dst, int k) {
+                                   const bool* up, T ux, T uy, T uz, T* dst, const int64_t* frow, int k) {
   T gx = 0, gy = 0, gz = 0, pmax = phi, pmin = phi;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -140,7 +146,7 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
       const T d2 = gx * fx[a] + gy * fy[a] + gz * fz[a];
       if (d2 != T(0)) {
         const T d1 = d2 > T(0) ? pmax - phi : pmin - phi;
-        const T psi = ((d1 * d1 + eps2) * d2 + T(2) * d2 * d2 * d1) / (d2 * (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2));
+        const T psi = lim_div((d1 * d1 + eps2) * d2 + T(2) * d2 * d2 * d1, d2 * (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2));
         L = psi < L ? psi : L;
       }
     }
@@ -151,7 +157,7 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     if (!up[a]) continue;
-    dst[a][k] = phi + (fx[a] - ux * sf[a]) * gx + (fy[a] - uy * sf[a]) * gy + (fz[a] - uz * sf[a]) * gz;
+    dst[frow[a] + k] = phi + (fx[a] - ux * sf[a]) * gx + (fy[a] - uy * sf[a]) * gy + (fz[a] - uz * sf[a]) * gz;
   }
 }
 
@@ -166,21 +172,18 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   const double* geo = d.cell_geo + CG * i;
   const T* G = (const T*)b.G;
   const T* R = (const T*)b.R;
+  T* FG = (T*)b.faceG;
+  T* FR = (T*)b.faceR;
   int32_t nb[4];
-  const T *sG[4], *sR[4];
-  T *dG[4], *dR[4];
+  int64_t srow[4], frow[4];  // element offsets of the neighbour rows and the face rows (shared by G and R)
   double nx[4], ny[4], nz[4];
   bool own[4];
   T wx[4], wy[4], wz[4], fx[4], fy[4], fz[4], sf[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     nb[a] = d.cell_nb[4 * i + a];
-    const int64_t f = d.cell_face[4 * i + a];
-    const int64_t src = nb[a] >= 0 ? nb[a] : i;
-    sG[a] = G + src * nv;
-    sR[a] = R + src * nv;
-    dG[a] = (T*)b.faceG + f * nv;
-    dR[a] = (T*)b.faceR + f * nv;
+    srow[a] = (int64_t)(nb[a] >= 0 ? nb[a] : i) * nv;
+    frow[a] = (int64_t)d.cell_face[4 * i + a] * nv;
     const double* s = geo + CG_FACE + CG_SLOT * a;
     own[a] = s[0] > 0.0;
     nx[a] = s[2];
@@ -199,12 +202,12 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   const T kh3 = (T)kh3d;
   const int limiter = d.limiter;
   const double snap = d.snap;
-  const T* selfG = G + i * nv;
-  const T* selfR = R + i * nv;
+  const int64_t self = i * nv;
   const int nvi = (int)nv;
   const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
-  T pG[U], pR[U], nG[U][4], nR[U][4];
+  T pG[U], pR[U], nG[U][4], nR[U][4], tx[U], ty[U], tz[U];
   double ux[U], uy[U], uz[U], um[U];
+  bool up[U][4];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = k0 + u * kBlock;
@@ -213,29 +216,35 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
     uy[u] = d.dvs[nv + k];
     uz[u] = d.dvs[2 * nv + k];
     um[u] = d.dvs[4 * nv + k];
-    pG[u] = selfG[k];
-    pR[u] = selfR[k];
+    pG[u] = G[self + k];
+    pR[u] = R[self + k];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      nG[u][a] = sG[a][k];
-      nR[u][a] = sR[a][k];
+      nG[u][a] = G[srow[a] + k];
+      nR[u][a] = R[srow[a] + k];
     }
   }
+  // upwind decisions first, so that the FP64 normals are dead during the arithmetic below
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int k = k0 + u * kBlock;
-    if (k >= nvi) continue;
-    bool up[4];
+    if (k0 + u * kBlock >= nvi) continue;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       double un = ux[u] * nx[a] + uy[u] * ny[a] + uz[u] * nz[a];
       un = fabs(un) <= snap * um[u] ? 0.0 : un;
       // upwind cell of the face for this velocity: the owner when u.n_face > 0, else the neighbour
-      up[a] = nb[a] >= 0 ? (own[a] ? un > 0.0 : un >= 0.0) : un > 0.0;
+      up[u][a] = nb[a] >= 0 ? (own[a] ? un > 0.0 : un >= 0.0) : un > 0.0;
     }
-    const T tx = (T)ux[u], ty = (T)uy[u], tz = (T)uz[u];
-    recon_write<T>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up, tx, ty, tz, dG, k);
-    recon_write<T>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up, tx, ty, tz, dR, k);
+    tx[u] = (T)ux[u];
+    ty[u] = (T)uy[u];
+    tz[u] = (T)uz[u];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * kBlock;
+    if (k >= nvi) continue;
+    recon_write<T>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FG, frow, k);
+    recon_write<T>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FR, frow, k);
   }
 }
 
@@ -550,45 +559,52 @@ __global__ __launch_bounds__(kBlock) void k_macro_prep(Dev d, const double* W, W
   w.mres[6 * i + 5] += (pa[0] * g.R * pa[4] - W[6 * i + 5]) / (g.Z * tau);
 }
 
-// One point relaxation of Eq. 43 at cell i (matrix-free increment G(W_j + dW_j) - G(W_j)).
-__device__ inline void macro_relax(const Dev& d, const double* W, const Work& w, int64_t i) {
-  const double* geo = d.cell_geo + CG * i;
-  double acc[6];
-  for (int m = 0; m < 6; ++m) acc[m] = w.mres[6 * i + m];
-  // issue every neighbour load before any arithmetic: the sweep is latency bound
-  int32_t nb[4];
-  double Wj[4][6], dWj[4][6];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) nb[a] = d.cell_nb[4 * i + a];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t j = nb[a] >= 0 ? nb[a] : i;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      Wj[a][m] = W[6 * j + m];
-      dWj[a][m] = w.dW[6 * j + m];
+// One point relaxation of Eq. 43 per cell of one colour (matrix-free increment G(W_j + dW_j) - G(W_j)).  The
+// sweep is latency bound: the four faces of a cell run on four consecutive lanes (each loads one neighbour
+// and evaluates one flux increment), and the cell's first lane subtracts the four terms in face order.  A
+// colour is ~N_c/5 cells, so small workgroups spread each launch over more CUs.
+constexpr int kMacroBlock = 64;
+
+__global__ __launch_bounds__(kMacroBlock) void k_macro_sweep(Dev d, const double* W, Work w, int64_t c0, int64_t c1) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = c0 + (t >> 2);
+  const int a = (int)(t & 3);
+  const bool valid = i < c1;
+  double term[6] = {0, 0, 0, 0, 0, 0};
+  if (valid) {
+    const int32_t nb = d.cell_nb[4 * i + a];
+    if (nb >= 0) {
+      const double* s = d.cell_geo + CG * i + CG_FACE + CG_SLOT * a;
+      double Wp[6], dWj[6], G1[6];
+      for (int m = 0; m < 6; ++m) {
+        dWj[m] = w.dW[6 * (int64_t)nb + m];
+        Wp[m] = W[6 * (int64_t)nb + m] + dWj[m];
+      }
+      euler_flux(Wp, s[2], s[3], s[4], G1);
+      const double* G0 = w.G0 + 24 * i + 6 * a;
+      const double r = w.rcf[4 * i + a];
+      for (int m = 0; m < 6; ++m) term[m] = 0.5 * s[1] * ((G1[m] - G0[m]) - r * dWj[m]);
     }
   }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    if (nb[a] < 0) continue;
-    const double* s = geo + CG_FACE + CG_SLOT * a;
-    double Wp[6], G1[6];
-    for (int m = 0; m < 6; ++m) Wp[m] = Wj[a][m] + dWj[a][m];
-    euler_flux(Wp, s[2], s[3], s[4], G1);
-    const double* G0 = w.G0 + 24 * i + 6 * a;
-    double r = w.rcf[4 * i + a];
-    for (int m = 0; m < 6; ++m) acc[m] -= 0.5 * s[1] * ((G1[m] - G0[m]) - r * dWj[a][m]);
+  double t1[6], t2[6], t3[6];
+  const int lane = threadIdx.x & 63;
+  for (int m = 0; m < 6; ++m) {
+    t1[m] = __shfl(term[m], lane + 1, 64);
+    t2[m] = __shfl(term[m], lane + 2, 64);
+    t3[m] = __shfl(term[m], lane + 3, 64);
   }
-  double D = w.mD[2 * i], D5 = w.mD[2 * i + 1];
+  if (!valid || a != 0) return;
+  double acc[6];
+  for (int m = 0; m < 6; ++m) acc[m] = w.mres[6 * i + m];
+  for (int m = 0; m < 6; ++m) {
+    acc[m] -= term[m];
+    acc[m] -= t1[m];
+    acc[m] -= t2[m];
+    acc[m] -= t3[m];
+  }
+  const double D = w.mD[2 * i], D5 = w.mD[2 * i + 1];
   for (int m = 0; m < 5; ++m) w.dW[6 * i + m] = acc[m] / D;
   w.dW[6 * i + 5] = acc[5] / D5;
-}
-
-__global__ __launch_bounds__(kBlock) void k_macro_sweep(Dev d, const double* W, Work w, int64_t c0, int64_t c1) {
-  int64_t i = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c1) return;
-  macro_relax(d, W, w, i);
 }
 
 // W~ = W^n + dW~; predicted equilibrium coefficients with q~ = q^n
@@ -649,8 +665,8 @@ void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
   hipLaunchKernelGGL(k_macro_prep, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, w);
   for (const int64_t c : sweep_sequence(color_off, n_colors, n_macro)) {
     const int64_t n = color_off[c + 1] - color_off[c];
-    hipLaunchKernelGGL(k_macro_sweep, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d,
-                       (const double*)b.W, w, color_off[c], color_off[c + 1]);
+    hipLaunchKernelGGL(k_macro_sweep, dim3((unsigned)((4 * n + kMacroBlock - 1) / kMacroBlock)), dim3(kMacroBlock), 0,
+                       st, d, (const double*)b.W, w, color_off[c], color_off[c + 1]);
   }
   hipLaunchKernelGGL(k_cell_eq, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, (const double*)b.q, w);
 }
