@@ -25,15 +25,18 @@ __device__ inline int64_t xcd_block(int64_t w, int64_t n) {
 // Reductions over a workgroup of NT threads (NT/64 wave64 wavefronts)
 // ---------------------------------------------------------------------------
 
+// s + x with its exact rounding error added to c (Knuth's branch-free TwoSum)
 __device__ inline void two_sum_add(double& s, double& c, double x) {
-  double t = s + x;
-  c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+  const double t = s + x;
+  const double z = t - s;
+  c += (s - (t - z)) + (x - z);
   s = t;
 }
 
-// N running FP64 sums per thread.  With Comp, every thread's running sum is Neumaier-compensated (the long
-// sequential part of the summation); the 64 lanes of a wavefront are combined by a pairwise shuffle tree
-// (error O(log2(64) eps)) and the wavefronts' results again with Neumaier compensation.  Without Comp the
+// N running FP64 sums per thread.  With Comp, every thread's running sum is compensated: the exact rounding
+// error of each addition (TwoSum) is accumulated beside it, over the long sequential part of the summation;
+// the 64 lanes of a wavefront are combined by a pairwise shuffle tree (error O(log2(64) eps)) and the
+// wavefronts' results again with compensation.  Without Comp the
 // running sums and the merge are plain FP64.
 template <int N, bool Comp, int NT> struct Acc {
   static constexpr int NW = NT / 64;
@@ -74,6 +77,33 @@ template <int N, bool Comp, int NT> struct Acc {
         }
       }
       out[m] = Comp ? a + b : a;
+    }
+    __syncthreads();
+  }
+  // The same totals written to LDS by thread 0 only (sh_out: N doubles), for a block that hands them to one
+  // thread: the totals are then not live in every thread's registers.
+  __device__ inline void reduce_to_lds(double* sh_out, double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      double a = Comp ? s[m] + c[m] : s[m];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      if (lane == 0) red[wid * N + m] = a;
+      __builtin_amdgcn_sched_barrier(0);  // one chain at a time: keeps the register peak low
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+      const int m = threadIdx.x;
+      double a = red[m], b = 0.0;
+      for (int q = 1; q < NW; ++q) {
+        if (Comp) {
+          two_sum_add(a, b, red[q * N + m]);
+        } else {
+          a += red[q * N + m];
+        }
+      }
+      sh_out[m] = Comp ? a + b : a;
     }
     __syncthreads();
   }

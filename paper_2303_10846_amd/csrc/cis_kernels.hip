@@ -10,7 +10,7 @@
 // velocity set of one face or cell (face pass, update) run one workgroup per
 // face or cell.  DVS moment sums are FP64: per-thread running sums, a pairwise
 // shuffle tree per wavefront, and a merge of the wavefronts; in the mixed mode
-// the sums of the conservative update are Neumaier-compensated.  The coloured
+// the sums of the conservative update are compensated (TwoSum error terms).  The coloured
 // Gauss-Seidel sweeps update one colour at a time: cells of one colour share no
 // face.  Nothing here is a dense contraction; the kernels are bound by HBM
 // bandwidth, latency and (face pass) vector ALU, not MFMA.
@@ -263,7 +263,7 @@ template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st
 // ---------------------------------------------------------------------------
 
 #ifndef CIS_UNROLL
-#define CIS_UNROLL 4
+#define CIS_UNROLL 2
 #endif
 constexpr int kUnroll = CIS_UNROLL;
 
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   const GasC& g = d.gas;
   const DvsRows V = dvs_rows(d);
   Acc<6, false, kBlock> acc;
-  double tot[6];
+  __shared__ double tot[6];
 
   if (bcs < 0) {
     // pass 1: the moments of Eqs. 47-49 and 51-52 in one sweep, taken about a reference velocity U0 (the mean
@@ -391,11 +391,11 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       a17.add(15, wr * vy);
       a17.add(16, wr * vz);
     });
-    double m[17];
-    a17.reduce(m, red17);
+    __shared__ double sh_m[17];
+    a17.reduce_to_lds(sh_m, red17);
     // the face state (Eqs. 47-52) and its equilibrium coefficients, computed by one thread, shared through LDS
     __shared__ double sh_ec[ER];
-    if (threadIdx.x == 0) face_state_coeffs(m, U0, s, g, sh_ec);
+    if (threadIdx.x == 0) face_state_coeffs(sh_m, U0, s, g, sh_ec);
     __syncthreads();
     Eq<T> e;
     e.load(sh_ec);
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       acc.add(4, v.h2 * wg + wr);
       acc.add(5, wr);
     });
-    acc.reduce(tot, red);
+    acc.reduce_to_lds(tot, red);
   } else {
     const double* bc = d.bc + BCW * bcs;
     const bool wall = bc[0] == 1.0;
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       acc.add(4, v.h2 * wg + wr);
       acc.add(5, wr);
     });
-    acc.reduce(tot, red);
+    acc.reduce_to_lds(tot, red);
   }
   if (threadIdx.x < 6) w.face_mac[6 * f + threadIdx.x] = A * tot[threadIdx.x];
 }
@@ -932,8 +932,8 @@ template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update
     acc.add(10, cy * wr);
     acc.add(11, cz * wr);
   });
-  double s[12];
-  acc.reduce(s, red);
+  __shared__ double s[12];
+  acc.reduce_to_lds(s, red);
   if (threadIdx.x == 0) {
     const GasC& gg = d.gas;
     const double* Wt = w.Wt + 6 * i;
