@@ -163,6 +163,27 @@ cis_status cis_moments(cis_state* s, double* W, double* q);
    n pointing from the fluid into the wall (Eq. 72 numerator). */
 cis_status cis_wall_heat_flux(cis_state* s, int32_t tag, double* Q);
 
+/* Loads on the faces of one wall, from the face distributions of the current state (Sec. 4, Eqs. 70-72).
+   n points from the gas into the wall.  Per face:
+     p   = sum_k w (u.n)^2 G_w                    the Eq. 70 numerator before p_inf is subtracted;
+     tau = sum_k w (u.n) u G_w - n p               the Eq. 71 numerator, as a vector (|tau| is the shear);
+     q   = sum_k w (u.n)(|u|^2/2 G_w + R_w)        the Eq. 72 numerator.
+   The force on the wall is sum_f A_f (p n + tau) and its heat load sum_f A_f q.  Divide by the free-stream
+   references to get C_p, C_tau, C_h and force coefficients. */
+typedef struct {
+  double x[3];   /* face centroid */
+  double area;
+  double n[3];   /* unit normal, gas -> wall */
+  double p;
+  double tau[3];
+  double q;
+} cis_wall_face;
+
+/* faces (host, [*n_faces], or NULL) receives the faces of `tag` in face order; *n_faces (or NULL) their count.
+   force (host [3], or NULL) and heat (host, or NULL) receive the integrated loads. */
+cis_status cis_wall_loads(cis_state* s, int32_t tag, int64_t* n_faces, cis_wall_face* faces, double* force,
+                          double* heat);
+
 /* Small internal arrays of the last iteration, copied to host (for stage-by-stage checks):
    which = 0: dW~ [n_cells][6] (Eq. 43 solution), 1: W~ [n_cells][6], 2: macro flux F [n_cells][6] (Eq. 37),
    3: tau~ [n_cells]. */

@@ -27,7 +27,7 @@ EXPORTS = [
     "cis_state_required_bytes", "cis_state_create", "cis_state_set_numerics", "cis_state_destroy",
     "cis_state_init_equilibrium", "cis_state_set", "cis_state_get", "cis_iterate", "cis_residual", "cis_moments",
     "cis_wall_heat_flux", "cis_debug_stage", "cis_profile_enable", "cis_profile_read", "cis_state_set_bc",
-    "cis_steady_residual", "cis_residual_vjp", "cis_adjoint_required_bytes", "cis_adjoint_solve",
+    "cis_steady_residual", "cis_residual_vjp", "cis_adjoint_required_bytes", "cis_adjoint_solve", "cis_wall_loads",
 ]
 STAGE_NAMES = ["recon", "face", "macro", "residual", "micro", "update"]
 
@@ -64,6 +64,11 @@ class BufferSizes(C.Structure):
 
 class AdjointInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double)]
+
+
+class WallFace(C.Structure):
+    _fields_ = [("x", C.c_double * 3), ("area", C.c_double), ("n", C.c_double * 3), ("p", C.c_double),
+                ("tau", C.c_double * 3), ("q", C.c_double)]
 
 
 class DeviceBuffers(C.Structure):
@@ -136,6 +141,8 @@ def load(allow_build: bool = True):
     lib.cis_profile_enable.argtypes = [P, C.c_int32]
     lib.cis_profile_read.restype = st
     lib.cis_profile_read.argtypes = [P, d, i64]
+    lib.cis_wall_loads.restype = st
+    lib.cis_wall_loads.argtypes = [P, C.c_int32, i64, P, d, d]
     lib.cis_state_set_bc.restype = st
     lib.cis_state_set_bc.argtypes = [P, C.POINTER(Bc), C.c_int32]
     lib.cis_steady_residual.restype = st
@@ -326,6 +333,18 @@ class Solver:
         _check(self.lib.cis_wall_heat_flux(self.h, int(tag), C.byref(Q)))
         return Q.value
 
+    def wall_loads(self, tag: int) -> dict:
+        """Per-face wall loads of `tag` (Eqs. 70-72 numerators) and the integrated force and heat load."""
+        n = C.c_int64(0)
+        _check(self.lib.cis_wall_loads(self.h, int(tag), C.byref(n), None, None, None))
+        arr = (WallFace * max(n.value, 1))()
+        F = np.zeros(3)
+        Q = C.c_double(0.0)
+        _check(self.lib.cis_wall_loads(self.h, int(tag), C.byref(n), C.cast(arr, C.c_void_p), _dp(F), C.byref(Q)))
+        rec = np.ctypeslib.as_array(C.cast(arr, C.POINTER(C.c_double)), shape=(max(n.value, 1), 12))[: n.value].copy()
+        return dict(x=rec[:, 0:3], area=rec[:, 3], n=rec[:, 4:7], p=rec[:, 7], tau=rec[:, 8:11], q=rec[:, 11],
+                    force=F, heat=Q.value)
+
     def profile(self, enable: bool = True):
         """Enable (and reset) per-stage hipEvent timing of iterate()."""
         _check(self.lib.cis_profile_enable(self.h, 1 if enable else 0))
@@ -469,3 +488,18 @@ def steady_residual_fn(solver, wall_tag, ff_tag, p, G, R, W, q):
     if _SR is None:
         _SR = _steady_residual_function()
     return _SR.apply(solver, wall_tag, ff_tag, p, G, R, W, q)
+
+
+def wall_coefficients(loads: dict, rho_inf: float, U_inf, T_inf: float, R: float = 0.5, A_ref: float = None) -> dict:
+    """C_p, C_tau, C_h per wall face (Eqs. 70-72) from Solver.wall_loads, and, with a reference area, the force
+    coefficients along U_inf (drag) and the heat-load coefficient."""
+    U = np.asarray(U_inf, dtype=float)
+    Um = float(np.linalg.norm(U))
+    qd = 0.5 * rho_inf * Um * Um
+    out = dict(Cp=(loads["p"] - rho_inf * R * T_inf) / qd, Ctau=np.linalg.norm(loads["tau"], axis=1) / qd,
+               Ch=loads["q"] / (qd * Um))
+    if A_ref:
+        out["CF"] = loads["force"] / (qd * A_ref)
+        out["Cd"] = float(loads["force"] @ U / Um) / (qd * A_ref)
+        out["CQ"] = loads["heat"] / (qd * Um * A_ref)
+    return out

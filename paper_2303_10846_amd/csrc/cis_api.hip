@@ -792,6 +792,51 @@ cis_status cis_wall_heat_flux(cis_state* s, int32_t tag, double* Q) {
   return CIS_OK;
 }
 
+cis_status cis_wall_loads(cis_state* s, int32_t tag, int64_t* n_faces, cis_wall_face* faces, double* force,
+                          double* heat) {
+  if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
+  const cis_mesh* m = s->mesh;
+  cis_status st = dispatch(s, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_recon<T>(s->dev, s->buf, s->stream);
+    launch_face<T>(s->dev, s->buf, s->work, s->stream);
+    return device_check("wall_loads");
+  });
+  if (st != CIS_OK) return st;
+  std::vector<double> fm(6 * m->nf);
+  HIP_TRY(hipMemcpyAsync(fm.data(), s->work.face_mac, fm.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  int64_t cnt = 0;
+  double F[3] = {0.0, 0.0, 0.0}, Q = 0.0;
+  for (int64_t f = 0; f < m->nf; ++f) {
+    if (m->face_cell[2 * f + 1] >= 0 || m->face_tag[f] != tag) continue;
+    const double A = m->fA[f];
+    const double* n = &m->fn[3 * f];
+    const double* mac = &fm[6 * f];  // A sum_k w (u.n) (G, u G, |u|^2/2 G + R, R)
+    const double mom[3] = {mac[1] / A, mac[2] / A, mac[3] / A};
+    const double p = mom[0] * n[0] + mom[1] * n[1] + mom[2] * n[2];
+    if (faces) {
+      cis_wall_face& o = faces[cnt];
+      for (int d = 0; d < 3; ++d) {
+        o.x[d] = m->xf[3 * f + d];
+        o.n[d] = n[d];
+        o.tau[d] = mom[d] - p * n[d];
+      }
+      o.area = A;
+      o.p = p;
+      o.q = mac[4] / A;
+    }
+    for (int d = 0; d < 3; ++d) F[d] += mac[1 + d];
+    Q += mac[4];
+    ++cnt;
+  }
+  if (n_faces) *n_faces = cnt;
+  if (force)
+    for (int d = 0; d < 3; ++d) force[d] = F[d];
+  if (heat) *heat = Q;
+  return CIS_OK;
+}
+
 cis_status cis_profile_enable(cis_state* s, int32_t enable) {
   if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
   s->profile = enable != 0;

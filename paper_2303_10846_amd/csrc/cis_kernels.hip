@@ -115,6 +115,11 @@ void launch_init_eq(const Dev& d, const Bufs& b, const double* W0, int per_cell,
 // Workgroup (cell, velocity chunk); each (face, velocity) value phi_bar is written once, by its upwind cell.
 // ---------------------------------------------------------------------------
 
+// Stores of write-once streams (phi_bar of the reconstruction, Res, phi^{n+1}) are non-temporal, so that they
+// do not push the row slices the same kernel re-reads out of the caches (measured: reconstruction and micro
+// residual faster; the face kernel's flux rows are better stored normally).
+template <class T> __device__ inline void st_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
 // Division in the limiter function: exact in FP64; in FP32 the fast reciprocal form (a few ulp on a value that
 // only scales a slope).
 __device__ inline double lim_div(double a, double b) { return a / b; }
@@ -157,7 +162,7 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     if (!up[a]) continue;
-    dst[frow[a] + k] = phi + (fx[a] - ux * sf[a]) * gx + (fy[a] - uy * sf[a]) * gy + (fz[a] - uz * sf[a]) * gz;
+    st_stream(dst + frow[a] + k, phi + (fx[a] - ux * sf[a]) * gx + (fy[a] - uy * sf[a]) * gy + (fz[a] - uz * sf[a]) * gz);
   }
 }
 
@@ -746,8 +751,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
     const T FR = sg[0] * xR[u][0] + sg[1] * xR[u][1] + sg[2] * xR[u][2] + sg[3] * xR[u][3];
     T gs, rs;
     e.eval(ux[u], uy[u], uz[u], gs, rs);
-    oG[k] = (gs - pG[u]) * itau - FG;
-    oR[k] = (rs - pR[u]) * itau - FR;
+    st_stream(oG + k, (gs - pG[u]) * itau - FG);
+    st_stream(oR + k, (rs - pR[u]) * itau - FR);
   }
 }
 
@@ -909,8 +914,8 @@ template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update
   k_loop(nv, [&](int k) {
     const T g = G[k] + dG[k];
     const T r = R[k] + dR[k];
-    G[k] = g;
-    R[k] = r;
+    st_stream(G + k, g);
+    st_stream(R + k, r);
     const Vel v = vel(V, k);
     T gs, rs;
     e.eval((T)v.ux, (T)v.uy, (T)v.uz, gs, rs);

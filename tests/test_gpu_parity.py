@@ -203,3 +203,33 @@ def test_mixed_precision_cavity_converged_fields():
     eq = abs(s.wall_heat_flux(2) - o.wall_heat_flux(2)) / abs(o.wall_heat_flux(2))
     say(f"mixed vs FP64 oracle: rho {er:.2e} T {eT:.2e} Q_lid {eq:.2e}; final residual {h[-1].max():.2e}")
     assert er < 1e-5 and eT < 1e-5 and eq < 1e-5
+
+
+def test_wall_loads_match_oracle_face_fluxes():
+    """Per-face pressure, shear and heat flux (Eqs. 70-72 numerators) and the integrated force and heat load on
+    the sphere wall, against the oracle's face macro fluxes on the same state."""
+    say("case small_sphere wall loads")
+    c = configs.small_sphere_case()
+    o, s = _pair(c, warm=4)
+    o.explicit()
+    g = o.geometry()
+    fm = o.stage("ffmac").reshape(-1, 6)
+    n = g["n"].reshape(-1, 3)
+    wall = (g["fn"] < 0) & (g["ftag"] == 1)
+    A = g["A"][wall]
+    mom = fm[wall, 1:4] / A[:, None]
+    p = np.einsum("ij,ij->i", mom, n[wall])
+    tau = mom - p[:, None] * n[wall]
+    q = fm[wall, 4] / A
+    L = s.wall_loads(1)
+    assert len(L["p"]) == int(wall.sum())
+    assert nrel(L["p"], p) < TOL
+    assert nrel(L["tau"], tau) < TOL
+    assert nrel(L["q"], q) < TOL
+    assert nrel(L["force"], fm[wall, 1:4].sum(axis=0)) < TOL
+    assert abs(L["heat"] - fm[wall, 4].sum()) <= TOL * abs(fm[wall, 4].sum())
+    assert abs(L["heat"] - s.wall_heat_flux(1)) <= 1e-14 * abs(L["heat"])
+    from paper_2303_10846_amd.binding import wall_coefficients
+    cf = wall_coefficients(L, 1.0, c["U_inf"], 1.0, A_ref=0.25 * np.pi)
+    say(f"Cd {cf['Cd']:.4f}  CQ {cf['CQ']:.4f}  Cp max {cf['Cp'].max():.3f}")
+    assert np.all(np.isfinite(cf["Cp"])) and cf["Cd"] > 0.0

@@ -547,3 +547,29 @@ def test_p11_complex_step_gradient_matches_fd_of_converged_heat_flux():
             Js.append(ob.steady_residual(1)[4])
         fd = (Js[0] - Js[1]) / (2 * h)
         assert abs(dJ - fd) < 1e-6 * max(abs(fd), abs(J0) * 1e-3), (param, dJ, fd)
+
+
+def test_wall_loads_of_gas_at_rest_are_its_pressure():
+    """Eqs. 70-72 on a closed diffuse box of gas at rest at the wall temperature: the normal momentum flux
+    sum_k w (u.n)^2 G_w is the textbook pressure rho R T on every wall face, the shear and the heat flux
+    vanish, and so does the net force (Gauss-Hermite velocities: the Maxwellian moments are exact)."""
+    c = configs.cavity_case(n=2, lid_speed=0.0)
+    u, w = dvs.gauss_hermite_dvs(6, np.zeros(3), 1.0)
+    c["u"], c["w"] = u, w
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.explicit()
+    g = o.geometry()
+    fm = o.stage("ffmac").reshape(-1, 6)
+    n = g["n"].reshape(-1, 3)
+    wall = g["fn"] < 0
+    A = g["A"][wall]
+    mom = fm[wall, 1:4] / A[:, None]
+    p = np.einsum("ij,ij->i", mom, n[wall])
+    tau = mom - p[:, None] * n[wall]
+    q = fm[wall, 4] / A
+    rho, T = c["W0"][0], 1.0
+    assert np.max(np.abs(p - rho * R_GAS * T)) < 1e-13
+    assert np.max(np.abs(tau)) < 1e-13
+    assert np.max(np.abs(q)) < 1e-13
+    assert np.max(np.abs(fm[wall, 1:4].sum(axis=0))) < 1e-13
