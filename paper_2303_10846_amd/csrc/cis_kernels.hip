@@ -877,10 +877,24 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, i
   micro_store<T, U>(c, in, k, nvi);
 }
 
+template <class T> __global__ __launch_bounds__(kBlock) void k_zero(T* a, T* b, int64_t n) {
+  for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n; x += (int64_t)gridDim.x * kBlock) {
+    a[x] = T(0);
+    b[x] = T(0);
+  }
+}
+
 template <class T>
 void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_micro,
                   hipStream_t st) {
   const std::vector<int64_t> seq = sweep_sequence(color_off, n_colors, n_micro);
+  if (seq.empty()) {
+    // no sweep: the increments of Eq. 33 stay zero
+    const int64_t n = d.nc * d.nv;
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 65536));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nb), dim3(kBlock), 0, st, (T*)b.dG, (T*)b.dR, n);
+    return;
+  }
   int64_t nonempty = 0;
   for (int64_t c = 0; c < n_colors; ++c) nonempty += color_off[c + 1] > color_off[c];
   for (size_t p = 0; p < seq.size(); ++p) {

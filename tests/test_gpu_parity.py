@@ -239,3 +239,17 @@ def test_wall_loads_match_oracle_face_fluxes():
     cf = wall_coefficients(L, 1.0, c["U_inf"], 1.0, A_ref=0.25 * np.pi)
     say(f"Cd {cf['Cd']:.4f}  CQ {cf['CQ']:.4f}  Cp max {cf['Cp'].max():.3f}")
     assert np.all(np.isfinite(cf["Cp"])) and cf["Cd"] > 0.0
+
+
+def test_no_micro_sweeps_means_zero_increments():
+    """n_micro = 0: Eq. 33 is not swept, the increments are zero and the update keeps phi^n (stage-by-stage)."""
+    say("case cavity n_micro 0")
+    c = configs.cavity_case(n=2, nv_side=4)
+    num = dict(c["num"], n_micro=0)
+    o, s = _pair(c, warm=2, num=num)
+    o.iterate(1)
+    s.iterate(1)
+    Go, Ro, Wo, qo = o.get_state()
+    Gs, Rs, Ws, qs = s.get_state()
+    assert nrel(Gs, Go) < TOL and nrel(Rs, Ro) < TOL
+    assert colrel(Ws, Wo) < TOL and colrel(qs, qo) < TOL
