@@ -74,6 +74,7 @@ __global__ void k_zero_i32(int32_t* p, int n) {
 struct cis_mesh {
   int64_t nc = 0, nf = 0, n_int = 0, n_b = 0, n_colors = 0;
   std::vector<int64_t> color_off;
+  std::vector<int32_t> spatial;  // cells in Morton order of their centroids (traversal order off the sweeps)
   std::vector<int32_t> cell_nb, cell_face, face_cell, face_tag;
   std::vector<double> V, h, xc, xf, fA, fn;  // cells: V, h, centroid; faces: centroid, area, unit normal
 };
@@ -96,7 +97,8 @@ struct cis_state {
   Bufs buf{};
   Work work{};
   // library-owned device arrays
-  int32_t *d_cell_nb = nullptr, *d_cell_face = nullptr, *d_face_cell = nullptr, *d_face_bc = nullptr;
+  int32_t *d_cell_nb = nullptr, *d_cell_face = nullptr, *d_face_cell = nullptr, *d_face_bc = nullptr,
+          *d_spatial = nullptr;
   double *d_cell_geo = nullptr, *d_face_geo = nullptr, *d_dvs = nullptr, *d_bc = nullptr;
   float* d_dvs_f = nullptr;
   int64_t res_cap = 0;
@@ -274,6 +276,30 @@ cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* te
       return fail(CIS_E_MESH, "cell " + std::to_string(i) + " has zero volume");
     }
     for (int d = 0; d < 3; ++d) m->xc[3 * i + d] = 0.25 * (p0[d] + p1[d] + p2[d] + p3[d]);
+  }
+  // Morton order of the centroids: kernels that read face neighbours walk the cells in this order, so that
+  // neighbouring rows are read close together in time (the colour-major numbering puts every face neighbour
+  // of a cell in another colour block)
+  {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n_cells; ++i)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = std::min(lo[d], m->xc[3 * i + d]);
+        hi[d] = std::max(hi[d], m->xc[3 * i + d]);
+      }
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)n_cells);
+    for (int64_t i = 0; i < n_cells; ++i) {
+      uint64_t code = 0;
+      for (int d = 0; d < 3; ++d) {
+        const double t = hi[d] > lo[d] ? (m->xc[3 * i + d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
+        const uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097152.0));
+        for (int b = 0; b < 21; ++b) code |= ((q >> b) & 1ull) << (3 * b + d);
+      }
+      key[(size_t)i] = {code, (int32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    m->spatial.resize((size_t)n_cells);
+    for (int64_t i = 0; i < n_cells; ++i) m->spatial[(size_t)i] = key[(size_t)i].second;
   }
   // faces (face a of a tet is opposite its local vertex a)
   std::unordered_map<TriKey, int64_t, TriHash> seen;
@@ -563,6 +589,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
     if (e == CIS_OK) e = x;
   };
   chk(own_upload(s, &s->d_cell_nb, m->cell_nb));
+  chk(own_upload(s, &s->d_spatial, m->spatial));
   chk(own_upload(s, &s->d_cell_face, m->cell_face));
   chk(own_upload(s, &s->d_face_cell, m->face_cell));
   chk(own_upload(s, &s->d_face_bc, face_bc));
@@ -601,6 +628,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   d.nf = nf;
   d.nv = nv;
   d.cell_nb = s->d_cell_nb;
+  d.spatial = s->d_spatial;
   d.cell_face = s->d_cell_face;
   d.cell_geo = s->d_cell_geo;
   d.face_cell = s->d_face_cell;

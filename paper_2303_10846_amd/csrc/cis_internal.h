@@ -48,6 +48,7 @@ struct GasC {
 struct Dev {
   int64_t nc, nf, nv;
   const int32_t* cell_nb;    // [nc][4] neighbour cell or -1
+  const int32_t* spatial;    // [nc] cells in Morton order of their centroids
   const int32_t* cell_face;  // [nc][4]
   const double* cell_geo;    // [nc][CG]
   const int32_t* face_cell;  // [nf][2] (cell the normal points out of, other cell or -1)

@@ -172,7 +172,7 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   constexpr int U = Vpt<T>::v;
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
-  const int64_t i = cc.cell;
+  const int64_t i = d.spatial[cc.cell];
   const int64_t nv = d.nv;
   const double* geo = d.cell_geo + CG * i;
   const T* G = (const T*)b.G;
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
   constexpr int U = Vpt<T>::v;
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
-  const int64_t i = cc.cell;
+  const int64_t i = d.spatial[cc.cell];
   const int64_t nv = d.nv;
   const double* geo = d.cell_geo + CG * i;
   const T *fG[4], *fR[4];
