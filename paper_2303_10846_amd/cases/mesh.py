@@ -91,13 +91,55 @@ def folded_faces(xyz: np.ndarray, tets: np.ndarray) -> int:
     return int(np.sum(sa * sb >= 0.0))
 
 
-def color_major(xyz: np.ndarray, tets: np.ndarray):
-    """Greedy first-fit colouring of the face-adjacency graph and colour-major renumbering.
+def _kempe_free(x, nbr, color, top, max_chain=4096):
+    """Give cell x (colour `top`) a colour below `top`, by a Kempe-chain interchange if none is free.
 
-    Cells are first put in Morton order of their centroids (locality), coloured
-    greedily in that order, then stably sorted by colour.  Returns
-    (tets_reordered, color_offsets) with color_offsets[c]..color_offsets[c+1]
-    the cells of colour c.  No two cells of one colour share a face.
+    For a neighbour y of x, of colour a, and a colour b != a below `top`: the connected set of cells coloured
+    a or b that contains y (the chain) has its two colours swapped, which keeps the colouring proper.  If
+    afterwards no neighbour of x is coloured a, x takes a.  Chains above max_chain cells are not tried.
+    Returns True on success (color updated in place).
+    """
+    used = {int(color[j]) for j in nbr[x]}
+    free = [c for c in range(top) if c not in used]
+    if free:
+        color[x] = free[0]
+        return True
+    for y in nbr[x]:
+        a = int(color[y])
+        for b in range(top):
+            if b == a:
+                continue
+            chain, stack = {y}, [y]
+            while stack and len(chain) <= max_chain:
+                u = stack.pop()
+                for v in nbr[u]:
+                    if v not in chain and int(color[v]) in (a, b):
+                        chain.add(v)
+                        stack.append(v)
+            if len(chain) > max_chain:
+                continue
+            after = [(b if int(color[j]) == a else a) if j in chain else int(color[j]) for j in nbr[x]]
+            if a in after:
+                continue
+            for u in chain:
+                color[u] = b if color[u] == a else a
+            color[x] = a
+            return True
+    return False
+
+
+def color_major(xyz: np.ndarray, tets: np.ndarray):
+    """Colouring of the face-adjacency graph and colour-major renumbering.
+
+    Cells are first put in Morton order of their centroids (locality) and coloured greedily (first fit) in
+    that order.  While the highest colour class is small (under 5% of the cells), its cells are moved to
+    lower colours by Kempe-chain interchanges, which removes that class.  The classes are then ordered so
+    that the largest comes last and the second largest first.  A forward + backward pair of colour sweeps
+    relaxes the last class once at the turn (its second relaxation would repeat the first bit for bit) and,
+    from the second pair on, the first class once at the other turn, so large end classes mean fewer
+    relaxations per pair.  Cells keep their Morton order within a class.  Returns (tets_reordered,
+    color_offsets) with color_offsets[c]..color_offsets[c+1] the cells of colour c.  No two cells of one
+    colour share a face.
     """
     nt = len(tets)
     cen = xyz[tets].mean(axis=1)
@@ -123,8 +165,24 @@ def color_major(xyz: np.ndarray, tets: np.ndarray):
         while c in used:
             c += 1
         color[i] = c
-    order = np.argsort(color, kind="stable")
     ncol = int(color.max()) + 1
+    while ncol > 2:
+        top = ncol - 1
+        cells = np.nonzero(color == top)[0]
+        if len(cells) > 0.05 * nt:
+            break
+        trial = color.copy()
+        if not all(_kempe_free(int(x), nbr, trial, top) for x in cells):
+            break
+        color = trial
+        ncol -= 1
+    sizes = np.bincount(color, minlength=ncol)
+    by_size = list(np.argsort(-sizes, kind="stable"))
+    seq = by_size[1:] + by_size[:1] if ncol > 1 else by_size     # second largest first, largest last
+    rank = np.empty(ncol, dtype=np.int64)
+    rank[np.asarray(seq, dtype=np.int64)] = np.arange(ncol)
+    color = rank[color]
+    order = np.argsort(color, kind="stable")
     offsets = np.zeros(ncol + 1, dtype=np.int64)
     offsets[1:] = np.cumsum(np.bincount(color, minlength=ncol))
     return np.ascontiguousarray(tets[order]), offsets

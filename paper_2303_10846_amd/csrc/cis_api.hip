@@ -99,6 +99,7 @@ struct cis_state {
   // library-owned device arrays
   int32_t *d_cell_nb = nullptr, *d_cell_face = nullptr, *d_face_cell = nullptr, *d_face_bc = nullptr,
           *d_spatial = nullptr;
+  float* d_cell_geo_f = nullptr;
   double *d_cell_geo = nullptr, *d_face_geo = nullptr, *d_dvs = nullptr, *d_bc = nullptr;
   float* d_dvs_f = nullptr;
   int64_t res_cap = 0;
@@ -563,6 +564,17 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
         sl[9 + r] = interior ? (I[3 * r] * dvec[a][0] + I[3 * r + 1] * dvec[a][1] + I[3 * r + 2] * dvec[a][2]) / det : 0.0;
     }
   }
+  std::vector<float> cgeof(CGF * nc, 0.0f);
+  for (int64_t i = 0; i < nc; ++i)
+    for (int a = 0; a < 4; ++a) {
+      const double* sl = &cgeo[CG * i + CG_FACE + CG_SLOT * a];
+      float* o = &cgeof[CGF * i + 7 * a];
+      for (int q = 0; q < 3; ++q) {
+        o[q] = (float)sl[5 + q];
+        o[4 + q] = (float)sl[9 + q];
+      }
+      o[3] = (float)sl[8];
+    }
   std::vector<double> dvsv(DVS_ARRAYS * nv, 0.0);
   std::vector<float> dvsf(DVS_F_ARRAYS * nv, 0.0f);
   for (int64_t k = 0; k < nv; ++k) {
@@ -594,6 +606,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   chk(own_upload(s, &s->d_face_cell, m->face_cell));
   chk(own_upload(s, &s->d_face_bc, face_bc));
   chk(own_upload(s, &s->d_cell_geo, cgeo));
+  chk(own_upload(s, &s->d_cell_geo_f, cgeof));
   chk(own_upload(s, &s->d_face_geo, fgeo));
   chk(own_upload(s, &s->d_dvs, dvsv));
   chk(own_upload(s, &s->d_dvs_f, dvsf));
@@ -631,6 +644,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   d.spatial = s->d_spatial;
   d.cell_face = s->d_cell_face;
   d.cell_geo = s->d_cell_geo;
+  d.cell_geo_f = s->d_cell_geo_f;
   d.face_cell = s->d_face_cell;
   d.face_bc = s->d_face_bc;
   d.face_geo = s->d_face_geo;

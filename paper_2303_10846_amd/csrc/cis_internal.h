@@ -16,6 +16,9 @@ namespace cis {
 constexpr int CG = 56;
 constexpr int CG_FACE = 8;
 constexpr int CG_SLOT = 12;
+// FP32 reconstruction geometry per cell: for face slot a, [7a, 7a + 3) = x_f - x_i, [7a + 3] = s_f,
+// [7a + 4, 7a + 7) = the least-squares weights of the neighbour difference
+constexpr int CGF = 32;
 
 // Per-face record, FP64, FGW doubles: [0] A  [1..3] unit normal (out of face_cell[2f])  [4] s  [5] dl
 constexpr int FGW = 8;
@@ -51,6 +54,7 @@ struct Dev {
   const int32_t* spatial;    // [nc] cells in Morton order of their centroids
   const int32_t* cell_face;  // [nc][4]
   const double* cell_geo;    // [nc][CG]
+  const float* cell_geo_f;   // [nc][CGF] FP32 copy of the reconstruction geometry, see CGF
   const int32_t* face_cell;  // [nf][2] (cell the normal points out of, other cell or -1)
   const int32_t* face_bc;    // [nf] slot in bc table, -1 interior
   const double* face_geo;    // [nf][FGW]

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "cis_device.h"
@@ -146,12 +147,15 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
   if (limiter) {
     const T scale = fabs(pmax) > fabs(pmin) ? fabs(pmax) : fabs(pmin);
     const T eps2 = kh3 * scale * scale;
+    // Venkatakrishnan's function with the common factor d2 divided out of both parts:
+    // psi = (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2), and psi = 1 where d2 = 0
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const T d2 = gx * fx[a] + gy * fy[a] + gz * fz[a];
       if (d2 != T(0)) {
         const T d1 = d2 > T(0) ? pmax - phi : pmin - phi;
-        const T psi = lim_div((d1 * d1 + eps2) * d2 + T(2) * d2 * d2 * d1, d2 * (d1 * d1 + T(2) * d2 * d2 + d1 * d2 + eps2));
+        const T d11 = d1 * d1, d12 = d1 * d2;
+        const T psi = lim_div(d11 + eps2 + T(2) * d12, d11 + T(2) * d2 * d2 + d12 + eps2);
         L = psi < L ? psi : L;
       }
     }
@@ -194,13 +198,25 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
     nx[a] = s[2];
     ny[a] = s[3];
     nz[a] = s[4];
-    fx[a] = (T)s[5];
-    fy[a] = (T)s[6];
-    fz[a] = (T)s[7];
-    sf[a] = (T)s[8];
-    wx[a] = (T)s[9];
-    wy[a] = (T)s[10];
-    wz[a] = (T)s[11];
+    if constexpr (std::is_same<T, float>::value) {
+      // the FP32 copy: used straight from scalar registers, no conversions
+      const float* sg = d.cell_geo_f + CGF * i + 7 * a;
+      fx[a] = sg[0];
+      fy[a] = sg[1];
+      fz[a] = sg[2];
+      sf[a] = sg[3];
+      wx[a] = sg[4];
+      wy[a] = sg[5];
+      wz[a] = sg[6];
+    } else {
+      fx[a] = s[5];
+      fy[a] = s[6];
+      fz[a] = s[7];
+      sf[a] = s[8];
+      wx[a] = s[9];
+      wy[a] = s[10];
+      wz[a] = s[11];
+    }
   }
   double kh3d = d.lim_K * geo[2];
   kh3d = kh3d * kh3d * kh3d;
@@ -576,7 +592,12 @@ __global__ __launch_bounds__(kMacroBlock) void k_macro_sweep(Dev d, const double
   const int a = (int)(t & 3);
   const bool valid = i < c1;
   double term[6] = {0, 0, 0, 0, 0, 0};
+  double acc[6], D = 1.0, D5 = 1.0;
   if (valid) {
+    // the cell's right-hand side and diagonal are loaded up front, with the neighbour's state
+    for (int m = 0; m < 6; ++m) acc[m] = w.mres[6 * i + m];
+    D = w.mD[2 * i];
+    D5 = w.mD[2 * i + 1];
     const int32_t nb = d.cell_nb[4 * i + a];
     if (nb >= 0) {
       const double* s = d.cell_geo + CG * i + CG_FACE + CG_SLOT * a;
@@ -599,15 +620,12 @@ __global__ __launch_bounds__(kMacroBlock) void k_macro_sweep(Dev d, const double
     t3[m] = __shfl(term[m], lane + 3, 64);
   }
   if (!valid || a != 0) return;
-  double acc[6];
-  for (int m = 0; m < 6; ++m) acc[m] = w.mres[6 * i + m];
   for (int m = 0; m < 6; ++m) {
     acc[m] -= term[m];
     acc[m] -= t1[m];
     acc[m] -= t2[m];
     acc[m] -= t3[m];
   }
-  const double D = w.mD[2 * i], D5 = w.mD[2 * i + 1];
   for (int m = 0; m < 5; ++m) w.dW[6 * i + m] = acc[m] / D;
   w.dW[6 * i + 5] = acc[5] / D5;
 }
