@@ -301,21 +301,21 @@ template <class F> __device__ inline void k_loop(int64_t nv, F&& body) {
   }
 }
 
-// The same loop with the loads of kPrefetch velocities per thread issued before any of their arithmetic:
+// The same loop with the loads of P velocities per thread issued before any of their arithmetic:
 // load(k, q) fills the registers of slot q (loads only), body(k, q) consumes them.  A face workgroup that
 // loops over a whole row is otherwise bound by one memory round trip per trip (measured: face kernel -12%;
-// the update kernel loses occupancy with it and is not faster).
-constexpr int kPrefetch = 4;
-template <class L, class B> __device__ inline void k_loop_pf(int64_t nv, L&& load, B&& body) {
+// the update kernel loses occupancy with it and is not faster).  P = 4 in FP32, 2 in FP64 (registers).
+template <class T> struct Prefetch { static constexpr int v = sizeof(T) == 4 ? 4 : 2; };
+template <int P, class L, class B> __device__ inline void k_loop_pf(int64_t nv, L&& load, B&& body) {
   const int n = (int)nv;
-  for (int k0 = threadIdx.x; k0 < n; k0 += kPrefetch * kBlock) {
+  for (int k0 = threadIdx.x; k0 < n; k0 += P * kBlock) {
 #pragma unroll
-    for (int q = 0; q < kPrefetch; ++q) {
+    for (int q = 0; q < P; ++q) {
       const int k = k0 + q * kBlock;
       if (k < n) load(k, q);
     }
 #pragma unroll
-    for (int q = 0; q < kPrefetch; ++q) {
+    for (int q = 0; q < P; ++q) {
       const int k = k0 + q * kBlock;
       if (k < n) body(k, q);
     }
@@ -406,9 +406,10 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
                           0.5 * (Wo[3] / Wo[0] + Wn[3] / Wn[0])};
     Acc<17, false, kBlock> a17;
     a17.zero();
-    T pg[kPrefetch], pr[kPrefetch];
-    double px[kPrefetch], py[kPrefetch], pz[kPrefetch], pw[kPrefetch];
-    k_loop_pf(nv, [&](int k, int q) {
+    constexpr int P = Prefetch<T>::v;
+    T pg[P], pr[P];
+    double px[P], py[P], pz[P], pw[P];
+    k_loop_pf<P>(nv, [&](int k, int q) {
       pg[q] = rowG[k];
       pr[q] = rowR[k];
       px[q] = V.ux[k];
@@ -453,8 +454,8 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     const T ct = (T)sh_ec[28], cs = (T)sh_ec[29];
     // pass 2: phi_f (Eq. 45), micro flux and macro flux
     acc.zero();
-    Vel pv[kPrefetch];
-    k_loop_pf(nv, [&](int k, int q) {
+    Vel pv[P];
+    k_loop_pf<P>(nv, [&](int k, int q) {
       pg[q] = UseLds ? sG[k] : rowG[k];
       pr[q] = UseLds ? sR[k] : rowR[k];
       pv[q] = vel(V, k);
@@ -532,20 +533,12 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   if (threadIdx.x < 6) w.face_mac[6 * f + threadIdx.x] = A * tot[threadIdx.x];
 }
 
-// phi_bar of one face is staged in LDS when it fits (gfx950: 160 KB per workgroup; above 64 KB the
-// kernel's dynamic-LDS limit is raised once), else re-read from global memory in passes 2 and 3.
-constexpr int64_t kLdsDefault = 64 * 1024, kLdsMax = 160 * 1024 - 4096;
+// phi_bar of one face is staged in LDS when the row takes at most 40 KB, so that four face workgroups still
+// share a CU (160 KB of LDS); a longer row is re-read from global memory (the caches) in pass 2.  Measured on
+// the sphere (4140 velocities): FP32 rows (33 KB) are faster staged, FP64 rows (66 KB) faster re-read.
+constexpr int64_t kLdsStageMax = 40 * 1024;
 
-template <class T> static bool face_lds_ok(int64_t nv) {
-  int64_t bytes = nv * 2 * (int64_t)sizeof(T);
-  if (bytes <= kLdsDefault) return true;
-  if (bytes > kLdsMax) return false;
-  static int raised = 0;  // 0 unknown, 1 raised, -1 refused
-  if (raised == 0)
-    raised = hipFuncSetAttribute((const void*)k_face<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kLdsMax) == hipSuccess ? 1 : -1;
-  return raised == 1;
-}
+template <class T> static bool face_lds_ok(int64_t nv) { return nv * 2 * (int64_t)sizeof(T) <= kLdsStageMax; }
 
 template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
   if (face_lds_ok<T>(d.nv)) {
