@@ -93,6 +93,7 @@ typedef struct {
   int64_t phi_bytes;   /* one [n_cells][n_vel] distribution array */
   int64_t face_bytes;  /* one [n_faces][n_vel] face array */
   int64_t cell6_bytes; /* one [n_cells][6] FP64 array (W or q) */
+  int64_t code_bytes;  /* the [n_cells][n_vel] uint8 upwind-code array */
   int64_t total_bytes; /* sum over all cis_device_buffers members */
 } cis_buffer_sizes;
 
@@ -108,6 +109,9 @@ typedef struct {
   void* faceR;
   double* W;    /* [n_cells][6] */
   double* q;    /* [n_cells][6] */
+  uint8_t* upwind; /* [n_cells][n_vel], written by cis_state_create: for face slot a of cell i (its a-th face),
+                      bits 2a..2a+1 of entry (i, k) are 1 if u_k.n > 0 (out of the cell), 2 if u_k.n < 0, 0 if
+                      |u_k.n| is within the tie tolerance of zero (Eq. 46 upwinding, Eq. 33 diagonal) */
 } cis_device_buffers;
 
 /* Last error message of this thread. */

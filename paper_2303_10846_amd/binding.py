@@ -59,7 +59,7 @@ class MeshInfo(C.Structure):
 
 
 class BufferSizes(C.Structure):
-    _fields_ = [(k, C.c_int64) for k in ("phi_bytes", "face_bytes", "cell6_bytes", "total_bytes")]
+    _fields_ = [(k, C.c_int64) for k in ("phi_bytes", "face_bytes", "cell6_bytes", "code_bytes", "total_bytes")]
 
 
 class AdjointInfo(C.Structure):
@@ -72,7 +72,7 @@ class WallFace(C.Structure):
 
 
 class DeviceBuffers(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("G", "R", "dG", "dR", "resG", "resR", "faceG", "faceR", "W", "q")]
+    _fields_ = [(k, C.c_void_p) for k in ("G", "R", "dG", "dR", "resG", "resR", "faceG", "faceR", "W", "q", "upwind")]
 
 
 _lib = None
@@ -263,9 +263,10 @@ class Solver:
             self.faceG, self.faceR = mk(self.nf), mk(self.nf)
             self.W = torch.zeros(self.nc, 6, dtype=torch.float64, device=self.device)
             self.q = torch.zeros(self.nc, 6, dtype=torch.float64, device=self.device)
+            self.upwind = torch.empty(self.nc, self.nv, dtype=torch.uint8, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         bufs = DeviceBuffers(*(t.data_ptr() for t in (self.G, self.R, self.dG, self.dR, self.resG, self.resR,
-                                                      self.faceG, self.faceR, self.W, self.q)))
+                                                      self.faceG, self.faceR, self.W, self.q, self.upwind)))
         bc_arr = _bc_array(self.bcs)
         self._gas_s = gas_struct(self.gas)
         self._num_s = numerics_struct(self.num)

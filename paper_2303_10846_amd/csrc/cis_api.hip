@@ -458,7 +458,8 @@ cis_status cis_state_required_bytes(const cis_mesh* m, const cis_dvs* d, int32_t
   out->phi_bytes = m->nc * d->n * es;
   out->face_bytes = m->nf * d->n * es;
   out->cell6_bytes = m->nc * 6 * 8;
-  out->total_bytes = 6 * out->phi_bytes + 2 * out->face_bytes + 2 * out->cell6_bytes;
+  out->code_bytes = m->nc * d->n;
+  out->total_bytes = 6 * out->phi_bytes + 2 * out->face_bytes + 2 * out->cell6_bytes + out->code_bytes;
   return CIS_OK;
 }
 
@@ -472,7 +473,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   cis_status st = check_numerics(num);
   if (st != CIS_OK) return st;
   if (!buf->G || !buf->R || !buf->dG || !buf->dR || !buf->resG || !buf->resR || !buf->faceG || !buf->faceR || !buf->W ||
-      !buf->q)
+      !buf->q || !buf->upwind)
     return fail(CIS_E_INVALID_ARG, "a device buffer is NULL");
   if (!(gas->R > 0) || !(gas->gamma > 1) || !(gas->Z > 0) || !(gas->mu_ref > 0) || !(gas->T_ref > 0))
     return fail(CIS_E_INVALID_ARG, "gas constants out of range");
@@ -620,6 +621,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   chk(own_alloc(s, &w.mD, 2 * nc));
   chk(own_alloc(s, &w.Fmac, 6 * nc));
   chk(own_alloc(s, &w.dW, 6 * nc));
+  chk(own_alloc(s, &w.mbase, nc));
   chk(own_alloc(s, &w.Wt, 6 * nc));
   chk(own_alloc(s, &w.eq, ER * nc));
   chk(own_alloc(s, &w.cellres, 6 * nc));
@@ -645,6 +647,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   d.cell_face = s->d_cell_face;
   d.cell_geo = s->d_cell_geo;
   d.cell_geo_f = s->d_cell_geo_f;
+  d.upw = buf->upwind;
   d.face_cell = s->d_face_cell;
   d.face_bc = s->d_face_bc;
   d.face_geo = s->d_face_geo;
@@ -655,6 +658,11 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   d.umax = dv->umax;
   fill_dev_numerics(s);
   s->buf = Bufs{buf->G, buf->R, buf->dG, buf->dR, buf->resG, buf->resR, buf->faceG, buf->faceR, buf->W, buf->q};
+  launch_upwind_codes(d, s->stream);
+  if (hipStreamSynchronize(s->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
+    delete s;
+    return fail(CIS_E_DEVICE, "upwind codes failed");
+  }
   *out = s;
   return CIS_OK;
 }
@@ -664,8 +672,14 @@ cis_status cis_state_set_numerics(cis_state* s, const cis_numerics* num) {
   cis_status st = check_numerics(num);
   if (st != CIS_OK) return st;
   if (num->cfl != s->num.cfl) return fail(CIS_E_UNSUPPORTED, "cfl (face step s_ij) is fixed at state creation");
+  const bool recode = num->snap != s->num.snap;
   s->num = *num;
   fill_dev_numerics(s);
+  if (recode) {
+    launch_upwind_codes(s->dev, s->stream);
+    st = device_check("upwind codes");
+    if (st != CIS_OK) return st;
+  }
   return CIS_OK;
 }
 

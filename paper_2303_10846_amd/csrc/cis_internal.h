@@ -55,6 +55,7 @@ struct Dev {
   const int32_t* cell_face;  // [nc][4]
   const double* cell_geo;    // [nc][CG]
   const float* cell_geo_f;   // [nc][CGF] FP32 copy of the reconstruction geometry, see CGF
+  uint8_t* upw;              // [nc][nv] upwind codes: bits 2a..2a+1 = 1 (u.n > 0), 2 (u.n < 0), 0 (tie) of slot a
   const int32_t* face_cell;  // [nf][2] (cell the normal points out of, other cell or -1)
   const int32_t* face_bc;    // [nf] slot in bc table, -1 interior
   const double* face_geo;    // [nf][FGW]
@@ -75,6 +76,7 @@ struct Work {
   double* mD;        // [nc][2]
   double* Fmac;      // [nc][6]
   double* dW;        // [nc][6]
+  double* mbase;     // [nc] 1/dt_i + 1/tau~_i, the velocity-independent part of the diagonal of Eq. 33
   double* Wt;        // [nc][6]
   double* eq;        // [nc][ER]
   double* cellres;   // [nc][6]
@@ -102,6 +104,7 @@ template <class T> void launch_micro(const Dev& d, const Bufs& b, const Work& w,
                                      int64_t n_colors, int n_micro, hipStream_t st);
 template <class T> void launch_update(const Dev& d, const Bufs& b, const Work& w, int64_t it, hipStream_t st);
 void launch_macro_flux_cells(const Dev& d, const Work& w, hipStream_t st);
+void launch_upwind_codes(const Dev& d, hipStream_t st);
 int max_velocities();
 std::vector<int64_t> sweep_sequence(const int64_t* color_off, int64_t n_colors, int n_pairs);
 

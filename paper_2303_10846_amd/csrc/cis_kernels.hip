@@ -185,7 +185,6 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   T* FR = (T*)b.faceR;
   int32_t nb[4];
   int64_t srow[4], frow[4];  // element offsets of the neighbour rows and the face rows (shared by G and R)
-  double nx[4], ny[4], nz[4];
   bool own[4];
   T wx[4], wy[4], wz[4], fx[4], fy[4], fz[4], sf[4];
 #pragma unroll
@@ -195,9 +194,6 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
     frow[a] = (int64_t)d.cell_face[4 * i + a] * nv;
     const double* s = geo + CG_FACE + CG_SLOT * a;
     own[a] = s[0] > 0.0;
-    nx[a] = s[2];
-    ny[a] = s[3];
-    nz[a] = s[4];
     if constexpr (std::is_same<T, float>::value) {
       // the FP32 copy: used straight from scalar registers, no conversions
       const float* sg = d.cell_geo_f + CGF * i + 7 * a;
@@ -222,21 +218,26 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   kh3d = kh3d * kh3d * kh3d;
   const T kh3 = (T)kh3d;
   const int limiter = d.limiter;
-  const double snap = d.snap;
   const int64_t self = i * nv;
   const int nvi = (int)nv;
   const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
   T pG[U], pR[U], nG[U][4], nR[U][4], tx[U], ty[U], tz[U];
-  double ux[U], uy[U], uz[U], um[U];
+  unsigned code[U];
   bool up[U][4];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = k0 + u * kBlock;
     if (k >= nvi) continue;
-    ux[u] = d.dvs[k];
-    uy[u] = d.dvs[nv + k];
-    uz[u] = d.dvs[2 * nv + k];
-    um[u] = d.dvs[4 * nv + k];
+    code[u] = d.upw[self + k];
+    if constexpr (std::is_same<T, float>::value) {
+      tx[u] = d.dvs_f[k];
+      ty[u] = d.dvs_f[nv + k];
+      tz[u] = d.dvs_f[2 * nv + k];
+    } else {
+      tx[u] = d.dvs[k];
+      ty[u] = d.dvs[nv + k];
+      tz[u] = d.dvs[2 * nv + k];
+    }
     pG[u] = G[self + k];
     pR[u] = R[self + k];
 #pragma unroll
@@ -245,20 +246,16 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
       nR[u][a] = R[srow[a] + k];
     }
   }
-  // upwind decisions first, so that the FP64 normals are dead during the arithmetic below
+  // upwind cell of the face for this velocity: the owner when u.n_face > 0, else the neighbour (a tie goes to
+  // the neighbour); the code of slot a holds the sign of u.n out of this cell
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (k0 + u * kBlock >= nvi) continue;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      double un = ux[u] * nx[a] + uy[u] * ny[a] + uz[u] * nz[a];
-      un = fabs(un) <= snap * um[u] ? 0.0 : un;
-      // upwind cell of the face for this velocity: the owner when u.n_face > 0, else the neighbour
-      up[u][a] = nb[a] >= 0 ? (own[a] ? un > 0.0 : un >= 0.0) : un > 0.0;
+      const unsigned c = (code[u] >> (2 * a)) & 3u;
+      up[u][a] = nb[a] >= 0 ? (own[a] ? c == 1u : c != 2u) : c == 1u;
     }
-    tx[u] = (T)ux[u];
-    ty[u] = (T)uy[u];
-    tz[u] = (T)uz[u];
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -671,6 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_eq(Dev d, const double* W, cons
   double* e = w.eq + ER * i;
   eq_coeffs(p, q + 6 * i, d.gas, e);
   e[7] = visc(p.Ttr, d.gas) / (p.rho * d.gas.R * p.Ttr);
+  w.mbase[i] = inv_dt_cell(d, d.cell_geo[CG * i + 2]) + 1.0 / e[7];
 }
 
 __global__ __launch_bounds__(kBlock) void k_macro_flux_cells(Dev d, Work w) {
@@ -813,11 +811,14 @@ void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, voi
 // increments of later colours are still zero and are not read.  Workgroup (cell, velocity chunk).
 // ---------------------------------------------------------------------------
 
-// Per-cell operands of one relaxation
+// Per-cell operands of one relaxation.  The signs of u.n come from the upwind codes (the same decisions as in
+// every other kernel); the magnitudes are computed in the precision of the distributions: in FP64 exactly as
+// before, in the mixed mode in FP32 (the increments of the sweep only steer the iteration, its fixed point is
+// set by Res).
 template <class T> struct MicroCell {
   const T *nG[4], *nR[4], *rG, *rR;
   T *oG, *oR;
-  double nx[4], ny[4], nz[4], av[4], base;
+  T nx[4], ny[4], nz[4], av[4], base;
   bool use[4];
 };
 
@@ -834,27 +835,28 @@ __device__ inline void micro_setup(const Dev& d, const Bufs& b, const Work& w, i
     c.nG[a] = (const T*)b.dG + row;
     c.nR[a] = (const T*)b.dR + row;
     const double* s = geo + CG_FACE + CG_SLOT * a;
-    c.nx[a] = s[2];
-    c.ny[a] = s[3];
-    c.nz[a] = s[4];
-    c.av[a] = s[1];
+    c.nx[a] = (T)s[2];
+    c.ny[a] = (T)s[3];
+    c.nz[a] = (T)s[4];
+    c.av[a] = (T)s[1];
   }
-  c.base = inv_dt_cell(d, geo[2]) + 1.0 / w.eq[ER * i + 7];
+  c.base = (T)w.mbase[i];
   c.rG = (const T*)b.resG + i * nv;
   c.rR = (const T*)b.resR + i * nv;
   c.oG = (T*)b.dG + i * nv;
   c.oR = (T*)b.dR + i * nv;
 }
 
-// Values a relaxation reads: u.n per face, the right-hand sides and the upstream neighbours' increments
+// Values a relaxation reads: the outflow part max(u.n, 0) and inflow part min(u.n, 0) per face, the right-hand
+// sides and the upstream neighbours' increments
 template <class T, int U> struct MicroIn {
-  double un[U][4];
+  T pos[U][4], neg[U][4];
   T xG[U], xR[U], yG[U][4], yR[U][4];
 };
 
 template <class T, int U>
-__device__ inline void micro_load(const MicroCell<T>& c, const double (*uv)[4], const int* k, int nvi, double snap,
-                                  MicroIn<T, U>& in) {
+__device__ inline void micro_load(const MicroCell<T>& c, const T (*uv)[3], const unsigned* code, const int* k,
+                                  int nvi, MicroIn<T, U>& in) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (k[u] >= nvi) continue;
@@ -862,10 +864,11 @@ __device__ inline void micro_load(const MicroCell<T>& c, const double (*uv)[4], 
     in.xR[u] = c.rR[k[u]];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      double t = uv[u][0] * c.nx[a] + uv[u][1] * c.ny[a] + uv[u][2] * c.nz[a];
-      t = fabs(t) <= snap * uv[u][3] ? 0.0 : t;
-      in.un[u][a] = t;
-      if (c.use[a] && t < 0.0) {
+      const unsigned cd = (code[u] >> (2 * a)) & 3u;
+      const T t = uv[u][0] * c.nx[a] + uv[u][1] * c.ny[a] + uv[u][2] * c.nz[a];
+      in.pos[u][a] = cd == 1u ? fmax(t, T(0)) : T(0);
+      in.neg[u][a] = cd == 2u ? fmin(t, T(0)) : T(0);
+      if (c.use[a] && cd == 2u) {
         in.yG[u][a] = c.nG[a][k[u]];
         in.yR[u][a] = c.nR[a][k[u]];
       }
@@ -874,24 +877,24 @@ __device__ inline void micro_load(const MicroCell<T>& c, const double (*uv)[4], 
 }
 
 template <class T, int U>
-__device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& in, const int* k, int nvi) {
+__device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& in, const unsigned* code,
+                                   const int* k, int nvi) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (k[u] >= nvi) continue;
-    double D = c.base;
-    double aG = (double)in.xG[u], aR = (double)in.xR[u];
+    T D = c.base;
+    T aG = in.xG[u], aR = in.xR[u];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const double t = in.un[u][a];
-      D += c.av[a] * fmax(t, 0.0);
-      if (c.use[a] && t < 0.0) {
-        aG -= c.av[a] * t * (double)in.yG[u][a];
-        aR -= c.av[a] * t * (double)in.yR[u][a];
+      D += c.av[a] * in.pos[u][a];
+      if (c.use[a] && ((code[u] >> (2 * a)) & 3u) == 2u) {
+        aG -= c.av[a] * in.neg[u][a] * in.yG[u][a];
+        aR -= c.av[a] * in.neg[u][a] * in.yR[u][a];
       }
     }
-    const double iD = 1.0 / D;
-    c.oG[k[u]] = (T)(aG * iD);
-    c.oR[k[u]] = (T)(aR * iD);
+    const T iD = T(1) / D;
+    c.oG[k[u]] = aG * iD;
+    c.oR[k[u]] = aR * iD;
   }
 }
 
@@ -904,22 +907,56 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, i
   if (cc.cell >= cnext - c0) return;
   const int64_t nv = d.nv;
   const int nvi = (int)nv;
+  const int64_t i = c0 + cc.cell;
   int k[U];
-  double uv[U][4];
+  unsigned code[U];
+  T uv[U][3];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     k[u] = (int)cc.chunk * (kBlock * U) + u * kBlock + (int)threadIdx.x;
     if (k[u] >= nvi) continue;
-    uv[u][0] = d.dvs[k[u]];
-    uv[u][1] = d.dvs[nv + k[u]];
-    uv[u][2] = d.dvs[2 * nv + k[u]];
-    uv[u][3] = d.dvs[4 * nv + k[u]];
+    code[u] = d.upw[i * nv + k[u]];
+    if constexpr (std::is_same<T, float>::value) {
+      uv[u][0] = d.dvs_f[k[u]];
+      uv[u][1] = d.dvs_f[nv + k[u]];
+      uv[u][2] = d.dvs_f[2 * nv + k[u]];
+    } else {
+      uv[u][0] = d.dvs[k[u]];
+      uv[u][1] = d.dvs[nv + k[u]];
+      uv[u][2] = d.dvs[2 * nv + k[u]];
+    }
   }
   MicroCell<T> c;
   MicroIn<T, U> in;
-  micro_setup<T>(d, b, w, c0 + cc.cell, cnext, first, c);
-  micro_load<T, U>(c, uv, k, nvi, d.snap, in);
-  micro_store<T, U>(c, in, k, nvi);
+  micro_setup<T>(d, b, w, i, cnext, first, c);
+  micro_load<T, U>(c, uv, code, k, nvi, in);
+  micro_store<T, U>(c, in, code, k, nvi);
+}
+
+// Upwind codes of every (cell, velocity): the sign of u.n out of the cell through each of its four faces, with
+// the tie rule |u.n| <= snap |u| -> 0 (Eq. 46), in FP64.  Computed once per state (and when snap changes).
+__global__ __launch_bounds__(kBlock) void k_upwind_codes(Dev d) {
+  const int64_t nv = d.nv;
+  const int64_t n = d.nc * nv;
+  for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n; x += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = x / nv, k = x - i * nv;
+    const double ux = d.dvs[k], uy = d.dvs[nv + k], uz = d.dvs[2 * nv + k], um = d.dvs[4 * nv + k];
+    const double* geo = d.cell_geo + CG * i;
+    unsigned code = 0;
+    for (int a = 0; a < 4; ++a) {
+      const double* s = geo + CG_FACE + CG_SLOT * a;
+      double un = ux * s[2] + uy * s[3] + uz * s[4];
+      un = fabs(un) <= d.snap * um ? 0.0 : un;
+      code |= (un > 0.0 ? 1u : (un < 0.0 ? 2u : 0u)) << (2 * a);
+    }
+    d.upw[x] = (uint8_t)code;
+  }
+}
+
+void launch_upwind_codes(const Dev& d, hipStream_t st) {
+  const int64_t n = d.nc * d.nv;
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 65536));
+  hipLaunchKernelGGL(k_upwind_codes, dim3(nb), dim3(kBlock), 0, st, d);
 }
 
 template <class T> __global__ __launch_bounds__(kBlock) void k_zero(T* a, T* b, int64_t n) {

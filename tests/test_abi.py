@@ -92,6 +92,8 @@ def test_required_bytes():
         assert lib.cis_state_required_bytes(mm.h, dv.h, prec, C.byref(s)) == 0
         assert s.phi_bytes == 48 * 64 * es
         assert s.face_bytes == mm.info.n_faces * 64 * es
+        assert s.code_bytes == 48 * 64
+        assert s.total_bytes == 6 * s.phi_bytes + 2 * s.face_bytes + 2 * s.cell6_bytes + s.code_bytes
     s = binding.BufferSizes()
     assert lib.cis_state_required_bytes(mm.h, dv.h, 7, C.byref(s)) == -1
 
