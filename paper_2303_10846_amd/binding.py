@@ -491,16 +491,35 @@ def steady_residual_fn(solver, wall_tag, ff_tag, p, G, R, W, q):
     return _SR.apply(solver, wall_tag, ff_tag, p, G, R, W, q)
 
 
-def wall_coefficients(loads: dict, rho_inf: float, U_inf, T_inf: float, R: float = 0.5, A_ref: float = None) -> dict:
-    """C_p, C_tau, C_h per wall face (Eqs. 70-72) from Solver.wall_loads, and, with a reference area, the force
-    coefficients along U_inf (drag) and the heat-load coefficient."""
+def wall_coefficients(loads: dict, rho_inf: float, U_inf, T_inf: float, R: float = 0.5, A_ref: float = None,
+                      L_ref: float = 1.0, x_ref=(0.0, 0.0, 0.0), lift_dir=None) -> dict:
+    """Wall coefficients from Solver.wall_loads, with q_inf = rho_inf |U_inf|^2 / 2 and p_inf = rho_inf R T_inf.
+
+    Per wall face (Eqs. 70-72): C_p = (p - p_inf) / q_inf, C_tau = |tau| / q_inf, C_h = q / (q_inf |U_inf|).
+    With a reference area A_ref (and length L_ref), from the force F = sum_f A_f (p n + tau) on the wall and its
+    moment M = sum_f (x_f - x_ref) x A_f (p n + tau):  CF = F / (q_inf A_ref); drag Cd = CF . e_D with
+    e_D = U_inf / |U_inf|; lift Cl = CF . e_L with e_L the unit part of lift_dir normal to e_D (default: z, or y
+    when z is along U_inf); CM = M / (q_inf A_ref L_ref) and the pitching moment Cm = CM . (e_L x e_D); and the
+    heat-load coefficient CQ = heat / (q_inf |U_inf| A_ref).
+    """
     U = np.asarray(U_inf, dtype=float)
     Um = float(np.linalg.norm(U))
     qd = 0.5 * rho_inf * Um * Um
     out = dict(Cp=(loads["p"] - rho_inf * R * T_inf) / qd, Ctau=np.linalg.norm(loads["tau"], axis=1) / qd,
                Ch=loads["q"] / (qd * Um))
     if A_ref:
+        eD = U / Um
+        eL = np.array([0.0, 0.0, 1.0]) if lift_dir is None else np.asarray(lift_dir, dtype=float)
+        eL = eL - (eL @ eD) * eD
+        if np.linalg.norm(eL) < 1e-12 and lift_dir is None:
+            eL = np.array([0.0, 1.0, 0.0]) - eD[1] * eD
+        eL = eL / np.linalg.norm(eL)
+        f = loads["area"][:, None] * (loads["p"][:, None] * loads["n"] + loads["tau"])
+        M = np.cross(loads["x"] - np.asarray(x_ref, dtype=float), f).sum(axis=0)
         out["CF"] = loads["force"] / (qd * A_ref)
-        out["Cd"] = float(loads["force"] @ U / Um) / (qd * A_ref)
+        out["Cd"] = float(out["CF"] @ eD)
+        out["Cl"] = float(out["CF"] @ eL)
+        out["CM"] = M / (qd * A_ref * L_ref)
+        out["Cm"] = float(out["CM"] @ np.cross(eL, eD))
         out["CQ"] = loads["heat"] / (qd * Um * A_ref)
     return out

@@ -228,7 +228,7 @@ def test_wall_loads_match_oracle_face_fluxes():
     oo, ol = np.lexsort(xo.T[::-1]), np.lexsort(L["x"].T[::-1])
     assert np.max(np.abs(xo[oo] - L["x"][ol])) < 1e-12
     p, tau, q = p[oo], tau[oo], q[oo]
-    L = dict(L, p=L["p"][ol], tau=L["tau"][ol], q=L["q"][ol])
+    L = dict(L, x=L["x"][ol], area=L["area"][ol], n=L["n"][ol], p=L["p"][ol], tau=L["tau"][ol], q=L["q"][ol])
     assert nrel(L["p"], p) < TOL
     assert nrel(L["tau"], tau) < TOL
     assert nrel(L["q"], q) < TOL
@@ -236,9 +236,14 @@ def test_wall_loads_match_oracle_face_fluxes():
     assert abs(L["heat"] - fm[wall, 4].sum()) <= TOL * abs(fm[wall, 4].sum())
     assert abs(L["heat"] - s.wall_heat_flux(1)) <= 1e-14 * abs(L["heat"])
     from paper_2303_10846_amd.binding import wall_coefficients
+    # the per-face loads integrate to the library's force
+    f = L["area"][:, None] * (L["p"][:, None] * L["n"] + L["tau"])
+    assert nrel(f.sum(axis=0), L["force"]) < 1e-12
     cf = wall_coefficients(L, 1.0, c["U_inf"], 1.0, A_ref=0.25 * np.pi)
-    say(f"Cd {cf['Cd']:.4f}  CQ {cf['CQ']:.4f}  Cp max {cf['Cp'].max():.3f}")
+    say(f"Cd {cf['Cd']:.4f}  Cl {cf['Cl']:.2e}  Cm {cf['Cm']:.2e}  CQ {cf['CQ']:.4f}  Cp max {cf['Cp'].max():.3f}")
     assert np.all(np.isfinite(cf["Cp"])) and cf["Cd"] > 0.0
+    # a sphere at zero incidence: lift and pitching moment about its centre are small beside the drag
+    assert abs(cf["Cl"]) < 0.05 * cf["Cd"] and abs(cf["Cm"]) < 0.05 * cf["Cd"]
 
 
 def test_no_micro_sweeps_means_zero_increments():
