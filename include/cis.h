@@ -58,10 +58,12 @@ typedef struct cis_mesh cis_mesh;
 typedef struct cis_dvs cis_dvs;
 typedef struct cis_state cis_state;
 
-/* Gas constants.  Rykov model, Sec. 2: Z_rot, delta, omega0, omega1 (Eqs. 11-12, 19-22);
-   VHS viscosity mu = mu_ref (T_tr/T_ref)^omega_vhs (Eq. 13); relaxation time tau = mu/p_tr. */
+/* Gas constants.  Rykov model, Sec. 2: Z_rot, delta, omega0, omega1 (Eqs. 11-12, 19-22); relaxation time
+   tau = mu/p_tr.  Viscosity: C_s = 0 selects the VHS law mu = mu_ref (T_tr/T_ref)^omega_vhs (Eq. 13); C_s > 0
+   selects Sutherland's law mu = mu_ref (T_tr/T_ref)^(3/2) (T_ref + C_s)/(T_tr + C_s) (Eq. 14), and omega_vhs
+   is then unused.  C_s < 0 is rejected. */
 typedef struct {
-  double R, gamma, Z, delta, omega0, omega1, mu_ref, omega_vhs, T_ref;
+  double R, gamma, Z, delta, omega0, omega1, mu_ref, omega_vhs, T_ref, C_s;
 } cis_gas;
 
 /* Numerics.

@@ -19,7 +19,7 @@ _SRC = os.path.join(_HERE, "cis_oracle.cpp")
 _LIB = os.path.join(_HERE, "_build", "libcis_oracle.so")
 _lib = None
 
-GAS_KEYS = ["R", "gamma", "Z", "delta", "omega0", "omega1", "mu_ref", "omega_vhs", "T_ref"]
+GAS_KEYS = ["R", "gamma", "Z", "delta", "omega0", "omega1", "mu_ref", "omega_vhs", "T_ref", "C_s"]
 NUM_KEYS = ["cfl", "inv_dt", "cfl_imp", "lim_K", "limiter", "n_macro", "n_micro", "snap", "macro_exact_jvp"]
 
 STAGES = dict(FG=0, FR=1, Fmac=2, dW=3, ResG=4, ResR=5, dG=6, dR=7, gradG=8, gradR=9, Gs=10, Rs=11, Qface=12,
@@ -88,7 +88,7 @@ def _f64(a):
 
 
 def gas_array(gas: dict) -> np.ndarray:
-    return np.array([float(gas[k]) for k in GAS_KEYS])
+    return np.array([float(gas.get(k, 0.0)) if k == "C_s" else float(gas[k]) for k in GAS_KEYS])
 
 
 def num_array(num: dict) -> np.ndarray:

@@ -47,14 +47,14 @@ constexpr double kPi = 3.14159265358979323846;
 // ---------------------------------------------------------------------------
 // Constants (passed from Python as flat double arrays)
 // ---------------------------------------------------------------------------
-enum GasIdx { G_R, G_GAMMA, G_Z, G_DELTA, G_OMEGA0, G_OMEGA1, G_MUREF, G_OMEGAV, G_TREF, G_COUNT };
+enum GasIdx { G_R, G_GAMMA, G_Z, G_DELTA, G_OMEGA0, G_OMEGA1, G_MUREF, G_OMEGAV, G_TREF, G_CS, G_COUNT };
 enum NumIdx { N_CFL, N_INVDT, N_CFLIMP, N_LIMK, N_LIMITER, N_NMACRO, N_NMICRO, N_SNAP, N_EXACTJVP, N_COUNT };
 
 struct Gas {
-  double R, gamma, Z, delta, omega0, omega1, mu_ref, omega_v, T_ref;
+  double R, gamma, Z, delta, omega0, omega1, mu_ref, omega_v, T_ref, C_s;
   explicit Gas(const double* g)
       : R(g[G_R]), gamma(g[G_GAMMA]), Z(g[G_Z]), delta(g[G_DELTA]), omega0(g[G_OMEGA0]),
-        omega1(g[G_OMEGA1]), mu_ref(g[G_MUREF]), omega_v(g[G_OMEGAV]), T_ref(g[G_TREF]) {}
+        omega1(g[G_OMEGA1]), mu_ref(g[G_MUREF]), omega_v(g[G_OMEGAV]), T_ref(g[G_TREF]), C_s(g[G_CS]) {}
 };
 
 struct Num {
@@ -297,8 +297,12 @@ template <class S> Prim<S> primitives(const S* W, const Gas& g) {
   return p;
 }
 
-// Eq. 13 (VHS): mu = mu_ref (T_tr / T_ref)^omega;  tau = mu(T_tr) / p_tr (text after Eq. 12)
-template <class S> S viscosity(const S& Ttr, const Gas& g) { return g.mu_ref * pow(Ttr / g.T_ref, g.omega_v); }
+// Eq. 13 (VHS): mu = mu_ref (T_tr / T_ref)^omega;  Eq. 14 (Sutherland, when C_s > 0):
+// mu = mu_ref (T_tr / T_ref)^(3/2) (T_ref + C_s) / (T_tr + C_s);  tau = mu(T_tr) / p_tr (text after Eq. 12)
+template <class S> S viscosity(const S& Ttr, const Gas& g) {
+  if (g.C_s > 0.0) return g.mu_ref * pow(Ttr / g.T_ref, 1.5) * (g.T_ref + g.C_s) / (Ttr + g.C_s);
+  return g.mu_ref * pow(Ttr / g.T_ref, g.omega_v);
+}
 template <class S> S relax_time(const Prim<S>& p, const Gas& g) {
   return viscosity(p.Ttr, g) / (p.rho * g.R * p.Ttr);
 }
@@ -1082,8 +1086,8 @@ int32_t orc_cs_gradient(void* sp, int32_t param, int32_t wall_tag, int32_t ff_ta
     for (int d = 0; d < 3; ++d) bcflat.push_back(b.U[d]);
     bcflat.push_back(b.T);
   }
-  double gas[G_COUNT] = {s->gas.R, s->gas.gamma, s->gas.Z, s->gas.delta, s->gas.omega0,
-                         s->gas.omega1, s->gas.mu_ref, s->gas.omega_v, s->gas.T_ref};
+  double gas[G_COUNT] = {s->gas.R,      s->gas.gamma,  s->gas.Z,       s->gas.delta, s->gas.omega0,
+                         s->gas.omega1, s->gas.mu_ref, s->gas.omega_v, s->gas.T_ref, s->gas.C_s};
   double num[N_COUNT] = {s->num.cfl, s->num.inv_dt, s->num.cfl_imp, s->num.lim_K, double(s->num.limiter),
                          double(s->num.n_macro), double(s->num.n_micro), s->num.snap, double(s->num.exact_jvp)};
   Solver<cplx> c(s->geo, gas, num, bcflat.data(), int(s->bcs.size()));
@@ -1138,8 +1142,8 @@ void orc_steady_residual_jvp(void* sp, int32_t wall_tag, int32_t ff_tag, const d
     for (int d = 0; d < 3; ++d) bcflat.push_back(b.U[d]);
     bcflat.push_back(b.T);
   }
-  double gas[G_COUNT] = {s->gas.R, s->gas.gamma, s->gas.Z, s->gas.delta, s->gas.omega0,
-                         s->gas.omega1, s->gas.mu_ref, s->gas.omega_v, s->gas.T_ref};
+  double gas[G_COUNT] = {s->gas.R,      s->gas.gamma,  s->gas.Z,       s->gas.delta, s->gas.omega0,
+                         s->gas.omega1, s->gas.mu_ref, s->gas.omega_v, s->gas.T_ref, s->gas.C_s};
   double num[N_COUNT] = {s->num.cfl, s->num.inv_dt, s->num.cfl_imp, s->num.lim_K, double(s->num.limiter),
                          double(s->num.n_macro), double(s->num.n_micro), s->num.snap, double(s->num.exact_jvp)};
   Solver<cplx> c(s->geo, gas, num, bcflat.data(), int(s->bcs.size()));

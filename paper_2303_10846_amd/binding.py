@@ -40,7 +40,7 @@ class CisError(RuntimeError):
 
 class Gas(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("R", "gamma", "Z", "delta", "omega0", "omega1", "mu_ref", "omega_vhs",
-                                          "T_ref")]
+                                          "T_ref", "C_s")]
 
 
 class Numerics(C.Structure):
@@ -178,7 +178,7 @@ def _ptr(t):
 
 def gas_struct(gas: dict) -> Gas:
     return Gas(*(float(gas[k]) for k in ("R", "gamma", "Z", "delta", "omega0", "omega1", "mu_ref", "omega_vhs",
-                                         "T_ref")))
+                                         "T_ref")), float(gas.get("C_s", 0.0)))
 
 
 def numerics_struct(num: dict) -> Numerics:

@@ -172,7 +172,7 @@ template <bool HasV> __global__ __launch_bounds__(kBlock) void k_cell_vjp(Dev d,
     gp[2] = s[2] + s[15];
     gp[3] = s[3] + s[16];
     gp[4] = s[4] - vW[5] * p.rho * g.R * z2;
-    gp[5] = s[5] + taubar * tau * (g.omega_v - 1.0) / p.Ttr;
+    gp[5] = s[5] + taubar * tau * (visc_exponent(p.Ttr, g) - 1.0) / p.Ttr;
     gp[6] = s[6] - vW[5] * p.rho * g.R * z1;
     double gW[6] = {0, 0, 0, 0, 0, 0};
     prim_vjp(W, g.R, gp, gW);

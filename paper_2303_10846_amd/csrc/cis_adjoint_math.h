@@ -161,7 +161,13 @@ __host__ __device__ inline void face_state(const S* S1, const S* S2, double s, c
   const S rR = rho * S(g.R);
   const S T = S(0.4) * (E - ke) / rR;
   const S Ttr_bar = S(2.0 / 3.0) * (E - ke - Er) / rR;
-  tau = S(g.mu_ref * pow(g.T_ref, -g.omega_v)) * powd(Ttr_bar, g.omega_v) / (rR * Ttr_bar);
+  if (g.C_s > 0.0) {
+    // Eq. 14
+    const S x = Ttr_bar / S(g.T_ref);
+    tau = S(g.mu_ref * (g.T_ref + g.C_s)) * powd(x, 1.5) / ((Ttr_bar + S(g.C_s)) * rR * Ttr_bar);
+  } else {
+    tau = S(g.mu_ref * pow(g.T_ref, -g.omega_v)) * powd(Ttr_bar, g.omega_v) / (rR * Ttr_bar);
+  }
   const S Erot = (S(g.Z) * tau * Er + S(s) * rR * T) / (S(g.Z) * tau + S(s));
   const S den_tr = tau + S(s) - S((s / 3.0) * (1.0 - 1.0 / g.Z + g.omega0 / g.Z));
   const S den_rot = tau + S(s) - S(s * (1.0 - g.delta) * (1.0 - 1.0 / g.Z + g.omega1 / g.Z));

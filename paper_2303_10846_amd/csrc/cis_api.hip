@@ -475,7 +475,8 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   if (!buf->G || !buf->R || !buf->dG || !buf->dR || !buf->resG || !buf->resR || !buf->faceG || !buf->faceR || !buf->W ||
       !buf->q || !buf->upwind)
     return fail(CIS_E_INVALID_ARG, "a device buffer is NULL");
-  if (!(gas->R > 0) || !(gas->gamma > 1) || !(gas->Z > 0) || !(gas->mu_ref > 0) || !(gas->T_ref > 0))
+  if (!(gas->R > 0) || !(gas->gamma > 1) || !(gas->Z > 0) || !(gas->mu_ref > 0) || !(gas->T_ref > 0) ||
+      !(gas->C_s >= 0) || !std::isfinite(gas->C_s))
     return fail(CIS_E_INVALID_ARG, "gas constants out of range");
   if (dv->n > (int64_t)max_velocities())
     return fail(CIS_E_UNSUPPORTED, "velocity set larger than " + std::to_string(max_velocities()));
@@ -654,7 +655,8 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   d.dvs = s->d_dvs;
   d.dvs_f = s->d_dvs_f;
   d.bc = s->d_bc;
-  d.gas = GasC{gas->R, gas->gamma, gas->Z, gas->delta, gas->omega0, gas->omega1, gas->mu_ref, gas->omega_vhs, gas->T_ref};
+  d.gas = GasC{gas->R,      gas->gamma,  gas->Z,         gas->delta, gas->omega0,
+               gas->omega1, gas->mu_ref, gas->omega_vhs, gas->T_ref, gas->C_s};
   d.umax = dv->umax;
   fill_dev_numerics(s);
   s->buf = Bufs{buf->G, buf->R, buf->dG, buf->dR, buf->resG, buf->resR, buf->faceG, buf->faceR, buf->W, buf->q};

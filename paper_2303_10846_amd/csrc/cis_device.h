@@ -133,9 +133,18 @@ __device__ inline Prim prim_of(const double* W, double R) {
   return p;
 }
 
-// Eq. 13, mu_ref (T_tr/T_ref)^omega as exp(omega log(T_tr/T_ref)): a few ulp, and far fewer registers than the
-// double-double pow of the math library (the face pass computes it once per face inside a wide kernel)
-__device__ inline double visc(double Ttr, const GasC& g) { return g.mu_ref * exp(g.omega_v * log(Ttr / g.T_ref)); }
+// Viscosity.  Eq. 13 (VHS), mu_ref (T_tr/T_ref)^omega as exp(omega log(T_tr/T_ref)): a few ulp, and far fewer
+// registers than the double-double pow of the math library (the face pass computes it once per face inside a
+// wide kernel).  Eq. 14 (Sutherland, C_s > 0): mu_ref x^(3/2) (T_ref + C_s)/(T_tr + C_s), x = T_tr/T_ref.
+__device__ inline double visc(double Ttr, const GasC& g) {
+  const double x = Ttr / g.T_ref;
+  if (g.C_s > 0.0) return g.mu_ref * x * sqrt(x) * (g.T_ref + g.C_s) / (Ttr + g.C_s);
+  return g.mu_ref * exp(g.omega_v * log(x));
+}
+// d ln(mu) / d ln(T_tr): omega (VHS), 3/2 - T_tr/(T_tr + C_s) (Sutherland)
+__device__ inline double visc_exponent(double Ttr, const GasC& g) {
+  return g.C_s > 0.0 ? 1.5 - Ttr / (Ttr + g.C_s) : g.omega_v;
+}
 
 // (2 pi R T)^-3/2
 __device__ inline double maxwell_norm(double RT) {

@@ -45,7 +45,7 @@ constexpr int BCW = 8;
 constexpr int ER = 32;
 
 struct GasC {
-  double R, gamma, Z, delta, omega0, omega1, mu_ref, omega_v, T_ref;
+  double R, gamma, Z, delta, omega0, omega1, mu_ref, omega_v, T_ref, C_s;  // C_s > 0: Sutherland (Eq. 14)
 };
 
 struct Dev {

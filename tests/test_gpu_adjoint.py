@@ -44,7 +44,13 @@ CASES = {
     "open_box_lim1": (lambda: _open_box(1), 1, 2),
     "cavity_lid": (lambda: configs.cavity_case(n=2, nv_side=5), 2, 99),       # moving hot-side wall, nv = 125
     "small_sphere": (lambda: configs.small_sphere_case(), 1, 2),
+    "open_box_sutherland": (lambda: _sutherland(_open_box(1), 0.8), 1, 2),   # Eq. 14 viscosity, limiter on
 }
+
+
+def _sutherland(case, C_s):
+    case["gas"] = dict(case["gas"], C_s=C_s)
+    return case
 
 
 def _pair(case, warm):

@@ -54,7 +54,13 @@ CASES = {
     "cavity_n3_dvs7": lambda: configs.cavity_case(n=3, nv_side=7),          # nv = 343, ragged tail
     "open_box_n3": lambda: configs.open_box_case(n=3, nv_side=6),           # far field + hot wall
     "small_sphere": lambda: configs.small_sphere_case(),                    # unstructured DVS, 1944 tets
+    "small_sphere_sutherland": lambda: _sutherland(configs.small_sphere_case(), 0.5),   # Eq. 14 viscosity
 }
+
+
+def _sutherland(case, C_s):
+    case["gas"] = dict(case["gas"], C_s=C_s)
+    return case
 
 
 @pytest.mark.parametrize("name", list(CASES))
