@@ -319,7 +319,12 @@ def test_p5_micro_sgs_converges_to_dense_solve_of_eq33():
                 M[j, j] += g["A"][f] / g["V"][j] * max(-un, 0.0)
                 M[i, j] += g["A"][f] / g["V"][i] * min(un, 0.0)
                 M[j, i] += g["A"][f] / g["V"][j] * min(-un, 0.0)
-        # P6: row sums of the transport part vanish for interior cells (closure), so M 1 >= diag part
+        # P6: on a cell with no boundary face, Delta phi = const gives (1/dt + 1/tau~) const: the transport
+        # part of each row sums to (1/V) u . sum_f A_f n_f = 0 (closure of the oracle's face geometry)
+        interior = np.ones(nc, dtype=bool)
+        interior[g["fo"][g["fn"] < 0]] = False
+        rows = M @ np.ones(nc) - (c["num"]["inv_dt"] + 1.0 / tau)
+        assert interior.any() and np.max(np.abs(rows[interior])) < 1e-12 * np.max(np.abs(M))
         x = np.linalg.solve(M, Res[:, k])
         assert rel(dG[:, k], x) < 1e-12
 
