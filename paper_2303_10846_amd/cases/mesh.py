@@ -128,18 +128,46 @@ def _kempe_free(x, nbr, color, top, max_chain=4096):
     return False
 
 
-def color_major(xyz: np.ndarray, tets: np.ndarray):
+def _greedy_colours(nbr, order, n):
+    """First-fit colouring of the cells in `order` (colours as bit positions of a small mask)."""
+    color = [-1] * n
+    for i in order:
+        used = 0
+        for j in nbr[i]:
+            cj = color[j]
+            if cj >= 0:
+                used |= 1 << cj
+        c = 0
+        while used >> c & 1:
+            c += 1
+        color[i] = c
+    return np.array(color, dtype=np.int64)
+
+
+def _sweep_cost(color):
+    """Cell relaxations of two forward + backward colour pairs with the classes ordered second largest first and
+    largest last: the last class is relaxed twice, the first three times, the others four times."""
+    s = np.sort(np.bincount(color))[::-1]
+    return 2 * s[0] + (3 * s[1] if len(s) > 1 else 0) + 4 * int(s[2:].sum())
+
+
+def color_major(xyz: np.ndarray, tets: np.ndarray, search_cells: int = 150_000):
     """Colouring of the face-adjacency graph and colour-major renumbering.
 
-    Cells are first put in Morton order of their centroids (locality) and coloured greedily (first fit) in
-    that order.  While the highest colour class is small (under 5% of the cells), its cells are moved to
-    lower colours by Kempe-chain interchanges, which removes that class.  The classes are then ordered so
-    that the largest comes last and the second largest first.  A forward + backward pair of colour sweeps
-    relaxes the last class once at the turn (its second relaxation would repeat the first bit for bit) and,
-    from the second pair on, the first class once at the other turn, so large end classes mean fewer
-    relaxations per pair.  Cells keep their Morton order within a class.  Returns (tets_reordered,
-    color_offsets) with color_offsets[c]..color_offsets[c+1] the cells of colour c.  No two cells of one
-    colour share a face.
+    1. Cells are put in Morton order of their centroids (locality) and coloured greedily (first fit).
+    2. Meshes of up to `search_cells` cells: iterated greedy recolouring (Culberson's method: recolour first fit
+       with the cells taken class by class, the classes largest first or in a seeded random order), which never
+       adds a colour, until three colours are reached (a face graph with odd cycles needs three); then a few
+       more rounds keep the three-colouring with the fewest sweep relaxations (_sweep_cost).
+    3. Otherwise, a sparse highest class (under 5% of the cells) is removed by Kempe-chain interchanges while
+       that succeeds.
+    4. The classes are ordered so that the largest comes last and the second largest first.  A forward +
+       backward pair of colour sweeps relaxes the last class once at the turn (its second relaxation would
+       repeat the first bit for bit) and, from the second pair on, the first class once at the other turn, so
+       large end classes mean fewer relaxations per pair; fewer colours mean fewer sweep launches.
+
+    Cells keep their Morton order within a class.  Returns (tets_reordered, color_offsets) with
+    color_offsets[c]..color_offsets[c+1] the cells of colour c.  No two cells of one colour share a face.
     """
     nt = len(tets)
     cen = xyz[tets].mean(axis=1)
@@ -158,13 +186,31 @@ def color_major(xyz: np.ndarray, tets: np.ndarray):
     for a, b in pairs.tolist():
         nbr[a].append(b)
         nbr[b].append(a)
-    color = np.full(nt, -1, dtype=np.int64)
-    for i in range(nt):
-        used = {color[j] for j in nbr[i] if color[j] >= 0}
-        c = 0
-        while c in used:
-            c += 1
-        color[i] = c
+    color = _greedy_colours(nbr, range(nt), nt)
+
+    def reorder(col, rng, largest_first):
+        classes = [np.nonzero(col == k)[0] for k in range(int(col.max()) + 1)]
+        perm = (np.argsort([-len(x) for x in classes], kind="stable") if largest_first
+                else rng.permutation(len(classes)))
+        return _greedy_colours(nbr, np.concatenate([classes[k] for k in perm]), nt)
+
+    if nt <= search_cells:
+        rng = np.random.default_rng(0)
+        for it in range(400):
+            if color.max() + 1 <= 3:
+                break
+            new = reorder(color, rng, largest_first=(it % 2 == 0))
+            if new.max() <= color.max():
+                color = new
+        if color.max() + 1 == 3:
+            best, cur = color, color
+            for it in range(30):
+                new = reorder(cur, rng, largest_first=(it % 3 != 0))
+                if new.max() + 1 == 3:
+                    cur = new
+                    if _sweep_cost(cur) < _sweep_cost(best):
+                        best = cur
+            color = best
     ncol = int(color.max()) + 1
     while ncol > 2:
         top = ncol - 1
