@@ -28,13 +28,6 @@ constexpr int FGW = 8;
 constexpr int DVS_ARRAYS = 6;
 constexpr int DVS_F_ARRAYS = 3;
 
-// Colour offsets passed by value to the cooperative sweep kernel.
-constexpr int kMaxColors = 15;
-struct ColorOff {
-  int n;
-  int64_t off[kMaxColors + 1];
-};
-
 // Boundary-condition record: [0] kind  [1] rho  [2..4] U  [5] T  [6..7] unused
 constexpr int BCW = 8;
 

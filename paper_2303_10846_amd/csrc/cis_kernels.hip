@@ -2,7 +2,9 @@
 // (arXiv 2303.10846, Sec. 3.5, Steps 2-6).
 //
 // Layout: distributions are [cell][velocity] rows (velocity contiguous); the
-// discrete velocity set is stored as separate coalesced arrays.  Kernels that
+// discrete velocity set is stored as separate coalesced arrays; the sign of u.n
+// through each face of each cell is precomputed once per state (upwind codes,
+// read by the reconstruction and the micro sweeps).  Kernels that
 // read neighbour rows (reconstruction, micro residual, micro sweeps) run one
 // workgroup per (cell, velocity chunk) in chunk-major order, so one velocity
 // chunk of every row is touched within a short window; each thread issues all
@@ -13,7 +15,7 @@
 // the sums of the conservative update are compensated (TwoSum error terms).  The coloured
 // Gauss-Seidel sweeps update one colour at a time: cells of one colour share no
 // face.  Nothing here is a dense contraction; the kernels are bound by HBM
-// bandwidth, latency and (face pass) vector ALU, not MFMA.
+// bandwidth, latency and vector ALU, not MFMA.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -275,8 +277,8 @@ template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st
 // collision-coupled face distribution (Eq. 45), micro flux A (u.n) phi_f (written in place over phi_bar)
 // and the face's macro flux A sum_k w (u.n) Phi phi_f (Eq. 37).  Boundary faces: diffuse wall with rho_w
 // from zero net mass flux, or far-field Maxwellian, for incoming velocities.  phi_bar is staged in LDS
-// (UseLds) or re-read from global memory in pass 2; every velocity loop issues kUnroll independent loads per
-// trip.  The face sums are plain FP64 (each face flux is computed once and applied with opposite signs to its two
+// (UseLds) or re-read from global memory in pass 2; the interior passes issue the loads of Prefetch<T>
+// velocities per thread before their arithmetic, the other velocity loops kUnroll per trip.  The face sums are plain FP64 (each face flux is computed once and applied with opposite signs to its two
 // cells, so conservation does not depend on their rounding; compensating them was measured at +40% face time).
 // ---------------------------------------------------------------------------
 
@@ -989,7 +991,7 @@ void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
 
 // ---------------------------------------------------------------------------
 // Step 6: phi^{n+1} = phi^n + dphi and the integral error compensation (Eqs. 62-67), c = u - U~;
-// Step 7: per-cell |W^{n+1} - W^n|, reduced by k_reduce_res.  One 1024-thread workgroup per cell.
+// Step 7: per-cell |W^{n+1} - W^n|, reduced by k_reduce_res.  One workgroup per cell.
 // ---------------------------------------------------------------------------
 
 template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update(Dev d, Bufs b, Work w) {
