@@ -78,16 +78,18 @@ def run_path(case, precision, steps, warmup, converge_iters):
     from paper_2303_10846_amd.binding import Solver
     s = Solver(case, precision=precision, device="cuda:0")
     s.init_equilibrium(case["W0"])
+    hists = []
     if warmup:
-        s.iterate(warmup)
+        hists.append(s.iterate(warmup))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = s.iterate(steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    hists.append(hist)
     # stage times with hipEvents on the solver's stream, over a second timed region of the same length
     s.profile(True)
-    s.iterate(steps)
+    hists.append(s.iterate(steps))
     prof = s.profile_read()
     s.profile(False)
     # continue to the converged plateau for the comparison of the two precisions (not timed)
@@ -95,10 +97,14 @@ def run_path(case, precision, steps, warmup, converge_iters):
     while done < converge_iters:
         n = min(200, converge_iters - done)
         hist = s.iterate(n)
+        hists.append(hist)
         done += n
         print(f"bench: {precision} {done} iterations, residual {hist[-1].max():.3e}", file=sys.stderr, flush=True)
     W, q = s.moments()
     Qw = s.wall_heat_flux(1)
+    # iterations from rest until the residual (max over the six components) first falls below each level
+    res = np.concatenate(hists).max(axis=1)
+    to_level = {f"{lv:.0e}": (int(np.argmax(res <= lv)) + 1 if np.any(res <= lv) else None) for lv in (1e-4, 1e-5, 1e-6)}
     pairs = s.nc * s.nv
     es = 8 if precision == "fp64" else 4
     sb = stage_bytes(s.nc, s.nf, s.nv, es, sweep_cells(case["mesh"]["color_offsets"], case["num"]["n_micro"]))
@@ -114,7 +120,7 @@ def run_path(case, precision, steps, warmup, converge_iters):
     roof = roofline(dom, precision, sb[dom], prof[dom][0] / steps, prof[dom][1] / steps)
     out = dict(value=pairs * steps / t, ms_per_step=1e3 * t / steps, pairs=pairs, n_cells=s.nc, n_faces=s.nf,
                n_vel=s.nv, residual_last=float(hist[-1].max()), iterations=max(done, warmup + 2 * steps),
-               stages=stages, roofline=roof, Qw=Qw, W=W)
+               stages=stages, roofline=roof, Qw=Qw, W=W, iterations_to=to_level)
     del s
     torch.cuda.empty_cache()
     return out
@@ -202,7 +208,9 @@ def main():
                "Qw": abs(r["Qw"] - f["Qw"]) / abs(f["Qw"])}
         line["mixed_vs_fp64"] = dict(err, iterations=r["iterations"], residual_mixed=r["residual_last"],
                                      residual_fp64=f["residual_last"], Qw_fp64=f["Qw"],
-                                     matched_error=bool(max(err.values()) <= 1e-5))
+                                     matched_error=bool(max(err.values()) <= 1e-5),
+                                     iterations_to_residual_mixed=r["iterations_to"],
+                                     iterations_to_residual_fp64=f["iterations_to"])
     if not args.no_cpu:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(case)
