@@ -249,15 +249,19 @@ typedef struct {
 cis_status cis_adjoint_required_bytes(const cis_state* s, int32_t restart, int64_t* bytes);
 
 /* Discrete adjoint at the current (steady) state: solves (dR/dx)^T lam = (dJ/dx)^T by restarted GMRES
-   with a diagonal right preconditioner, then dJdp (host [3]) = dJ/dp - lam^T dR/dp for
+   with a right preconditioner, then dJdp (host [3]) = dJ/dp - lam^T dR/dp for
    p = (T_w, rho_inf, |U_inf|).  lam: device [2 n_cells n_vel + 12 n_cells] FP64, laid out as
    [lam_G | lam_R | lam_W | lam_q].  work: caller-owned device memory of at least
    cis_adjoint_required_bytes(restart).  J (host, or NULL) receives the objective.  Stops after max_iter
    Krylov iterations or when the true residual is below rtol relative to |dJ/dx|; info (or NULL) reports
-   which.  dJdp is only the steady-state derivative when R(x; p) is near zero. */
+   which.  dJdp is only the steady-state derivative when R(x; p) is near zero.
+   The preconditioner approximates the phi block of (dR/dx)^T by -(D + N^T), where -(D + N) is dR_phi/dphi
+   with first-order upwind faces (Eq. 32) and the collision term frozen, D_i = 1/tau_i + sum_f (A_f/V_i)
+   max(u.n, 0).  precond_pairs = 0 applies -D^-1; n > 0 applies n forward + backward Gauss-Seidel pairs over
+   the colours, from zero (0..64).  The W and q rows are left as they are. */
 cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int32_t restart, int32_t max_iter,
-                             double rtol, void* work, int64_t work_bytes, double* lam, double* dJdp, double* J,
-                             cis_adjoint_info* info);
+                             double rtol, int32_t precond_pairs, void* work, int64_t work_bytes, double* lam,
+                             double* dJdp, double* J, cis_adjoint_info* info);
 
 #ifdef __cplusplus
 }

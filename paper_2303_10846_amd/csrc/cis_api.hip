@@ -999,12 +999,12 @@ cis_status cis_adjoint_required_bytes(const cis_state* s, int32_t restart, int64
 }
 
 cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int32_t restart, int32_t max_iter,
-                             double rtol, void* work, int64_t work_bytes, double* lam, double* dJdp, double* J,
-                             cis_adjoint_info* info) {
+                             double rtol, int32_t precond_pairs, void* work, int64_t work_bytes, double* lam,
+                             double* dJdp, double* J, cis_adjoint_info* info) {
   if (!s || !work || !lam || !dJdp) return fail(CIS_E_INVALID_ARG, "NULL argument");
   if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the adjoint is FP64 only");
-  if (restart < 1 || restart > 1000 || max_iter < 0 || !(rtol > 0.0))
-    return fail(CIS_E_INVALID_ARG, "restart, max_iter or rtol out of range");
+  if (restart < 1 || restart > 1000 || max_iter < 0 || !(rtol > 0.0) || precond_pairs < 0 || precond_pairs > 64)
+    return fail(CIS_E_INVALID_ARG, "restart, max_iter, rtol or precond_pairs out of range");
   if (work_bytes < adjoint_doubles(s, restart) * (int64_t)sizeof(double))
     return fail(CIS_E_INVALID_ARG, "work buffer smaller than cis_adjoint_required_bytes");
   AdjSlots sl;
@@ -1020,6 +1020,12 @@ cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int
   hipStream_t q = s->stream;
   auto dots = [&](const double* Vb, int nvec, const double* w, double* host) {
     return dev_dots(s, Vb, N, nvec, w, part, hdev, host);
+  };
+  auto precond = [&](const double* in, double* out) {
+    if (precond_pairs == 0)
+      launch_precond(s->dev, s->buf, in, out, q);
+    else
+      launch_adj_sweeps(s->dev, s->buf, in, out, s->mesh->color_off.data(), s->mesh->n_colors, precond_pairs, q);
   };
   // right-hand side and the explicit parameter dependence of J
   double gpJ[3], gpL[3] = {0.0, 0.0, 0.0};
@@ -1043,7 +1049,7 @@ cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int
     for (int j = 0; j < m && iters < max_iter; ++j) {
       double* vj = V + (int64_t)j * N;
       double* w = V + (int64_t)(j + 1) * N;
-      launch_precond(s->dev, s->buf, vj, z, q);
+      precond(vj, z);
       run_vjp(s, z, 0.0, sl, w);
       // classical Gram-Schmidt, twice
       if ((st = dots(V, j + 1, w, h.data())) != CIS_OK) return st;
@@ -1082,7 +1088,7 @@ cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int
     HIP_TRY(hipMemcpyAsync(hdev, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, q));
     launch_axpby(N, 0.0, z, 0.0, z, q);
     launch_gemv_sub(V, N, jend, hdev, z, q);
-    launch_precond(s->dev, s->buf, z, V + (int64_t)m * N, q);
+    precond(z, V + (int64_t)m * N);
     launch_axpby(N, 1.0, V + (int64_t)m * N, 1.0, lam, q);
     // true residual r = b - A lam, and lam^T dR/dp
     run_vjp(s, lam, 0.0, sl, V);

@@ -112,6 +112,8 @@ struct AdjArgs {
 void launch_cell_steady(const Dev& d, const Bufs& b, double* rG, double* rR, double* rW, double* rq, hipStream_t st);
 void launch_vjp(const Dev& d, const Bufs& b, const AdjArgs& a, hipStream_t st);
 void launch_precond(const Dev& d, const Bufs& b, const double* in, double* out, hipStream_t st);
+void launch_adj_sweeps(const Dev& d, const Bufs& b, const double* in, double* out, const int64_t* color_off,
+                       int64_t n_colors, int n_pairs, hipStream_t st);
 void launch_dots(const double* V, int64_t n, int nvec, const double* w, double* part, double* out, hipStream_t st);
 void launch_gemv_sub(const double* V, int64_t n, int nvec, const double* h, double* w, hipStream_t st);
 void launch_axpby(int64_t n, double a, const double* x, double c, double* y, hipStream_t st);

@@ -142,6 +142,11 @@ def test_adjoint_gradient_matches_complex_step_and_finite_differences():
     a = s.adjoint(1, 2, restart=60, max_iter=3000, rtol=1e-12)
     say("adjoint iterations", a["iterations"], "rel residual", a["rel_residual"], "dJdp", a["dJdp"])
     assert a["converged"]
+    # the diagonal preconditioner reaches the same gradient in more iterations
+    a0 = s.adjoint(1, 2, restart=60, max_iter=3000, rtol=1e-12, precond_pairs=0)
+    say("diagonal preconditioner: iterations", a0["iterations"], "dJdp", a0["dJdp"])
+    assert a0["converged"] and a["iterations"] < a0["iterations"]
+    assert np.allclose(a0["dJdp"], a["dJdp"], rtol=1e-8, atol=0.0)
     # oracle: complex step through the iteration from the converged state
     o = oracle.Oracle(c)
     o.set_state(*base)
