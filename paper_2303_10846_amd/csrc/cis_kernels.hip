@@ -30,15 +30,19 @@
 namespace cis {
 
 // Velocities per thread in the (cell, chunk) kernels, chunk = kBlock * Vpt<T>: 2 in FP32, 1 in FP64 (measured
-// on the sphere workload: more velocities per thread raise the loads in flight but cost occupancy).
+// on the sphere workload: more velocities per thread raise the loads in flight but cost occupancy).  The
+// reconstruction and the micro sweep take one in both precisions (kVptOne: measured faster in FP32, micro
+// 3.84 -> 3.69 ms; the micro residual is faster with two).
 template <class T> struct Vpt;
 template <> struct Vpt<double> { static constexpr int v = 1; };
 template <> struct Vpt<float> { static constexpr int v = 2; };
+constexpr int kVptOne = 1;
 
-template <class T> static inline unsigned n_chunks(int64_t nv) {
-  constexpr int c = kBlock * Vpt<T>::v;
+template <int U> static inline unsigned n_chunks_u(int64_t nv) {
+  constexpr int c = kBlock * U;
   return (unsigned)((nv + c - 1) / c);
 }
+template <class T> static inline unsigned n_chunks(int64_t nv) { return n_chunks_u<Vpt<T>::v>(nv); }
 
 // (cell, chunk) workgroups run on a 1-D grid in chunk-major order: all cells of chunk 0, then of chunk 1, ...,
 // so that at any time the whole GPU works on one velocity chunk of every row (a slice that stays in the
@@ -64,8 +68,11 @@ template <class T, class F> __device__ inline void chunk_loop(int64_t nv, int64_
   }
 }
 
+template <int U> static inline dim3 cell_chunk_grid_u(int64_t ncells, int64_t nv) {
+  return dim3((unsigned)(padded_cells(ncells) * (int64_t)n_chunks_u<U>(nv)));
+}
 template <class T> static inline dim3 cell_chunk_grid(int64_t ncells, int64_t nv) {
-  return dim3((unsigned)(padded_cells(ncells) * (int64_t)n_chunks<T>(nv)));
+  return cell_chunk_grid_u<Vpt<T>::v>(ncells, nv);
 }
 
 
@@ -175,7 +182,7 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
 // Every load of a thread's velocities is issued before its first store (the stores could alias later loads
 // as far as the compiler knows); per-cell geometry is converted once into registers.
 template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b) {
-  constexpr int U = Vpt<T>::v;
+  constexpr int U = kVptOne;
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
   const int64_t i = d.spatial[cc.cell];
@@ -269,7 +276,7 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
 }
 
 template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_recon<T>, cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b);
+  hipLaunchKernelGGL(k_recon<T>, cell_chunk_grid_u<kVptOne>(d.nc, d.nv), dim3(kBlock), 0, st, d, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -904,7 +911,7 @@ __device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& i
 // (Relaxing several cells per workgroup with the next cell's loads issued ahead was measured slower.)
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, int64_t c0, int64_t cnext, int first) {
-  constexpr int U = Vpt<T>::v;
+  constexpr int U = kVptOne;
   const CellChunk cc = cell_chunk(cnext - c0);
   if (cc.cell >= cnext - c0) return;
   const int64_t nv = d.nv;
@@ -1058,7 +1065,7 @@ void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
   for (size_t p = 0; p < seq.size(); ++p) {
     const int64_t c = seq[p];
     const int64_t n = color_off[c + 1] - color_off[c];
-    hipLaunchKernelGGL(k_micro_sweep<T>, cell_chunk_grid<T>(n, d.nv), dim3(kBlock), 0, st, d, b, w, color_off[c],
+    hipLaunchKernelGGL(k_micro_sweep<T>, cell_chunk_grid_u<kVptOne>(n, d.nv), dim3(kBlock), 0, st, d, b, w, color_off[c],
                        color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
   }
 }
