@@ -97,6 +97,23 @@ def test_one_iteration_stage_by_stage_fp64(name):
     assert np.max(np.abs(hs - ho)) <= 1e-11 * np.max(np.abs(ho)) + 1e-20
 
 
+def test_lu_sgs_settings_one_pair_each_fp64():
+    """LU-SGS for both implicit systems: one forward + backward pair from zero (n_macro = n_micro = 1), which for
+    Eq. 33 is the LU-SGS step (D + L) D^-1 (D + U) dphi = Res; stage-by-stage against the oracle."""
+    c = configs.small_sphere_case()
+    say("case", c["name"], "n_macro = n_micro = 1")
+    num = dict(c["num"], n_macro=1, n_micro=1)
+    o, s = _pair(c, warm=3, num=num)
+    o.iterate(1)
+    s.iterate(1)
+    assert colrel(s.debug_stage("dW"), o.stage("dW")) < TOL
+    assert nrel(s.dG.cpu().numpy(), o.stage("dG")) < TOL
+    assert nrel(s.dR.cpu().numpy(), o.stage("dR")) < TOL
+    G, R, W, q = s.get_state()
+    Go, Ro, Wo, qo = o.get_state()
+    assert nrel(G, Go) < TOL and colrel(W, Wo) < TOL and colrel(q, qo) < 1e-10
+
+
 def test_cavity_full_config_200_iterations_fp64():
     """The 6x6x6x6-tet cavity with the 8^3 DVS (1296 x 512), 200 iterations from rest."""
     c = configs.cavity_case(seed=0)
