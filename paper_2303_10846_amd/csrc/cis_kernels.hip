@@ -821,13 +821,14 @@ void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, voi
 // ---------------------------------------------------------------------------
 
 // Per-cell operands of one relaxation.  The signs of u.n come from the upwind codes (the same decisions as in
-// every other kernel); the magnitudes are computed in the precision of the distributions: in FP64 exactly as
-// before, in the mixed mode in FP32 (the increments of the sweep only steer the iteration, its fixed point is
-// set by Res).
+// every other kernel); the magnitudes u.n are computed in the precision of the distributions (FP32 in the
+// mixed mode; the increments of the sweep only steer the iteration, its fixed point is set by Res).  The
+// diagonal D = 1/dt + 1/tau~ + sum_f (A/V) max(u.n, 0) is summed and inverted in FP64 in both modes.
 template <class T> struct MicroCell {
   const T *nG[4], *nR[4], *rG, *rR;
   T *oG, *oR;
-  T nx[4], ny[4], nz[4], av[4], base;
+  T nx[4], ny[4], nz[4], av[4];
+  double dbase;  // 1/dt + 1/tau~
   bool use[4];
 };
 
@@ -849,7 +850,7 @@ __device__ inline void micro_setup(const Dev& d, const Bufs& b, const Work& w, i
     c.nz[a] = (T)s[4];
     c.av[a] = (T)s[1];
   }
-  c.base = (T)w.mbase[i];
+  c.dbase = w.mbase[i];
   c.rG = (const T*)b.resG + i * nv;
   c.rR = (const T*)b.resR + i * nv;
   c.oG = (T*)b.dG + i * nv;
@@ -891,19 +892,19 @@ __device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& i
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (k[u] >= nvi) continue;
-    T D = c.base;
+    double D = c.dbase;
     T aG = in.xG[u], aR = in.xR[u];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      D += c.av[a] * in.pos[u][a];
+      D += (double)(c.av[a] * in.pos[u][a]);
       if (c.use[a] && ((code[u] >> (2 * a)) & 3u) == 2u) {
         aG -= c.av[a] * in.neg[u][a] * in.yG[u][a];
         aR -= c.av[a] * in.neg[u][a] * in.yR[u][a];
       }
     }
-    const T iD = T(1) / D;
-    c.oG[k[u]] = aG * iD;
-    c.oR[k[u]] = aR * iD;
+    const double iD = 1.0 / D;
+    c.oG[k[u]] = (T)((double)aG * iD);
+    c.oR[k[u]] = (T)((double)aR * iD);
   }
 }
 
