@@ -6,6 +6,9 @@ mixed-precision path (FP32 distributions and flux kernels, FP64 moments, macro s
 update) and the FP64 path.  Inputs are generated on the host and copied to HBM before the timed region; the
 timed region is K iterations on the GPU.  Both runs then continue to the converged plateau, where the mixed
 fields are compared with the FP64 ones ("at matched error").
+
+--workload capsule times the Ma 10 capsule instead (303 264 tets x 10 568 velocities, 3.2e9 pairs, about 156 GB
+of mixed-precision state), mixed precision only.
 """
 import argparse
 import json
@@ -48,7 +51,7 @@ STAGE_KERNEL = {"recon": "k_recon", "face": "k_face", "residual": "k_residual", 
                 "update": "k_update"}
 
 
-def roofline(stage, precision, alg_bytes_iter, ms_iter, launches_iter):
+def roofline(stage, precision, alg_bytes_iter, ms_iter, launches_iter, workload="sphere"):
     """Roofline of the dominant stage: algorithmic bytes per launch over the average launch duration (hipEvents
     on the library's stream), and the counter-measured HBM bytes per launch when the committed rocprofv3
     summary still matches the kernel sources."""
@@ -59,7 +62,7 @@ def roofline(stage, precision, alg_bytes_iter, ms_iter, launches_iter):
     out = {"kernel": STAGE_KERNEL[stage], "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": ach / HBM_PEAK_GBS, "traffic": None, "launches_per_iter": launches_iter,
            "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": t_launch * 1e6}
-    path = os.path.join(ROOT, "profiles", f"{stage}_{precision}_sphere_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"{stage}_{precision}_{workload}_counters.txt")
     if os.path.exists(path):
         c = prof_summary.read_counters(path)
         if c.get("source_sha256") == prof_summary.source_hash() and STAGE_KERNEL[stage] in c.get("kernel", ""):
@@ -72,7 +75,7 @@ def roofline(stage, precision, alg_bytes_iter, ms_iter, launches_iter):
     return out
 
 
-def run_path(case, precision, steps, warmup, converge_iters):
+def run_path(case, precision, steps, warmup, converge_iters, workload="sphere"):
     import torch
 
     from paper_2303_10846_amd.binding import Solver
@@ -117,7 +120,7 @@ def run_path(case, precision, steps, warmup, converge_iters):
         stages[k] = e
     hbm = {k: v for k, v in stages.items() if k in sb}
     dom = max(hbm, key=lambda k: hbm[k]["ms_per_iter"])
-    roof = roofline(dom, precision, sb[dom], prof[dom][0] / steps, prof[dom][1] / steps)
+    roof = roofline(dom, precision, sb[dom], prof[dom][0] / steps, prof[dom][1] / steps, workload)
     out = dict(value=pairs * steps / t, ms_per_step=1e3 * t / steps, pairs=pairs, n_cells=s.nc, n_faces=s.nf,
                n_vel=s.nv, residual_last=float(hist[-1].max()), iterations=max(done, warmup + 2 * steps),
                stages=stages, roofline=roof, Qw=Qw, W=W, iterations_to=to_level)
@@ -153,6 +156,9 @@ def main():
                     help="iterations (from rest) after which the two precisions' fields are compared")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--workload", choices=["sphere", "capsule"], default="sphere",
+                    help="sphere (the headline workload) or the Ma 10 capsule (303k tets x 10.6k velocities, "
+                         "mixed precision only: its FP64 state does not fit one GPU)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the DVS-sharded multi-GPU path is a design, not code); "
@@ -169,12 +175,19 @@ def main():
               file=sys.stderr, flush=True)
         del a, b
     from paper_2303_10846_amd.cases import configs
-    case = configs.sphere_case(seed=0)
+    if args.workload == "capsule":
+        if args.precision == "fp64":
+            print("bench.py: the capsule's FP64 state does not fit one GPU; use --precision mixed", file=sys.stderr)
+            sys.exit(2)
+        args.precision = "mixed"
+        args.no_cpu = True          # the oracle sample of this mesh does not fit the host's memory
+        args.converge_iters = 0
+    case = configs.sphere_case(seed=0) if args.workload == "sphere" else configs.capsule_case(seed=0)
     print(f"bench: {case['name']} tets={len(case['mesh']['tets'])} nv={len(case['u'])}", file=sys.stderr, flush=True)
     res = {}
     for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
         print(f"bench: timing {prec}", file=sys.stderr, flush=True)
-        res[prec] = run_path(case, prec, args.steps, args.warmup, args.converge_iters)
+        res[prec] = run_path(case, prec, args.steps, args.warmup, args.converge_iters, args.workload)
         print(f"bench: {prec} {res[prec]['ms_per_step']:.2f} ms/iter", file=sys.stderr, flush=True)
     main_key = "mixed" if "mixed" in res else "fp64"
     r = res[main_key]
@@ -183,7 +196,9 @@ def main():
         "value": r["value"], "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64" if main_key == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": "sphere Ma 5 Kn 0.1 Tw/Tinf 3, graded tets x unstructured DVS, from rest",
+        "config": {"workload": ("sphere Ma 5 Kn 0.1 Tw/Tinf 3, graded tets x unstructured DVS, from rest"
+                                if args.workload == "sphere" else
+                                "capsule Ma 10 Kn 0.01 Tw/Tinf 4.18, graded tets x unstructured DVS, from rest"),
                    "n_cells": r["n_cells"], "n_faces": r["n_faces"], "n_vel": r["n_vel"], "pairs": r["pairs"],
                    "precision": main_key, "n_macro_sweeps": case["num"]["n_macro"],
                    "n_micro_sweeps": case["num"]["n_micro"]},
