@@ -281,3 +281,36 @@ def test_no_micro_sweeps_means_zero_increments():
     Gs, Rs, Ws, qs = s.get_state()
     assert nrel(Gs, Go) < TOL and nrel(Rs, Ro) < TOL
     assert colrel(Ws, Wo) < TOL and colrel(qs, qo) < TOL
+
+
+@pytest.mark.parametrize("name", ["cavity_n3_dvs7", "small_sphere"])
+def test_upwind_codes_match_oracle_decisions(name):
+    """The per-(cell, velocity) upwind codes written by cis_state_create: for face slot a (the face opposite local
+    vertex a) 1 where u.n out of the cell exceeds the tie tolerance, 2 where it is below minus it, 0 otherwise,
+    against the oracle's geometry; and the two cells of an interior face see opposite codes."""
+    say("case", name, "upwind codes")
+    c = CASES[name]()
+    o = oracle.Oracle(c)
+    g = o.geometry()
+    s = solver(c)
+    codes = s.upwind.cpu().numpy().astype(np.int64)
+    u = np.asarray(c["u"], dtype=np.float64)
+    snap = c["num"]["snap"] * np.linalg.norm(u, axis=1)
+    nc = codes.shape[0]
+    want = np.zeros_like(codes)
+    for a in range(4):
+        f = g["cf"][:, a]
+        sign = np.where(g["fo"][f] == np.arange(nc), 1.0, -1.0)
+        un = (u @ g["n"][f].T).T * sign[:, None]                      # [nc][nv]
+        ca = np.where(un > snap[None, :], 1, np.where(un < -snap[None, :], 2, 0))
+        want |= ca << (2 * a)
+    assert np.array_equal(codes, want)
+    # opposite codes across every interior face
+    for a in range(4):
+        f = g["cf"][:, a]
+        j = np.where(g["fo"][f] == np.arange(nc), g["fn"][f], g["fo"][f])
+        inner = j >= 0
+        b = np.argmax(g["cf"][j[inner]] == f[inner, None], axis=1)
+        ci = (codes[inner] >> (2 * a)) & 3
+        cj = (codes[j[inner]] >> (2 * b[:, None])) & 3
+        assert np.array_equal(np.where(ci == 0, 0, 3 - ci), cj)
