@@ -140,9 +140,15 @@ def cpu_baseline(case, stride=8, iters=8):
     t = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     pairs = o.nc * o.nv
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": pairs * iters / t, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
             "sample": f"sphere mesh {o.nc} tets x every {stride}th DVS point ({o.nv} of {len(case['u'])}), "
-                      f"{iters} FP64 iterations from rest, {t:.1f} s"}
+                      f"{iters} FP64 iterations from rest, {t:.1f} s, {cores} OpenMP threads on {model}"}
 
 
 def main():
