@@ -12,6 +12,7 @@ of mixed-precision state), mixed precision only.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -129,8 +130,8 @@ def run_path(case, precision, steps, warmup, converge_iters, workload="sphere"):
     return out
 
 
-def cpu_baseline(case, stride=8, iters=8):
-    """The oracle on the sphere mesh with every `stride`-th velocity (a bounded sample), timed per iteration."""
+def _oracle_rate(case, stride, iters):
+    """Cell-velocity updates/s of the oracle on `case` with every `stride`-th velocity, and the seconds taken."""
     import oracle
     c = dict(case, u=case["u"][::stride], w=case["w"][::stride] * stride)
     o = oracle.Oracle(c)
@@ -138,17 +139,85 @@ def cpu_baseline(case, stride=8, iters=8):
     t0 = time.perf_counter()
     o.iterate(iters)
     t = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    pairs = o.nc * o.nv
+    return o.nc * o.nv * iters / t, t, o.nc, o.nv
+
+
+def cpu_baseline(case, stride=8, iters=8, stride_1t=32, iters_1t=2):
+    """The oracle on the sphere mesh with every `stride`-th velocity (a bounded sample), timed per iteration,
+    on all host threads; then on one thread with every `stride_1t`-th velocity."""
+    import oracle
+    cores = oracle.threads()
+    value, t, nc, nv = _oracle_rate(case, stride, iters)
+    oracle.threads(1)
+    try:
+        value_1t, t_1t, _, nv_1t = _oracle_rate(case, stride_1t, iters_1t)
+    finally:
+        oracle.threads(cores)
     model = "unknown CPU"
     try:
         with open("/proc/cpuinfo") as f:
             model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return {"value": pairs * iters / t, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"sphere mesh {o.nc} tets x every {stride}th DVS point ({o.nv} of {len(case['u'])}), "
-                      f"{iters} FP64 iterations from rest, {t:.1f} s, {cores} OpenMP threads on {model}"}
+    return {"value": value, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"sphere mesh {nc} tets x one DVS point in {stride} ({nv} of {len(case['u'])}), "
+                      f"{iters} FP64 iterations from rest, {t:.1f} s, {cores} OpenMP threads on {model}",
+            "single_thread": {"value": value_1t, "cores": 1,
+                              "sample": f"one DVS point in {stride_1t} ({nv_1t}), {iters_1t} iterations, "
+                                        f"{t_1t:.1f} s"}}
+
+
+# DVS sets of the velocity-space study on the sphere: (name, outer radius / sqrt(R T0), target count).  Like the
+# paper's capsule series (Sec. 4.4, Table 7), the first four shrink the spacing inside a ball of radius
+# 5 sqrt(R T0) and the last two shrink the ball to 4 and 3 sqrt(R T0); every set keeps the refined balls of
+# Eq. 74 at the free-stream and wall velocities.
+DVS_STUDY = (("V1", 5.0, 16000), ("V2", 5.0, 12000), ("V3", 5.0, 8000), ("V4", 5.0, 4096), ("V5", 4.0, 3000),
+             ("V6", 3.0, 2000))
+
+
+def dvs_study(iters):
+    """Aerodynamic coefficients of the Ma 5 sphere against the size and extent of the DVS (mixed precision,
+    `iters` iterations from rest each), with relative differences against the finest set."""
+    import torch
+
+    from paper_2303_10846_amd.binding import Solver, wall_coefficients
+    from paper_2303_10846_amd.cases import configs, dvs
+    case = configs.sphere_case(seed=0)
+    gas_R, T_inf, tw, mach = 0.5, 1.0, case["T_w"], case["mach"]
+    T0 = dvs.total_temperature(T_inf, mach)
+    rows = []
+    for name, factor, target in DVS_STUDY:
+        u, w = dvs.paper_unstructured_dvs(case["U_inf"], T_inf, tw, mach, factor, target=target)
+        c = dict(case, u=u, w=w)
+        print(f"bench: dvs study {name}: radius {factor} sqrt(R T0), {len(u)} velocities", file=sys.stderr,
+              flush=True)
+        s = Solver(c, precision="mixed", device="cuda:0")
+        s.init_equilibrium(c["W0"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, hist = 0, None
+        while done < iters:
+            n = min(200, iters - done)
+            hist = s.iterate(n)
+            done += n
+            print(f"bench: dvs study {name} {done} iterations, residual {hist[-1].max():.3e}", file=sys.stderr,
+                  flush=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        co = wall_coefficients(s.wall_loads(1), 1.0, case["U_inf"], T_inf, gas_R, A_ref=math.pi * 0.25)
+        rows.append(dict(name=name, radius_over_sqrt_RT0=factor,
+                         radius=factor * math.sqrt(gas_R * max(T0, tw)), n_vel=len(u),
+                         ball_volume_covered=float(w.sum() / (4.0 / 3.0 * math.pi *
+                                                              (factor * math.sqrt(gas_R * max(T0, tw))) ** 3)),
+                         Cd=co["Cd"], CQ=float(co["CQ"]), Cp_max=float(co["Cp"].max()), Ch_max=float(co["Ch"].max()),
+                         residual=float(hist[-1].max()), ms_per_iter=1e3 * t / iters))
+        del s
+        torch.cuda.empty_cache()
+    ref = rows[0]
+    for r in rows:
+        r["rel_diff_vs_" + ref["name"]] = {k: (r[k] - ref[k]) / abs(ref[k]) for k in ("Cd", "CQ", "Cp_max", "Ch_max")}
+    return {"study": "DVS size and extent, sphere Ma 5 Kn 0.1 Tw/Tinf 3", "n_cells": len(case["mesh"]["tets"]),
+            "iterations": iters, "precision": "mixed", "A_ref": "pi d^2 / 4", "sets": rows}
 
 
 def main():
@@ -165,6 +234,9 @@ def main():
     ap.add_argument("--workload", choices=["sphere", "capsule"], default="sphere",
                     help="sphere (the headline workload) or the Ma 10 capsule (303k tets x 10.6k velocities, "
                          "mixed precision only: its FP64 state does not fit one GPU)")
+    ap.add_argument("--dvs-study", type=int, default=0, metavar="ITERS",
+                    help="instead of timing, run the sphere with six DVS sets for ITERS iterations each and print "
+                         "the wall coefficients against the DVS")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the DVS-sharded multi-GPU path is a design, not code); "
@@ -180,6 +252,9 @@ def main():
         print(f"bench: copy probe {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written",
               file=sys.stderr, flush=True)
         del a, b
+    if args.dvs_study:
+        print(json.dumps(dvs_study(args.dvs_study)))
+        return
     from paper_2303_10846_amd.cases import configs
     if args.workload == "capsule":
         if args.precision == "fp64":

@@ -51,6 +51,8 @@ def _load():
     lib.orc_geom_create.argtypes = [d, C.c_int64, i32, C.c_int64, i32, i32, C.c_int64, d, d, C.c_int64,
                                     C.c_double, i32]
     lib.orc_geom_destroy.argtypes = [P]
+    lib.orc_threads.restype = C.c_int32
+    lib.orc_threads.argtypes = [C.c_int32]
     lib.orc_geom_counts.argtypes = [P, i64]
     lib.orc_geom_arrays.argtypes = [P, d, d, d, d, i64, i64, i64, i32, d, d, d, d]
     lib.orc_solver_create.restype = P
@@ -85,6 +87,11 @@ def _dp(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def threads(n: int = 0) -> int:
+    """Set the OpenMP thread count of the oracle's loops (n <= 0: unchanged); returns the count in force."""
+    return int(_load().orc_threads(n))
 
 
 def gas_array(gas: dict) -> np.ndarray:

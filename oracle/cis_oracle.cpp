@@ -964,6 +964,12 @@ void* orc_geom_create(const double* xyz, int64_t nn, const int32_t* tet, int64_t
 
 void orc_geom_destroy(void* g) { delete static_cast<Geom*>(g); }
 
+// OpenMP thread count of the oracle's parallel loops (n <= 0 leaves it); returns the count now in force.
+int32_t orc_threads(int32_t n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
+
 // counts: nc, nf, n_interior, nv
 void orc_geom_counts(void* gp, int64_t* out) {
   Geom* g = static_cast<Geom*>(gp);
