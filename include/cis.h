@@ -71,7 +71,10 @@ typedef struct {
               s_ij = min(dt_i, dt_j) (Eq. 45).
    inv_dt, cfl_imp : implicit time step of Eqs. 29 and 34, one per cell,
               1/dt_i = inv_dt + max_k|u_k| / (cfl_imp h_i) (second term dropped when cfl_imp = 0).
-   lim_K    : Venkatakrishnan constant, eps^2 = (K h)^3 max_stencil|phi|^2; limiter = 0 turns it off.
+   lim_K    : Venkatakrishnan constant, eps^2 = (K h)^3 max_stencil|phi|^2.
+   limiter  : 0 off; 1 Venkatakrishnan, differentiated by cis_residual_vjp on the branch the state takes;
+              2 the same limiter in the iteration, held fixed (frozen) by cis_residual_vjp, whose product is
+              then the derivative of the scheme with the limiter values of the current state.
    snap     : |u.n| <= snap |u| counts as u.n = 0 (upwind side x_j, Eq. 46).
    n_macro, n_micro : forward+backward sweep pairs of the macro (Eq. 43) and micro (Eq. 33) PR-SGS. */
 typedef struct {
@@ -233,7 +236,7 @@ cis_status cis_steady_residual(cis_state* s, int32_t wall_tag, double* rG, doubl
    vG, vR, vW, vq are all set or all NULL (v = 0, e.g. for dJ/dx alone with cJ = 1).  Outputs must not
    overlap the inputs.  Faces whose tag is not wall_tag / ff_tag contribute nothing to gp; a tag of -1
    means none (wall_tag must exist when cJ != 0).  The limiter (Eq. 46) is differentiated on the branch
-   that the current state takes. */
+   that the current state takes (numerics.limiter = 1) or held fixed (numerics.limiter = 2). */
 cis_status cis_residual_vjp(cis_state* s, const double* vG, const double* vR, const double* vW, const double* vq,
                             double cJ, int32_t wall_tag, int32_t ff_tag, double* gG, double* gR, double* gW,
                             double* gq, double* gp);
@@ -244,8 +247,8 @@ typedef struct {
   double rel_residual;
 } cis_adjoint_info;
 
-/* Device workspace of cis_adjoint_solve for GMRES(restart), in bytes: (restart + 3) vectors of
-   2 n_cells n_vel + 12 n_cells doubles, plus reduction scratch. */
+/* Device workspace of cis_adjoint_solve for GMRES(restart), in bytes: (restart + 4) vectors of
+   2 n_cells n_vel + 12 n_cells doubles, plus reduction scratch and 24 doubles per cell. */
 cis_status cis_adjoint_required_bytes(const cis_state* s, int32_t restart, int64_t* bytes);
 
 /* Discrete adjoint at the current (steady) state: solves (dR/dx)^T lam = (dJ/dx)^T by restarted GMRES
@@ -258,10 +261,17 @@ cis_status cis_adjoint_required_bytes(const cis_state* s, int32_t restart, int64
    The preconditioner approximates the phi block of (dR/dx)^T by -(D + N^T), where -(D + N) is dR_phi/dphi
    with first-order upwind faces (Eq. 32) and the collision term frozen, D_i = 1/tau_i + sum_f (A_f/V_i)
    max(u.n, 0).  precond_pairs = 0 applies -D^-1; n > 0 applies n forward + backward Gauss-Seidel pairs over
-   the colours, from zero (0..64).  The W and q rows are left as they are. */
+   the colours, from zero (0..64).
+   macro_pairs = 0: the W and q rows are left as they are.  macro_pairs > 0 (up to 200) selects the block
+   preconditioner over (phi, W, q): the W and q rows are eliminated exactly (their diagonal block taken as the
+   identity), and the phi Schur complement is approximated by the transpose of the linearised implicit step
+   of Steps 4-5: the transport solve above, then the steady macroscopic system of Eq. 43 (no 1/dt term),
+   transposed, with macro_pairs forward + backward PR-SGS pairs, whose correction is spread back over the
+   velocities through the conserved moments.  Errors: CIS_E_INVALID_ARG for NULL pointers, a short work
+   buffer or counts out of range; CIS_E_UNSUPPORTED in the mixed mode; CIS_E_DEVICE on a HIP error. */
 cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int32_t restart, int32_t max_iter,
-                             double rtol, int32_t precond_pairs, void* work, int64_t work_bytes, double* lam,
-                             double* dJdp, double* J, cis_adjoint_info* info);
+                             double rtol, int32_t precond_pairs, int32_t macro_pairs, void* work,
+                             int64_t work_bytes, double* lam, double* dJdp, double* J, cis_adjoint_info* info);
 
 #ifdef __cplusplus
 }

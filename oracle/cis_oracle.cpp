@@ -569,6 +569,9 @@ template <class S> struct Solver {
               }
               if (re(psi) < re(L)) L = psi;  // reading: L = min(1, min_f psi_f)
             }
+            // limiter = 2: the same L in the iteration, held fixed in derivatives (frozen limiter), so a
+            // complex step carries none of it
+            if (num.limiter == 2) L = S(re(L));
           }
           for (int d = 0; d < 3; ++d) out[3 * (size_t(i) * nv + k) + d] = L * gr[d];
         }

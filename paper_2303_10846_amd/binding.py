@@ -152,7 +152,8 @@ def load(allow_build: bool = True):
     lib.cis_adjoint_required_bytes.restype = st
     lib.cis_adjoint_required_bytes.argtypes = [P, C.c_int32, i64]
     lib.cis_adjoint_solve.restype = st
-    lib.cis_adjoint_solve.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32, P,
+    lib.cis_adjoint_solve.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                      C.c_int32, P,
                                       C.c_int64, P, d, d, C.POINTER(AdjointInfo)]
     _lib = lib
     return lib
@@ -423,10 +424,11 @@ class Solver:
         return gG, gR, gW, gq, gp
 
     def adjoint(self, wall_tag: int, ff_tag: int = -1, restart: int = 60, max_iter: int = 3000,
-                rtol: float = 1e-11, precond_pairs: int = 2) -> dict:
+                rtol: float = 1e-11, precond_pairs: int = 2, macro_pairs: int = 0) -> dict:
         """Discrete adjoint at the current state: dJ/dp for p = (T_w, rho_inf, |U_inf|), J and lambda.
         precond_pairs: Gauss-Seidel pairs of the transposed upwind transport operator as GMRES preconditioner
-        (0: its diagonal)."""
+        (0: its diagonal).  macro_pairs > 0: block preconditioner over (phi, W, q), with that many transposed
+        macro-system pairs after the transport sweeps."""
         t = self.torch
         nb = C.c_int64(0)
         _check(self.lib.cis_adjoint_required_bytes(self.h, int(restart), C.byref(nb)))
@@ -436,7 +438,8 @@ class Solver:
         J = C.c_double(0.0)
         info = AdjointInfo()
         _check(self.lib.cis_adjoint_solve(self.h, int(wall_tag), int(ff_tag), int(restart), int(max_iter),
-                                          float(rtol), int(precond_pairs), _ptr(work), nb.value, _ptr(lam),
+                                          float(rtol), int(precond_pairs), int(macro_pairs), _ptr(work),
+                                          nb.value, _ptr(lam),
                                           _dp(dJdp), C.byref(J), C.byref(info)))
         return dict(dJdp=dJdp, J=J.value, lam=lam, iterations=info.iterations, converged=bool(info.converged),
                     rel_residual=info.rel_residual)

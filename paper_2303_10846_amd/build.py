@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libcis.so")
 SOURCES = [os.path.join(CSRC, n) for n in ("cis_api.hip", "cis_kernels.hip", "cis_adjoint.hip")]
-HEADERS = [os.path.join(CSRC, n) for n in ("cis_internal.h", "cis_device.h", "cis_adjoint_math.h")] + [
+HEADERS = [os.path.join(CSRC, n) for n in ("cis_internal.h", "cis_device.h", "cis_adjoint_math.h", "cis_adjoint.h")] + [
     os.path.join(os.path.dirname(HERE), "include", "cis.h")]
 
 FLAGS = [

@@ -17,6 +17,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "cis_adjoint.h"
 #include "cis_adjoint_math.h"
 #include "cis_device.h"
 #include "cis_internal.h"
@@ -110,9 +111,11 @@ void launch_cell_steady(const Dev& d, const Bufs& b, double* rG, double* rR, dou
 
 // ---------------------------------------------------------------------------
 // VJP, cell terms: everything of R_phi, R_W, R_q except the micro flux.  Writes gG, gR (plain stores), gW, gq.
+// PhiOnly: the seed is (vG, vR) alone and only gW, gq are written, i.e. (dR_phi/d(W, q))^T v_phi.
 // ---------------------------------------------------------------------------
 
-template <bool HasV> __global__ __launch_bounds__(kBlock) void k_cell_vjp(Dev d, Bufs b, AdjArgs a) {
+template <bool HasV, bool PhiOnly = false>
+__global__ __launch_bounds__(kBlock) void k_cell_vjp(Dev d, Bufs b, AdjArgs a) {
   __shared__ double red[(kBlock / 64) * 2 * 17];
   const int64_t i = blockIdx.x, nv = d.nv;
   const GasC& g = d.gas;
@@ -125,8 +128,8 @@ template <bool HasV> __global__ __launch_bounds__(kBlock) void k_cell_vjp(Dev d,
   e.setup(th, g);
   double vW[6], vq[6];
   for (int m = 0; m < 6; ++m) {
-    vW[m] = HasV ? a.vW[6 * i + m] : 0.0;
-    vq[m] = HasV ? a.vq[6 * i + m] : 0.0;
+    vW[m] = HasV && !PhiOnly ? a.vW[6 * i + m] : 0.0;
+    vq[m] = HasV && !PhiOnly ? a.vq[6 * i + m] : 0.0;
   }
   const double* G = (const double*)b.G + i * nv;
   const double* R = (const double*)b.R + i * nv;
@@ -144,8 +147,10 @@ template <bool HasV> __global__ __launch_bounds__(kBlock) void k_cell_vjp(Dev d,
     // -(dR/dphi_k)^T v: the collision term, the moments of R_W and the heat-flux sums of R_q
     const double aG = vg * it + v.w * (vW[0] + vW[1] * v.ux + vW[2] * v.uy + vW[3] * v.uz + vW[4] * v.h2 + 0.5 * c2 * vqc);
     const double aR = vr * it + v.w * (vW[4] + vW[5] + vq[3] * cx + vq[4] * cy + vq[5] * cz);
-    a.gG[i * nv + k] = -aG;
-    a.gR[i * nv + k] = -aR;
+    if (!PhiOnly) {
+      a.gG[i * nv + k] = -aG;
+      a.gR[i * nv + k] = -aR;
+    }
 #pragma unroll
     for (int m = 0; m < NTH; ++m) acc.add(m, aG * dG[m] + aR * dR[m]);
     acc.add(13, -(vg * (Gs - gk) + vr * (Rs - rk)) * it * it);
@@ -536,7 +541,8 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
     }
   };
   double grx = L * gbx, gry = L * gby, grz = L * gbz;
-  if (amin >= 0) {
+  // the limiter's own derivative; limiter = 2 holds L fixed (frozen-limiter linearisation)
+  if (amin >= 0 && d.limiter != 2) {
     const double Lb = gbx * gx + gby * gy + gbz * gz;
     const double d1 = d1m, d2 = d2m;
     const double N = (d1 * d1 + eps2) * d2 + 2.0 * d2 * d2 * d1;
@@ -639,6 +645,168 @@ __global__ __launch_bounds__(kBlock) void k_precond(Dev d, Bufs b, const double*
 void launch_precond(const Dev& d, const Bufs& b, const double* in, double* out, hipStream_t st) {
   const unsigned nch = (unsigned)std::min<int64_t>((d.nv + kBlock - 1) / kBlock, 64);
   hipLaunchKernelGGL(k_precond, dim3((unsigned)d.nc, nch), dim3(kBlock), 0, st, d, b, in, out);
+}
+
+// ---------------------------------------------------------------------------
+// Block preconditioner over (phi, Y = (W, q)).  With x = (phi, Y), dR/dx = [[A, B], [C, E]] where B = dR_phi/dY
+// and C = dR_Y/dphi = -M (the moment and heat-flux sums of R_W, R_q) are cell-local and E ~ I.  For
+// (dR/dx)^T x = s, eliminating Y gives
+//   S x_phi = s_phi + M^T s_Y,  S = (A - B C)^T,   x_Y = s_Y - B^T x_phi.
+// A - B C is the collision-coupled transport operator whose slow modes are the macroscopic ones; the implicit
+// step of Steps 4-5 linearised, (D + N)^-1 [I + (1/tau) dphi*/dW Mac^-1 M_c] (macro system of Eq. 43, then the
+// micro system of Eq. 33 with the predicted equilibrium), approximates -(A - B C)^-1, so
+//   x_phi = z + M_c^T Mac^-T B^T z,  z = -(D + N)^-T (s_phi + M^T s_Y),
+// with B^T z from the cell VJP.  Mac is the steady macro system: D_i = sum_f (A_f/V_i) r_f / 2 (+ 1/(Z tau_i)
+// for rho E_rot), off-diagonal blocks (A_f/V_i)(dG_n/dW (W_j) - r_f I)/2.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// out_phi = in_phi + M^T in_Y (the phi rows of s - C^T s_Y); the Y rows are copied.
+__global__ __launch_bounds__(kBlock) void k_adj_expand(Dev d, Bufs b, const double* in, double* out) {
+  const int64_t i = blockIdx.x, nv = d.nv, P = d.nc * nv;
+  const Prim p = prim_of(b.W + 6 * i, d.gas.R);
+  const double* sW = in + 2 * P + 6 * i;
+  const double* sq = in + 2 * P + 6 * d.nc + 6 * i;
+  double vW[6], vq[6];
+  for (int m = 0; m < 6; ++m) {
+    vW[m] = sW[m];
+    vq[m] = sq[m];
+  }
+  for (int64_t k = (int64_t)blockIdx.y * kBlock + threadIdx.x; k < nv; k += (int64_t)gridDim.y * kBlock) {
+    const Vel v = vel(d, k);
+    const double cx = v.ux - p.U[0], cy = v.uy - p.U[1], cz = v.uz - p.U[2];
+    const double c2 = cx * cx + cy * cy + cz * cz;
+    const double vqc = vq[0] * cx + vq[1] * cy + vq[2] * cz;
+    out[i * nv + k] =
+        in[i * nv + k] + v.w * (vW[0] + vW[1] * v.ux + vW[2] * v.uy + vW[3] * v.uz + vW[4] * v.h2 + 0.5 * c2 * vqc);
+    out[P + i * nv + k] = in[P + i * nv + k] + v.w * (vW[4] + vW[5] + vq[3] * cx + vq[4] * cy + vq[5] * cz);
+  }
+  if (blockIdx.y == 0 && threadIdx.x < 12) {
+    const int64_t o = 2 * P + (threadIdx.x < 6 ? 6 * i + threadIdx.x : 6 * d.nc + 6 * i + threadIdx.x - 6);
+    out[o] = in[o];
+  }
+}
+
+// x_phi += M_c^T u: the conserved-moment rows of the macro residual (rho, rho U, rho E from G; rho E, rho E_rot
+// from R) spread back over the velocities.
+__global__ __launch_bounds__(kBlock) void k_adj_lift(Dev d, const double* u, double* x) {
+  const int64_t i = blockIdx.x, nv = d.nv, P = d.nc * nv;
+  double c[6];
+  for (int m = 0; m < 6; ++m) c[m] = u[6 * i + m];
+  for (int64_t k = (int64_t)blockIdx.y * kBlock + threadIdx.x; k < nv; k += (int64_t)gridDim.y * kBlock) {
+    const Vel v = vel(d, k);
+    x[i * nv + k] += v.w * (c[0] + c[1] * v.ux + c[2] * v.uy + c[3] * v.uz + c[4] * v.h2);
+    x[P + i * nv + k] += v.w * (c[4] + c[5]);
+  }
+}
+
+// Face spectral radii r_f (Eq. 41, from the cells' own W) and the diagonals of the steady macro system.
+__global__ __launch_bounds__(kBlock) void k_adj_macro_prep(Dev d, Bufs b, double* rc, double* mD) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.nc) return;
+  const GasC& g = d.gas;
+  const double* geo = d.cell_geo + CG * i;
+  const Prim pa = prim_of(b.W + 6 * i, g.R);
+  double acc = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    const double* s = geo + CG_FACE + CG_SLOT * a;
+    const int32_t nb = d.cell_nb[4 * i + a];
+    const Prim pb = nb >= 0 ? prim_of(b.W + 6 * (int64_t)nb, g.R) : pa;
+    const double rho = 0.5 * (pa.rho + pb.rho), T = 0.5 * (pa.T + pb.T), Ttr = 0.5 * (pa.Ttr + pb.Ttr);
+    const double Un = 0.5 * ((pa.U[0] + pb.U[0]) * s[2] + (pa.U[1] + pb.U[1]) * s[3] + (pa.U[2] + pb.U[2]) * s[4]);
+    const double r = fabs(Un) + sqrt(g.gamma * g.R * T) +
+                     2.0 * visc(Ttr, g) / (rho * d.face_geo[FGW * (int64_t)d.cell_face[4 * i + a] + 5]);
+    rc[4 * i + a] = r;
+    acc += 0.5 * s[1] * r;
+  }
+  const double tau = visc(pa.Ttr, g) / (pa.rho * g.R * pa.Ttr);
+  mD[2 * i] = acc;
+  mD[2 * i + 1] = acc + 1.0 / (g.Z * tau);
+}
+
+// One point relaxation over one colour of Mac^T u = t.  Row i of Mac^T couples the neighbours j through
+// Mac_ji^T = -(A_f/V_j)(dG_n/dW (W_i)^T + r_f I)/2 with n out of cell i (the flux Jacobian is odd in n and r_f
+// is the same from both sides).  Four lanes per cell, one per face, as in the forward macro sweep.
+__global__ __launch_bounds__(64) void k_adj_macro_sweep(Dev d, Bufs b, const double* rc, const double* mD,
+                                                        const double* t, double* u, int64_t c0, int64_t c1) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = c0 + (tid >> 2);
+  const int a = (int)(tid & 3);
+  const bool valid = i < c1;
+  double term[6] = {0, 0, 0, 0, 0, 0};
+  if (valid) {
+    const int32_t nb = d.cell_nb[4 * i + a];
+    if (nb >= 0) {
+      const double* geo = d.cell_geo + CG * i;
+      const double* s = geo + CG_FACE + CG_SLOT * a;
+      const double half_av = 0.5 * s[1] * geo[0] * d.cell_geo[CG * (int64_t)nb + 1];
+      double uj[6], gj[6];
+      for (int m = 0; m < 6; ++m) uj[m] = u[6 * (int64_t)nb + m];
+      euler_flux_vjp(b.W + 6 * i, s[2], s[3], s[4], uj, gj);
+      const double r = rc[4 * i + a];
+      for (int m = 0; m < 6; ++m) term[m] = half_av * (gj[m] + r * uj[m]);
+    }
+  }
+  double t1[6], t2[6], t3[6];
+  const int lane = threadIdx.x & 63;
+  for (int m = 0; m < 6; ++m) {
+    t1[m] = __shfl(term[m], lane + 1, 64);
+    t2[m] = __shfl(term[m], lane + 2, 64);
+    t3[m] = __shfl(term[m], lane + 3, 64);
+  }
+  if (!valid || a != 0) return;
+  const double D = mD[2 * i], D5 = mD[2 * i + 1];
+  for (int m = 0; m < 6; ++m) {
+    const double acc = t[6 * i + m] + term[m] + t1[m] + t2[m] + t3[m];
+    u[6 * i + m] = acc / (m == 5 ? D5 : D);
+  }
+}
+
+// x_Y = s_Y - (gW, gq)
+__global__ __launch_bounds__(kBlock) void k_adj_ysub(int64_t nc, int64_t off, const double* in, const double* gW,
+                                                     const double* gq, double* out) {
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < 12 * nc; t += (int64_t)gridDim.x * kBlock)
+    out[off + t] = in[off + t] - (t < 6 * nc ? gW[t] : gq[t - 6 * nc]);
+}
+
+}  // namespace
+
+void launch_adj_block_precond(const Dev& d, const Bufs& b, const double* in, double* out, double* tmp, double* cell,
+                              const int64_t* color_off, int64_t n_colors, int micro_pairs, int macro_pairs,
+                              hipStream_t st) {
+  const int64_t nc = d.nc, P = d.nc * d.nv;
+  double* gW = cell;
+  double* gq = gW + 6 * nc;
+  double* u = gq + 6 * nc;
+  double* rc = u + 6 * nc;
+  double* mD = rc + 4 * nc;
+  const unsigned nch = (unsigned)std::min<int64_t>((d.nv + kBlock - 1) / kBlock, 64);
+  const unsigned ncb = (unsigned)((nc + kBlock - 1) / kBlock);
+  // z = -(D + N)^-T (s_phi + M^T s_Y)
+  hipLaunchKernelGGL(k_adj_expand, dim3((unsigned)nc, nch), dim3(kBlock), 0, st, d, b, in, tmp);
+  if (micro_pairs > 0)
+    launch_adj_sweeps(d, b, tmp, out, color_off, n_colors, micro_pairs, st);
+  else
+    launch_precond(d, b, tmp, out, st);
+  AdjArgs a{out, out + P, nullptr, nullptr, 0.0, -1, -1, -1, nullptr, nullptr, gW, gq, nullptr};
+  if (macro_pairs > 0) {
+    // t = B^T z (W part), then Mac^T u = t and x_phi = z + M_c^T u
+    hipLaunchKernelGGL((k_cell_vjp<true, true>), dim3((unsigned)nc), dim3(kBlock), 0, st, d, b, a);
+    hipLaunchKernelGGL(k_adj_macro_prep, dim3(ncb), dim3(kBlock), 0, st, d, b, rc, mD);
+    launch_axpby(6 * nc, 0.0, gW, 0.0, u, st);
+    for (const int64_t c : sweep_sequence(color_off, n_colors, macro_pairs)) {
+      const int64_t n = color_off[c + 1] - color_off[c];
+      hipLaunchKernelGGL(k_adj_macro_sweep, dim3((unsigned)((4 * n + 63) / 64)), dim3(64), 0, st, d, b,
+                         (const double*)rc, (const double*)mD, (const double*)gW, u, color_off[c], color_off[c + 1]);
+    }
+    hipLaunchKernelGGL(k_adj_lift, dim3((unsigned)nc, nch), dim3(kBlock), 0, st, d, (const double*)u, out);
+  }
+  // x_Y = s_Y - B^T x_phi
+  hipLaunchKernelGGL((k_cell_vjp<true, true>), dim3((unsigned)nc), dim3(kBlock), 0, st, d, b, a);
+  const int64_t tail = 12 * nc;
+  hipLaunchKernelGGL(k_adj_ysub, dim3((unsigned)std::min<int64_t>((tail + kBlock - 1) / kBlock, 4096)), dim3(kBlock),
+                     0, st, nc, 2 * P, in, (const double*)gW, (const double*)gq, out);
 }
 
 namespace {

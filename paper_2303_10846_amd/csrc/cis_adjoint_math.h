@@ -110,6 +110,29 @@ struct EqAd {
   }
 };
 
+// g = J^T v with J = dG_n/dW the Jacobian of the Euler flux along n of the macroscopic system (Eq. 37 with the
+// equilibrium closure p = (gamma - 1)(rho E - rho |U|^2 / 2), gamma = 7/5, and rho E_rot carried with U.n), at the
+// state W = (rho, rho U, rho E, rho E_rot).  Written out from G_n = (rho U.n, rho U U.n + p n, (rho E + p) U.n,
+// rho E_rot U.n): with s = v.G_n, K = (v_m.(rho U) + v_4 (rho E + p) + v_5 rho E_rot)/rho and P = v_m.n + v_4 U.n,
+//   ds/drho = -U.n K + (|U|^2/5) P,  ds/d(rho U) = v_0 n + v_m U.n + K n - (2/5) U P,
+//   ds/d(rho E) = (2/5) P + v_4 U.n,  ds/d(rho E_rot) = v_5 U.n.
+__host__ __device__ inline void euler_flux_vjp(const double* W, double nx, double ny, double nz, const double* v,
+                                               double* g) {
+  const double ir = 1.0 / W[0];
+  const double Ux = W[1] * ir, Uy = W[2] * ir, Uz = W[3] * ir;
+  const double U2 = Ux * Ux + Uy * Uy + Uz * Uz;
+  const double p = 0.4 * (W[4] - 0.5 * W[0] * U2);
+  const double Un = Ux * nx + Uy * ny + Uz * nz;
+  const double K = (v[1] * W[1] + v[2] * W[2] + v[3] * W[3] + v[4] * (W[4] + p) + v[5] * W[5]) * ir;
+  const double P = v[1] * nx + v[2] * ny + v[3] * nz + v[4] * Un;
+  g[0] = -Un * K + 0.2 * U2 * P;
+  g[1] = v[0] * nx + v[1] * Un + K * nx - 0.4 * Ux * P;
+  g[2] = v[0] * ny + v[2] * Un + K * ny - 0.4 * Uy * P;
+  g[3] = v[0] * nz + v[3] * Un + K * nz - 0.4 * Uz * P;
+  g[4] = 0.4 * P + v[4] * Un;
+  g[5] = v[5] * Un;
+}
+
 // Forward-mode dual number with N derivative components (used once per face, on one thread).
 template <int N> struct Dual {
   double v;

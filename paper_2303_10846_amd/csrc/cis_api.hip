@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/cis.h"
+#include "cis_adjoint.h"
 #include "cis_internal.h"
 
 using namespace cis;
@@ -135,7 +136,8 @@ bool finite_all(const double* p, size_t n) {
 cis_status check_numerics(const cis_numerics* n) {
   if (!n) return fail(CIS_E_INVALID_ARG, "numerics is NULL");
   if (!(n->cfl > 0.0) || !(n->inv_dt >= 0.0) || !(n->cfl_imp >= 0.0) || !(n->lim_K >= 0.0) || !(n->snap >= 0.0) ||
-      n->n_macro < 0 || n->n_micro < 0 || n->n_macro > 100000 || n->n_micro > 100000)
+      n->n_macro < 0 || n->n_micro < 0 || n->n_macro > 100000 || n->n_micro > 100000 || n->limiter < 0 ||
+      n->limiter > 2)
     return fail(CIS_E_INVALID_ARG, "numerics out of range");
   return CIS_OK;
 }
@@ -225,7 +227,8 @@ cis_status dev_dots(cis_state* s, const double* V, int64_t n, int nvec, const do
 
 int64_t adjoint_doubles(const cis_state* s, int32_t restart) {
   const int64_t N = 2 * s->mesh->nc * s->dvs->n + 12 * s->mesh->nc;
-  return ((int64_t)restart + 3) * N + ((int64_t)restart + 2) * (dot_partials() + 1);
+  return ((int64_t)restart + 4) * N + ((int64_t)restart + 2) * (dot_partials() + 1) +
+         kBlockPrecondCellDoubles * s->mesh->nc;
 }
 
 }  // namespace
@@ -999,12 +1002,13 @@ cis_status cis_adjoint_required_bytes(const cis_state* s, int32_t restart, int64
 }
 
 cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int32_t restart, int32_t max_iter,
-                             double rtol, int32_t precond_pairs, void* work, int64_t work_bytes, double* lam,
-                             double* dJdp, double* J, cis_adjoint_info* info) {
+                             double rtol, int32_t precond_pairs, int32_t macro_pairs, void* work,
+                             int64_t work_bytes, double* lam, double* dJdp, double* J, cis_adjoint_info* info) {
   if (!s || !work || !lam || !dJdp) return fail(CIS_E_INVALID_ARG, "NULL argument");
   if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the adjoint is FP64 only");
-  if (restart < 1 || restart > 1000 || max_iter < 0 || !(rtol > 0.0) || precond_pairs < 0 || precond_pairs > 64)
-    return fail(CIS_E_INVALID_ARG, "restart, max_iter, rtol or precond_pairs out of range");
+  if (restart < 1 || restart > 1000 || max_iter < 0 || !(rtol > 0.0) || precond_pairs < 0 || precond_pairs > 64 ||
+      macro_pairs < 0 || macro_pairs > 200)
+    return fail(CIS_E_INVALID_ARG, "restart, max_iter, rtol, precond_pairs or macro_pairs out of range");
   if (work_bytes < adjoint_doubles(s, restart) * (int64_t)sizeof(double))
     return fail(CIS_E_INVALID_ARG, "work buffer smaller than cis_adjoint_required_bytes");
   AdjSlots sl;
@@ -1017,12 +1021,17 @@ cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int
   double* z = b + N;                       // preconditioned vector / update
   double* part = z + N;                    // [m+1][dot_partials()]
   double* hdev = part + (int64_t)(m + 2) * dot_partials();
+  double* ptmp = hdev + (m + 2);           // block preconditioner: a full-length vector and per-cell scratch
+  double* pcell = ptmp + N;
   hipStream_t q = s->stream;
   auto dots = [&](const double* Vb, int nvec, const double* w, double* host) {
     return dev_dots(s, Vb, N, nvec, w, part, hdev, host);
   };
   auto precond = [&](const double* in, double* out) {
-    if (precond_pairs == 0)
+    if (macro_pairs > 0)
+      launch_adj_block_precond(s->dev, s->buf, in, out, ptmp, pcell, s->mesh->color_off.data(), s->mesh->n_colors,
+                               precond_pairs, macro_pairs, q);
+    else if (precond_pairs == 0)
       launch_precond(s->dev, s->buf, in, out, q);
     else
       launch_adj_sweeps(s->dev, s->buf, in, out, s->mesh->color_off.data(), s->mesh->n_colors, precond_pairs, q);

@@ -673,3 +673,43 @@ def test_p9_colour_major_order_converges_as_fast_as_natural_order():
         n_nat = iterations(case, morton(np.asarray(case["mesh"]["xyz"]), tets))
         assert n_col < 200 and n_nat < 200
         assert n_col <= 1.1 * n_nat, (case["name"], n_col, n_nat)
+
+
+def test_frozen_limiter_derivative_keeps_l_fixed():
+    """limiter = 2 runs the limiter of limiter = 1 and holds it fixed in derivatives.  The limiter value is
+    invariant under a positive scaling of phi (psi is homogeneous of degree 0 in (Delta1, Delta2, eps)), so
+    along the direction phi itself the frozen derivative equals central differences of the limited residual
+    and the differentiated-branch derivative; along a generic direction the two derivatives differ."""
+    c = _open_box(1)
+    o1 = oracle.Oracle(c)
+    o1.init_equilibrium(c["W0"])
+    o1.iterate(6)
+    G, R, W, q = o1.get_state()
+    c2 = dict(c, num=dict(c["num"], limiter=2))
+    o2 = oracle.Oracle(c2)
+    o2.set_state(G, R, W, q)
+    r1, r2 = o1.steady_residual(1), o2.steady_residual(1)
+    for m in range(5):
+        assert np.array_equal(np.asarray(r1[m]), np.asarray(r2[m]))      # same scheme in the iteration
+    zW, zq, zp = np.zeros_like(W), np.zeros_like(q), np.zeros(3)
+    jf = o2.steady_residual_jvp(G, R, zW, zq, zp, wall_tag=1, ff_tag=2)
+    ja = o1.steady_residual_jvp(G, R, zW, zq, zp, wall_tag=1, ff_tag=2)
+    eps = 1e-6
+    ob = oracle.Oracle(c)
+    ob.set_state((1 + eps) * G, (1 + eps) * R, W, q)
+    rp = ob.steady_residual(1)
+    ob.set_state((1 - eps) * G, (1 - eps) * R, W, q)
+    rm = ob.steady_residual(1)
+    for m in range(5):
+        fd = (np.asarray(rp[m]) - np.asarray(rm[m])) / (2 * eps)
+        assert rel(jf[m], fd) < 1e-7, (m, rel(jf[m], fd))
+        assert rel(jf[m], ja[m]) < 1e-12, (m, rel(jf[m], ja[m]))
+    rng = np.random.default_rng(4)
+    u = [rng.standard_normal(G.shape) * np.abs(G), rng.standard_normal(R.shape) * np.abs(R)]
+    jf = o2.steady_residual_jvp(*u, zW, zq, zp, wall_tag=1, ff_tag=2)
+    ja = o1.steady_residual_jvp(*u, zW, zq, zp, wall_tag=1, ff_tag=2)
+    j0 = oracle.Oracle(dict(c, num=dict(c["num"], limiter=0)))
+    j0.set_state(G, R, W, q)
+    jn = j0.steady_residual_jvp(*u, zW, zq, zp, wall_tag=1, ff_tag=2)
+    assert rel(jf[0], ja[0]) > 1e-6       # the limiter's derivative is dropped ...
+    assert rel(jf[0], jn[0]) > 1e-6       # ... but not the limiter itself
