@@ -220,6 +220,62 @@ def dvs_study(iters):
             "iterations": iters, "precision": "mixed", "A_ref": "pi d^2 / 4", "sets": rows}
 
 
+def adjoint_check(gmres_iters=300, fd_rel=1e-3, fd_iters=400):
+    """Discrete adjoint of the FP64 sphere at its converged plateau against central differences of the
+    converged heat load.  The limiter is held fixed in the adjoint (limiter = 2, block preconditioner); the
+    adjoint with the limiter differentiated on its active branch (limiter = 1) is run beside it for 60 GMRES
+    iterations to show where it stands."""
+    import torch
+
+    from paper_2303_10846_amd.binding import Solver
+    from paper_2303_10846_amd.cases import configs
+    case = configs.sphere_case(seed=0)
+    case["num"] = dict(case["num"], limiter=2)
+    s = Solver(case, precision="fp64", device="cuda:0")
+    s.init_equilibrium(case["W0"])
+    hist = s.iterate(600)
+    print(f"bench: adjoint check primal residual {hist[-1].max():.3e}", file=sys.stderr, flush=True)
+    base = s.get_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a = s.adjoint(1, 2, restart=50, max_iter=gmres_iters, rtol=1e-8, precond_pairs=2, macro_pairs=20)
+    t_adj = time.perf_counter() - t0
+    print(f"bench: frozen-limiter adjoint {a['iterations']} iterations, relative residual {a['rel_residual']:.2e}",
+          file=sys.stderr, flush=True)
+    del a["lam"]
+    torch.cuda.empty_cache()
+    s.set_numerics(limiter=1)
+    act = s.adjoint(1, 2, restart=20, max_iter=60, rtol=1e-8, precond_pairs=2)
+    s.set_numerics(limiter=2)
+    del act["lam"]
+    torch.cuda.empty_cache()
+    p0 = s.params(1, 2)
+    fd = []
+    for k in range(3):
+        h = fd_rel * abs(p0[k])
+        J = []
+        for sgn in (1, -1):
+            p = p0.copy()
+            p[k] += sgn * h
+            s.set_params(p, 1, 2)
+            s.set_state(*base)
+            hk = s.iterate(fd_iters)
+            J.append(s.wall_heat_flux(1))
+            print(f"bench: adjoint check p[{k}] {sgn:+d}h residual {hk[-1].max():.2e}", file=sys.stderr, flush=True)
+        fd.append((J[0] - J[1]) / (2 * h))
+    s.set_params(p0, 1, 2)
+    adj = [float(x) for x in a["dJdp"]]
+    return {"check": "dQ_w/dp of the converged sphere (Ma 5, Kn 0.1), p = (T_w, rho_inf, |U_inf|)",
+            "n_cells": s.nc, "n_vel": s.nv, "primal_residual": float(hist[-1].max()), "J": a["J"],
+            "adjoint_frozen_limiter": {"dJdp": adj, "gmres_iterations": a["iterations"], "restart": 50,
+                                       "rel_residual": a["rel_residual"], "seconds": t_adj,
+                                       "precond_pairs": 2, "macro_pairs": 20},
+            "adjoint_active_limiter": {"dJdp": [float(x) for x in act["dJdp"]], "gmres_iterations": act["iterations"],
+                                       "restart": 20, "rel_residual": act["rel_residual"]},
+            "central_differences": {"dJdp": [float(x) for x in fd], "h_over_p": fd_rel, "iterations": fd_iters},
+            "rel_diff_frozen_vs_fd": [(x - y) / abs(y) for x, y in zip(adj, fd)]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +293,9 @@ def main():
     ap.add_argument("--dvs-study", type=int, default=0, metavar="ITERS",
                     help="instead of timing, run the sphere with six DVS sets for ITERS iterations each and print "
                          "the wall coefficients against the DVS")
+    ap.add_argument("--adjoint-check", action="store_true",
+                    help="instead of timing, solve the sphere's discrete adjoint and compare dQ_w/dp with central "
+                         "differences of the converged heat load")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the DVS-sharded multi-GPU path is a design, not code); "
@@ -252,6 +311,9 @@ def main():
         print(f"bench: copy probe {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written",
               file=sys.stderr, flush=True)
         del a, b
+    if args.adjoint_check:
+        print(json.dumps(adjoint_check()))
+        return
     if args.dvs_study:
         print(json.dumps(dvs_study(args.dvs_study)))
         return
