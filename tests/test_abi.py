@@ -114,3 +114,6 @@ def test_state_create_rejects_null_buffers_before_touching_the_device():
     bad = binding.numerics_struct(dict(c["num"], cfl=-1.0))
     assert lib.cis_state_create(mm.h, dv.h, C.byref(gas), C.byref(bad), bcs, 2, 0, C.byref(bufs), None,
                                 C.byref(h)) == -1
+    bad = binding.numerics_struct(dict(c["num"], limiter=3))          # limiter is 0, 1 or 2
+    assert lib.cis_state_create(mm.h, dv.h, C.byref(gas), C.byref(bad), bcs, 2, 0, C.byref(bufs), None,
+                                C.byref(h)) == -1
