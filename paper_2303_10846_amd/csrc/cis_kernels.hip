@@ -458,29 +458,40 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     Eq<T> e;
     e.load(sh_ec);
     const T ct = (T)sh_ec[28], cs = (T)sh_ec[29];
-    // pass 2: phi_f (Eq. 45), micro flux and macro flux
+    // pass 2: phi_f (Eq. 45), micro flux and macro flux.  The upwind side (with its tie rule) is the owner's
+    // upwind code, as in the reconstruction, and u.n is the plain FP64 product; |u|^2/2 is formed in registers
+    // (fewer cached DVS loads per velocity).
+    const int64_t own = d.face_cell[2 * f];
+    int slot = 0;
+    for (int a = 1; a < 4; ++a)
+      if (d.cell_face[4 * own + a] == (int32_t)f) slot = a;
+    const uint8_t* code = d.upw + own * nv;
     acc.zero();
-    Vel pv[P];
+    unsigned pc[P];
     k_loop_pf<P>(nv, [&](int k, int q) {
       pg[q] = UseLds ? sG[k] : rowG[k];
       pr[q] = UseLds ? sR[k] : rowR[k];
-      pv[q] = vel(V, k);
+      px[q] = V.ux[k];
+      py[q] = V.uy[k];
+      pz[q] = V.uz[k];
+      pw[q] = V.w[k];
+      pc[q] = code[k];
     }, [&](int k, int q) {
       const T gb = pg[q], rb = pr[q];
-      const Vel v = pv[q];
+      const double ux = px[q], uy = py[q], uz = pz[q], vw = pw[q];
       T gs, rs;
-      e.eval((T)v.ux, (T)v.uy, (T)v.uz, gs, rs);
+      e.eval((T)ux, (T)uy, (T)uz, gs, rs);
       const T gf = ct * gb + cs * gs;
       const T rf = ct * rb + cs * rs;
-      const double un = udotn(v, nx, ny, nz, d.snap);
+      const double un = ((pc[q] >> (2 * slot)) & 3u) == 0u ? 0.0 : ux * nx + uy * ny + uz * nz;
       rowG[k] = (T)(A * un) * gf;
       rowR[k] = (T)(A * un) * rf;
-      double wg = v.w * un * (double)gf, wr = v.w * un * (double)rf;
+      double wg = vw * un * (double)gf, wr = vw * un * (double)rf;
       acc.add(0, wg);
-      acc.add(1, v.ux * wg);
-      acc.add(2, v.uy * wg);
-      acc.add(3, v.uz * wg);
-      acc.add(4, v.h2 * wg + wr);
+      acc.add(1, ux * wg);
+      acc.add(2, uy * wg);
+      acc.add(3, uz * wg);
+      acc.add(4, 0.5 * (ux * ux + uy * uy + uz * uz) * wg + wr);
       acc.add(5, wr);
     });
     acc.reduce_to_lds(tot, red);
@@ -1096,18 +1107,18 @@ template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update
     const T r = R[k] + dR[k];
     st_stream(G + k, g);
     st_stream(R + k, r);
-    const Vel v = vel(V, k);
+    const double vx = V.ux[k], vy = V.uy[k], vz = V.uz[k], vw = V.w[k];
     T gs, rs;
-    e.eval((T)v.ux, (T)v.uy, (T)v.uz, gs, rs);
+    e.eval((T)vx, (T)vy, (T)vz, gs, rs);
     double gd = (double)g - (double)gs, rd = (double)r - (double)rs;
-    double cx = v.ux - Ux, cy = v.uy - Uy, cz = v.uz - Uz;
+    double cx = vx - Ux, cy = vy - Uy, cz = vz - Uz;
     double c2 = cx * cx + cy * cy + cz * cz;
-    double wg = v.w * gd, wr = v.w * rd;
+    double wg = vw * gd, wr = vw * rd;
     acc.add(0, wg);
-    acc.add(1, v.ux * wg);
-    acc.add(2, v.uy * wg);
-    acc.add(3, v.uz * wg);
-    acc.add(4, v.h2 * wg + wr);
+    acc.add(1, vx * wg);
+    acc.add(2, vy * wg);
+    acc.add(3, vz * wg);
+    acc.add(4, 0.5 * (vx * vx + vy * vy + vz * vz) * wg + wr);
     acc.add(5, wr);
     double hc = 0.5 * c2 * wg;
     acc.add(6, cx * hc);
