@@ -279,6 +279,42 @@ def adjoint_check(gmres_iters=300, fd_rel=1e-3, fd_iters=400):
             "rel_diff_frozen_vs_fd": [(x - y) / abs(y) for x, y in zip(adj, fd)]}
 
 
+# Implicit-step schedule of the capsule's convergence run: iteration from which each cfl_imp applies.  Ma 10 from
+# rest needs a small implicit step until the bow shock has formed; afterwards the step grows.
+CAPSULE_CFL_RAMP = ((0, 1.0), (800, 3.0), (1100, 10.0), (1400, 30.0), (1700, 100.0))
+
+
+def capsule_converge(iters):
+    """The Ma 10 capsule (mixed precision) from rest to its converged coefficients, with the cfl_imp schedule
+    above: residual, C_d, heat-load coefficient C_Q and C_l every 100 iterations."""
+    import torch
+
+    from paper_2303_10846_amd.binding import Solver, wall_coefficients
+    from paper_2303_10846_amd.cases import configs
+    case = configs.capsule_case(seed=0)
+    s = Solver(case, precision="mixed", device="cuda:0")
+    s.init_equilibrium(case["W0"])
+    ramp = dict(CAPSULE_CFL_RAMP)
+    hist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < iters:
+        if done in ramp:
+            s.set_numerics(cfl_imp=ramp[done])
+        h = s.iterate(100)
+        done += 100
+        co = wall_coefficients(s.wall_loads(1), 1.0, case["U_inf"], 1.0, 0.5, A_ref=math.pi * 0.25)
+        row = dict(iteration=done, seconds=time.perf_counter() - t0, residual=float(h[-1].max()), Cd=co["Cd"],
+                   CQ=float(co["CQ"]), Cl=co["Cl"])
+        hist.append(row)
+        print(f"bench: capsule {done} iterations, residual {row['residual']:.3e}, Cd {row['Cd']:.6f}, "
+              f"CQ {row['CQ']:.6f}", file=sys.stderr, flush=True)
+    return {"run": "capsule Ma 10 Kn 0.01 Tw/Tinf 4.18 from rest, mixed precision, A_ref = pi D^2 / 4",
+            "n_cells": s.nc, "n_vel": s.nv, "cfl_imp_schedule": [list(x) for x in CAPSULE_CFL_RAMP],
+            "history": hist}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +335,9 @@ def main():
     ap.add_argument("--adjoint-check", action="store_true",
                     help="instead of timing, solve the sphere's discrete adjoint and compare dQ_w/dp with central "
                          "differences of the converged heat load")
+    ap.add_argument("--capsule-converge", type=int, default=0, metavar="ITERS",
+                    help="instead of timing, run the capsule from rest for ITERS iterations (a multiple of 100) "
+                         "and print its residual and wall coefficients every 100 iterations")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the DVS-sharded multi-GPU path is a design, not code); "
@@ -314,6 +353,9 @@ def main():
         print(f"bench: copy probe {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written",
               file=sys.stderr, flush=True)
         del a, b
+    if args.capsule_converge:
+        print(json.dumps(capsule_converge(args.capsule_converge)))
+        return
     if args.adjoint_check:
         print(json.dumps(adjoint_check()))
         return
