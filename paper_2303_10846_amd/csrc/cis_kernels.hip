@@ -881,8 +881,8 @@ __device__ inline void micro_load(const MicroCell<T>& c, const T (*uv)[3], const
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (k[u] >= nvi) continue;
-    in.xG[u] = c.rG[k[u]];
-    in.xR[u] = c.rR[k[u]];
+    in.xG[u] = __builtin_nontemporal_load(c.rG + k[u]);
+    in.xR[u] = __builtin_nontemporal_load(c.rR + k[u]);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const unsigned cd = (code[u] >> (2 * a)) & 3u;
@@ -914,8 +914,8 @@ __device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& i
       }
     }
     const double iD = 1.0 / D;
-    c.oG[k[u]] = (T)((double)aG * iD);
-    c.oR[k[u]] = (T)((double)aR * iD);
+    st_stream(c.oG + k[u], (T)((double)aG * iD));
+    st_stream(c.oR + k[u], (T)((double)aR * iD));
   }
 }
 
@@ -952,6 +952,97 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, i
   micro_setup<T>(d, b, w, i, cnext, first, c);
   micro_load<T, U>(c, uv, code, k, nvi, in);
   micro_store<T, U>(c, in, code, k, nvi);
+}
+
+// The mixed-mode sweep moves V adjacent velocities per thread as one vector per row (one load or store of
+// 4V bytes instead of V), when nv is a multiple of V so that every row offset keeps the vectors aligned.  The
+// arithmetic is that of k_micro_sweep<float>, velocity by velocity; a neighbour's vector is loaded when any of
+// the V velocities takes it as its upstream value.  The right-hand sides are read and the increments written
+// non-temporally (in every precision): the increments are next read by other colours' launches and the update,
+// after the caches have turned over.  Measured on the sphere (4140 velocities): micro sweep 3.79 -> 3.45 ms
+// with V = 4 (90 VGPRs, 5 waves per SIMD), 3.52 ms with V = 2; non-temporal 3.44 -> 3.14 ms (FP64 6.89 ->
+// 6.58 ms).
+template <int V> struct alignas(4 * V) VecF { float v[V]; };
+template <int V> struct ExtV;
+template <> struct ExtV<2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct ExtV<4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <int V> __device__ inline VecF<V> ld_nt(const float* p) {
+  const typename ExtV<V>::type x = __builtin_nontemporal_load(reinterpret_cast<const typename ExtV<V>::type*>(p));
+  VecF<V> r;
+#pragma unroll
+  for (int q = 0; q < V; ++q) r.v[q] = x[q];
+  return r;
+}
+template <int V> __device__ inline void st_nt(float* p, const VecF<V>& v) {
+  typename ExtV<V>::type x;
+#pragma unroll
+  for (int q = 0; q < V; ++q) x[q] = v.v[q];
+  __builtin_nontemporal_store(x, reinterpret_cast<typename ExtV<V>::type*>(p));
+}
+template <int V> struct CodeT;
+template <> struct CodeT<2> { using type = uint16_t; };
+template <> struct CodeT<4> { using type = uint32_t; };
+
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work w, int64_t c0, int64_t cnext,
+                                                            int first) {
+  const CellChunk cc = cell_chunk(cnext - c0);
+  if (cc.cell >= cnext - c0) return;
+  const int64_t nv = d.nv;
+  const int64_t i = c0 + cc.cell;
+  const int k = (int)cc.chunk * (V * kBlock) + V * (int)threadIdx.x;
+  if (k >= (int)nv) return;
+  using VF = VecF<V>;
+  const unsigned cw = *reinterpret_cast<const typename CodeT<V>::type*>(d.upw + i * nv + k);
+  const VF vx = *reinterpret_cast<const VF*>(d.dvs_f + k);
+  const VF vy = *reinterpret_cast<const VF*>(d.dvs_f + nv + k);
+  const VF vz = *reinterpret_cast<const VF*>(d.dvs_f + 2 * nv + k);
+  MicroCell<float> c;
+  micro_setup<float>(d, b, w, i, cnext, first, c);
+  const VF xG = ld_nt<V>(c.rG + k);
+  const VF xR = ld_nt<V>(c.rR + k);
+  unsigned code[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) code[q] = (cw >> (8 * q)) & 0xffu;
+  float pos[V][4], neg[V][4];
+  VF yG[4], yR[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    bool need = false;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const unsigned cd = (code[q] >> (2 * a)) & 3u;
+      const float t = vx.v[q] * c.nx[a] + vy.v[q] * c.ny[a] + vz.v[q] * c.nz[a];
+      pos[q][a] = cd == 1u ? fmaxf(t, 0.0f) : 0.0f;
+      neg[q][a] = cd == 2u ? fminf(t, 0.0f) : 0.0f;
+      need = need || cd == 2u;
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) yG[a].v[q] = yR[a].v[q] = 0.0f;
+    if (c.use[a] && need) {
+      yG[a] = *reinterpret_cast<const VF*>(c.nG[a] + k);
+      yR[a] = *reinterpret_cast<const VF*>(c.nR[a] + k);
+    }
+  }
+  VF oG, oR;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    double D = c.dbase;
+    float aG = xG.v[q], aR = xR.v[q];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      D += (double)(c.av[a] * pos[q][a]);
+      if (c.use[a] && ((code[q] >> (2 * a)) & 3u) == 2u) {
+        aG -= c.av[a] * neg[q][a] * yG[a].v[q];
+        aR -= c.av[a] * neg[q][a] * yR[a].v[q];
+      }
+    }
+    const double iD = 1.0 / D;
+    oG.v[q] = (float)((double)aG * iD);
+    oR.v[q] = (float)((double)aR * iD);
+  }
+  st_nt<V>(c.oG + k, oG);
+  st_nt<V>(c.oR + k, oR);
 }
 
 // Preconditioner of the discrete adjoint (FP64): point relaxation over one colour of
@@ -1077,8 +1168,15 @@ void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
   for (size_t p = 0; p < seq.size(); ++p) {
     const int64_t c = seq[p];
     const int64_t n = color_off[c + 1] - color_off[c];
-    hipLaunchKernelGGL(k_micro_sweep<T>, cell_chunk_grid_u<kVptOne>(n, d.nv), dim3(kBlock), 0, st, d, b, w, color_off[c],
-                       color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
+    if (std::is_same<T, float>::value && d.nv % 4 == 0)
+      hipLaunchKernelGGL(k_micro_sweep_vec<4>, cell_chunk_grid_u<4>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
+                         color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
+    else if (std::is_same<T, float>::value && d.nv % 2 == 0)
+      hipLaunchKernelGGL(k_micro_sweep_vec<2>, cell_chunk_grid_u<2>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
+                         color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_micro_sweep<T>, cell_chunk_grid_u<kVptOne>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
+                         color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
   }
 }
 

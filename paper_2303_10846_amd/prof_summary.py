@@ -3,6 +3,7 @@
     python -m paper_2303_10846_amd.prof_summary stats    <trace_dir> <out.txt> --command "..."
     python -m paper_2303_10846_amd.prof_summary counters <fetch_dir> <write_dir> <out.txt> --kernel NAME \
         --probe-mib 1024 --command "..."
+    python -m paper_2303_10846_amd.prof_summary sq <pmc_dir> <out.txt> --kernels NAME ... --command "..."
 
 The counters summary calibrates FETCH_SIZE and WRITE_SIZE (KiB per dispatch) against a plain elementwise
 kernel of known size that the profiled program runs first (bench.py --copy-probe-mb), and records a hash of
@@ -129,6 +130,35 @@ def counters(fetch_dir: str, write_dir: str, out: str, kernel: str, probe_mib: f
     print("\n".join(lines))
 
 
+def sq(pmc_dir: str, out: str, command: str, kernels: list, cus: int = 256, simds: int = 4, ghz: float = 2.4):
+    """Per-dispatch averages of SQ instruction counters for the named kernels.  valu_issue_us is the time the
+    VALU instructions alone occupy the SIMDs: a wavefront's VALU instruction takes 4 cycles of a 16-lane SIMD
+    (unpacked FP32 or FP64), spread over cus * simds SIMDs at ghz."""
+    path = _find(pmc_dir, "counter_collection.csv")
+    names = sorted({r["Counter_Name"] for r in csv.DictReader(open(path))})
+    per = {c: _per_dispatch(path, c) for c in names}
+    lines = ["# rocprofv3 SQ instruction counters (per dispatch, whole GPU)", f"# command: {command}",
+             f"# source_sha256: {source_hash()}", f"# valu_issue_us = SQ_INSTS_VALU * 4 / ({cus} * {simds}) / {ghz} GHz",
+             ""]
+    for want in kernels:
+        ks = [k for k in per[names[0]] if want in k]
+        if not ks:
+            continue
+        k = ks[0]
+        avg = {c: sum(per[c][k]) / len(per[c][k]) for c in names if per[c].get(k)}
+        lines.append(f"kernel: {short_name(k)}")
+        for c in names:
+            if c in avg:
+                lines.append(f"  {c}: {avg[c]:.6g}")
+        if "SQ_INSTS_VALU" in avg:
+            lines.append(f"  valu_issue_us: {avg['SQ_INSTS_VALU'] * 4 / (cus * simds) / (ghz * 1e3):.1f}")
+        if "SQ_INSTS_VALU" in avg and "SQ_WAVES" in avg:
+            lines.append(f"  valu_per_wave: {avg['SQ_INSTS_VALU'] / avg['SQ_WAVES']:.1f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def read_counters(path: str) -> dict:
     """Key/value lines of a counters summary (the header block only)."""
     out = {}
@@ -159,11 +189,18 @@ def main():
     b.add_argument("--kernel", required=True)
     b.add_argument("--probe-mib", type=float, required=True)
     b.add_argument("--command", required=True)
+    c = sub.add_parser("sq")
+    c.add_argument("pmc_dir")
+    c.add_argument("out")
+    c.add_argument("--command", required=True)
+    c.add_argument("--kernels", nargs="+", required=True)
     args = ap.parse_args()
     if args.cmd == "stats":
         stats(args.trace_dir, args.out, args.command, bench_log=args.bench_log)
-    else:
+    elif args.cmd == "counters":
         counters(args.fetch_dir, args.write_dir, args.out, args.kernel, args.probe_mib, args.command)
+    else:
+        sq(args.pmc_dir, args.out, args.command, args.kernels)
 
 
 if __name__ == "__main__":

@@ -284,6 +284,32 @@ def test_mixed_precision_cavity_converged_fields():
     assert er < 1e-5 and eT < 1e-5 and eq < 1e-5
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 4), (9, 9, 6), (7, 7, 7)])
+def test_mixed_micro_sweep_vector_widths(dims):
+    """The mixed micro sweep moves 4, 2 or 1 velocities per thread as one vector, by nv mod 4 (256, 486, 343
+    velocities here): one mixed iteration from the oracle's state against the FP64 oracle's.  The bar is FP32
+    rounding (6e-8) of phi amplified by the cancellation in Res = (phi* - phi)/tau - F, whose terms are up to
+    ~1e3 times Res on this nearly resting cavity: measured 0.6-2.2e-5 for all three widths, and the same with
+    the one-velocity kernel alone.  A wrong upstream value or upwind bit gives O(1) errors."""
+    u, w = _grid_dvs(*dims)
+    c = dict(configs.cavity_case(n=3, nv_side=4), u=u, w=w)
+    say("case cavity n=3, nv", len(u))
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(3)
+    G, R, W, q = o.get_state()
+    s = solver(c, precision="mixed")
+    s.set_state(G, R, W, q)
+    o.iterate(1)
+    s.iterate(1)
+    eG = nrel(s.dG.cpu().numpy(), o.stage("dG"))
+    eR = nrel(s.dR.cpu().numpy(), o.stage("dR"))
+    Wm, _ = s.moments()
+    eW = colrel(Wm, o.get_state()[2])
+    say(f"mixed vs FP64 oracle: dG {eG:.2e} dR {eR:.2e} W {eW:.2e}")
+    assert eG < 1e-4 and eR < 1e-4 and eW < 1e-4
+
+
 def test_wall_loads_match_oracle_face_fluxes():
     """Per-face pressure, shear and heat flux (Eqs. 70-72 numerators) and the integrated force and heat load on
     the sphere wall, against the oracle's face macro fluxes on the same state."""
