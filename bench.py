@@ -180,11 +180,22 @@ def cpu_baseline(case, stride=8, iters=8, stride_1t=32, iters_1t=2):
 # Eq. 74 at the free-stream and wall velocities.
 DVS_STUDY = (("V1", 5.0, 16000), ("V2", 5.0, 12000), ("V3", 5.0, 8000), ("V4", 5.0, 4096), ("V5", 4.0, 3000),
              ("V6", 3.0, 2000))
+# On the capsule: the timed workload's set (10 568 velocities in the 5 sqrt(R T0) ball), a coarser spacing and
+# the two smaller balls.
+CAPSULE_DVS_STUDY = (("C2", 5.0, 6000), ("C3", 4.0, 4500), ("C4", 3.0, 3500))
 
 
-def dvs_study(iters):
+def _coefficients(s, case, T_inf=1.0, gas_R=0.5):
+    from paper_2303_10846_amd.binding import wall_coefficients
+    co = wall_coefficients(s.wall_loads(1), 1.0, case["U_inf"], T_inf, gas_R, A_ref=math.pi * 0.25)
+    return dict(Cd=co["Cd"], CQ=float(co["CQ"]), Cp_max=float(co["Cp"].max()), Ch_max=float(co["Ch"].max()))
+
+
+def dvs_study(iters, workload="sphere"):
     """Aerodynamic coefficients of the Ma 5 sphere against the size and extent of the DVS (mixed precision,
     `iters` iterations from rest each), with relative differences against the finest set."""
+    if workload == "capsule":
+        return capsule_dvs_study(iters)
     import torch
 
     from paper_2303_10846_amd.binding import Solver, wall_coefficients
@@ -283,6 +294,72 @@ def adjoint_check(gmres_iters=300, fd_rel=1e-3, fd_iters=400):
             "rel_diff_frozen_vs_fd": [(x - y) / abs(y) for x, y in zip(adj, fd)]}
 
 
+# Implicit-step schedule of a capsule run that starts from a converged macroscopic field (another DVS's)
+CAPSULE_WARM_RAMP = ((0, 10.0), (100, 30.0), (300, 100.0))
+
+
+def capsule_dvs_study(iters, warm_iters=1000):
+    """The capsule's wall coefficients against the DVS.  The timed workload's set (C1) runs from rest with the
+    schedule of the convergence run; each other set starts from the equilibrium of C1's converged W and runs
+    `warm_iters` iterations (a coarse set from rest does not survive the bow shock's formation at cfl_imp = 1:
+    its state turns non-physical).  Relative differences against C1."""
+    import torch
+
+    from paper_2303_10846_amd.binding import CisError, Solver
+    from paper_2303_10846_amd.cases import configs, dvs
+    case = configs.capsule_case(seed=0)
+    T0 = dvs.total_temperature(1.0, case["mach"])
+    rtop = math.sqrt(0.5 * max(T0, case["T_w"]))
+
+    def run(c, W0, sched, n_it, name):
+        s = Solver(c, precision="mixed", device="cuda:0")
+        s.init_equilibrium(W0)
+        ramp = dict(sched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, res = 0, None
+        while done < n_it:
+            if done in ramp:
+                s.set_numerics(cfl_imp=ramp[done])
+            try:
+                h = s.iterate(100)
+            except CisError as e:
+                print(f"bench: capsule dvs study {name} stopped at {done}: {e}", file=sys.stderr, flush=True)
+                return s, None, done, time.perf_counter() - t0
+            done += 100
+            res = float(h[-1].max())
+            print(f"bench: capsule dvs study {name} {done} iterations, residual {res:.3e}", file=sys.stderr,
+                  flush=True)
+        torch.cuda.synchronize()
+        return s, res, done, time.perf_counter() - t0
+
+    rows = []
+    s, res, done, t = run(case, case["W0"], CAPSULE_CFL_RAMP, iters, "C1")
+    W_ref, _ = s.moments()
+    rows.append(dict(name="C1", radius_over_sqrt_RT0=5.0, n_vel=len(case["u"]), start="rest", iterations=done,
+                     residual=res, ms_per_iter=1e3 * t / max(done, 1), **_coefficients(s, case)))
+    del s
+    torch.cuda.empty_cache()
+    for name, factor, target in CAPSULE_DVS_STUDY:
+        u, w = dvs.paper_unstructured_dvs(case["U_inf"], 1.0, case["T_w"], case["mach"], factor, target=target)
+        c = dict(case, u=u, w=w)
+        print(f"bench: capsule dvs study {name}: radius {factor} sqrt(R T0), {len(u)} velocities", file=sys.stderr,
+              flush=True)
+        s, res, done, t = run(c, W_ref, CAPSULE_WARM_RAMP, warm_iters, name)
+        row = dict(name=name, radius_over_sqrt_RT0=factor, n_vel=len(u), start="C1's converged W",
+                   ball_volume_covered=float(w.sum() / (4.0 / 3.0 * math.pi * (factor * rtop) ** 3)),
+                   iterations=done, residual=res, ms_per_iter=1e3 * t / done if done else None)
+        if res is not None:
+            row.update(_coefficients(s, c))
+            row["rel_diff_vs_C1"] = {k: (row[k] - rows[0][k]) / abs(rows[0][k]) for k in ("Cd", "CQ", "Cp_max", "Ch_max")}
+        rows.append(row)
+        del s
+        torch.cuda.empty_cache()
+    return {"study": "DVS size and extent, capsule Ma 10 Kn 0.01 Tw/Tinf 4.18", "n_cells": len(case["mesh"]["tets"]),
+            "precision": "mixed", "A_ref": "pi D^2 / 4", "cfl_imp_schedule_from_rest": [list(x) for x in CAPSULE_CFL_RAMP],
+            "cfl_imp_schedule_warm": [list(x) for x in CAPSULE_WARM_RAMP], "sets": rows}
+
+
 # Implicit-step schedule of the capsule's convergence run: iteration from which each cfl_imp applies.  Ma 10 from
 # rest needs a small implicit step until the bow shock has formed; afterwards the step grows.
 CAPSULE_CFL_RAMP = ((0, 1.0), (800, 3.0), (1100, 10.0), (1400, 30.0), (1700, 100.0))
@@ -364,7 +441,7 @@ def main():
         print(json.dumps(adjoint_check()))
         return
     if args.dvs_study:
-        print(json.dumps(dvs_study(args.dvs_study)))
+        print(json.dumps(dvs_study(args.dvs_study, args.workload)))
         return
     from paper_2303_10846_amd.cases import configs
     if args.workload == "capsule":
