@@ -74,6 +74,20 @@ def roofline(stage, precision, alg_bytes_iter, ms_iter, launches_iter, workload=
             out["traffic_frac"] = tb / t_launch / 1e9 / HBM_PEAK_GBS
             out["traffic_over_algorithmic"] = tb / per_launch
             out["traffic_source"] = os.path.relpath(path, ROOT)
+    # VALU issue time of the same kernel (SQ_INSTS_VALU, 4 cycles per wavefront instruction) as a fraction of
+    # its duration: how close the kernel is to the instruction-issue bound
+    sq_path = os.path.join(ROOT, "profiles", f"sq_{precision}_{workload}_counters.txt")
+    if os.path.exists(sq_path):
+        lines = open(sq_path).read().splitlines()
+        if any(l.strip() == f"# source_sha256: {prof_summary.source_hash()}" for l in lines[:4]):
+            cur = None
+            for l in lines:
+                if l.startswith("kernel:"):
+                    cur = l.split(":", 1)[1].strip()
+                elif cur and STAGE_KERNEL[stage] in cur and l.strip().startswith("valu_issue_us:"):
+                    out["valu_issue_frac"] = float(l.split(":", 1)[1]) / (t_launch * 1e6)
+                    out["valu_source"] = os.path.relpath(sq_path, ROOT)
+                    break
     return out
 
 
