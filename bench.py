@@ -435,7 +435,7 @@ def main():
                          "and print its residual and wall coefficients every 100 iterations")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the DVS-sharded multi-GPU path is a design, not code); "
+        print("bench.py runs on one GPU only (the DVS-sharded multi-GPU path is a design, not code); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe_mb:

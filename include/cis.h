@@ -48,7 +48,7 @@ enum {
   CIS_E_DVS = -3,         /* weight <= 0 or non-finite velocity */
   CIS_E_DEVICE = -4,      /* a HIP runtime call failed */
   CIS_E_NONFINITE = -5,   /* NaN/Inf, or rho <= 0 / T <= 0 in a predicted or updated cell state */
-  CIS_E_UNSUPPORTED = -6  /* request outside what this build supports (more than 16384 velocities) */
+  CIS_E_UNSUPPORTED = -6  /* request outside what the library supports (more than 16384 velocities) */
 };
 
 enum { CIS_FP64 = 0, CIS_MIXED = 1 };
