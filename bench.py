@@ -417,6 +417,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--sweeps", type=int, nargs=2, default=None, metavar=("N_MACRO", "N_MICRO"),
+                    help="forward + backward pairs of the macro and micro sweeps (default 40 2, the paper's "
+                         "PR-SGS setting; 1 1 is LU-SGS)")
     ap.add_argument("--converge-iters", type=int, default=600,
                     help="iterations (from rest) after which the two precisions' fields are compared")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -465,6 +468,8 @@ def main():
         args.precision = "mixed"
         args.converge_iters = 0
     case = configs.sphere_case(seed=0) if args.workload == "sphere" else configs.capsule_case(seed=0)
+    if args.sweeps:
+        case["num"] = dict(case["num"], n_macro=args.sweeps[0], n_micro=args.sweeps[1])
     print(f"bench: {case['name']} tets={len(case['mesh']['tets'])} nv={len(case['u'])}", file=sys.stderr, flush=True)
     res = {}
     for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
@@ -489,6 +494,9 @@ def main():
     }
     if r["roofline_sweep"]:
         line["roofline_micro_sweep"] = r["roofline_sweep"]
+    if args.converge_iters:
+        line["convergence"] = {"iterations": r["iterations"], "residual_last": r["residual_last"],
+                               "iterations_to_residual": r["iterations_to"], "Qw": r["Qw"]}
     if "fp64" in res and main_key != "fp64":
         f = res["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "roofline": f["roofline"],
