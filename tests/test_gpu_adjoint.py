@@ -148,11 +148,20 @@ def test_adjoint_gradient_matches_complex_step_and_finite_differences():
     say("diagonal preconditioner: iterations", a0["iterations"], "dJdp", a0["dJdp"])
     assert a0["converged"] and a["iterations"] < a0["iterations"]
     assert np.allclose(a0["dJdp"], a["dJdp"], rtol=1e-8, atol=0.0)
-    # and the block preconditioner over (phi, W, q) in fewer still
+    # and the block preconditioner over (phi, W, q) in fewer still, also with the diagonal as its transport part
     ab = s.adjoint(1, 2, restart=60, max_iter=3000, rtol=1e-12, precond_pairs=2, macro_pairs=10)
     say("block preconditioner: iterations", ab["iterations"], "dJdp", ab["dJdp"])
     assert ab["converged"] and ab["iterations"] < a["iterations"]
     assert np.allclose(ab["dJdp"], a["dJdp"], rtol=1e-8, atol=0.0)
+    ad = s.adjoint(1, 2, restart=60, max_iter=3000, rtol=1e-12, precond_pairs=0, macro_pairs=10)
+    say("block preconditioner with the diagonal: iterations", ad["iterations"])
+    assert ad["converged"] and ad["iterations"] < a0["iterations"]
+    assert np.allclose(ad["dJdp"], a["dJdp"], rtol=1e-8, atol=0.0)
+    from paper_2303_10846_amd.binding import CisError
+    for bad in (dict(macro_pairs=201), dict(macro_pairs=-1), dict(precond_pairs=65)):
+        with pytest.raises(CisError) as e:
+            s.adjoint(1, 2, restart=5, max_iter=5, **bad)
+        assert e.value.status == -1
     # oracle: complex step through the iteration from the converged state
     o = oracle.Oracle(c)
     o.set_state(*base)
