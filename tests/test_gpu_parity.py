@@ -286,8 +286,8 @@ def test_mixed_precision_cavity_converged_fields():
 
 @pytest.mark.parametrize("dims", [(8, 8, 4), (9, 9, 6), (7, 7, 7)])
 def test_mixed_micro_sweep_vector_widths(dims):
-    """The mixed micro sweep moves 4, 2 or 1 velocities per thread as one vector, by nv mod 4 (256, 486, 343
-    velocities here): one mixed iteration from the oracle's state against the FP64 oracle's.  The bar is FP32
+    """The mixed micro sweep and micro residual move 4, 2 or 1 velocities per thread as one vector, by nv mod 4
+    (256, 486, 343 velocities here): one mixed iteration from the oracle's state against the FP64 oracle's.  The bar is FP32
     rounding (6e-8) of phi amplified by the cancellation in Res = (phi* - phi)/tau - F, whose terms are up to
     ~1e3 times Res on this nearly resting cavity: measured 0.6-2.2e-5 for all three widths, and the same with
     the one-velocity kernel alone.  A wrong upstream value or upwind bit gives O(1) errors."""
