@@ -31,8 +31,9 @@ namespace cis {
 
 // Velocities per thread in the (cell, chunk) kernels, chunk = kBlock * Vpt<T>: 2 in FP32, 1 in FP64 (measured
 // on the sphere workload: more velocities per thread raise the loads in flight but cost occupancy).  The
-// reconstruction and the micro sweep take one in both precisions (kVptOne: measured faster in FP32, micro
-// 3.84 -> 3.69 ms; the micro residual is faster with two).
+// reconstruction and the scalar micro sweep take one in both precisions (kVptOne: measured faster in FP32).
+// In the mixed mode the micro sweep and the micro residual have vector forms (k_micro_sweep_vec,
+// k_residual_vec) for an nv that is a multiple of 4 or 2.
 template <class T> struct Vpt;
 template <> struct Vpt<double> { static constexpr int v = 1; };
 template <> struct Vpt<float> { static constexpr int v = 2; };
