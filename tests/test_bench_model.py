@@ -1,0 +1,60 @@
+"""The benchmark's byte model, sweep counting and output contract (no GPU)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _sequence(off, n_pairs):
+    """Colour order of n_pairs forward + backward passes, a colour that follows itself relaxed once."""
+    seq = []
+    n = len(off) - 1
+    for _ in range(n_pairs):
+        for c in list(range(n)) + list(range(n - 1, -1, -1)):
+            if off[c + 1] > off[c] and (not seq or seq[-1] != c):
+                seq.append(c)
+    return seq
+
+
+@pytest.mark.parametrize("off,pairs", [([0, 3, 5, 9], 2), ([0, 4, 4, 10], 1), ([0, 7], 3), ([0, 2, 6, 7, 12], 40)])
+def test_sweep_cells_counts_the_deduplicated_relaxations(off, pairs):
+    seq = _sequence(off, pairs)
+    want = sum(off[c + 1] - off[c] for c in seq)
+    assert bench.sweep_cells(off, pairs) == want
+    # three colours, two pairs: 0 1 2 1 0 1 2 1 0 (the last colour once at each turn, the first at the middle)
+    if off == [0, 3, 5, 9] and pairs == 2:
+        assert seq == [0, 1, 2, 1, 0, 1, 2, 1, 0]
+
+
+def test_stage_bytes_model():
+    nc, nf, nv, es, mc = 10, 22, 7, 4, 30
+    sb = bench.stage_bytes(nc, nf, nv, es, mc)
+    assert sb["recon"] == (2 * nc + 2 * nf) * nv * es
+    assert sb["face"] == 4 * nf * nv * es
+    assert sb["residual"] == (2 * nf + 4 * nc) * nv * es
+    assert sb["micro"] == 6 * mc * nv * es
+    assert sb["update"] == 6 * nc * nv * es
+
+
+def test_roofline_carries_the_contract_keys():
+    r = bench.roofline("micro", "mixed", 9.0e9, 2.0, 9.0, workload="no-such-workload")
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in r
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["traffic"] is None                                   # no committed counters for this workload
+    assert abs(r["achieved"] - 9.0e9 / 9 / (2.0e-3 / 9) / 1e9) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-12
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout.strip() == ""
