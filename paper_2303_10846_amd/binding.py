@@ -322,6 +322,31 @@ class Solver:
         _check(self.lib.cis_iterate(self.h, int(n), _dp(hist)))
         return hist
 
+    def converge(self, tol: float = 1e-10, max_iter: int = 10000, cfl_schedule=None, chunk: int = 100,
+                 callback=None) -> np.ndarray:
+        """Iterate until the global average residual (Step 7; the largest of its six components) falls below
+        `tol`, the paper's steady-state criterion (1e-10, Sec. 4), or `max_iter` iterations have run.
+        cfl_schedule: optional (iteration, cfl_imp) pairs, each applied from that iteration on (a small implicit
+        step while a shock forms from rest, a larger one afterwards).  The residual is checked every `chunk`
+        iterations; callback(iteration, history) runs after each chunk.  Returns the residual history."""
+        switch = {int(i): float(c) for i, c in (cfl_schedule or ())}
+        hist = []
+        done = 0
+        while done < max_iter:
+            end = min(done + chunk, max_iter)
+            while done < end:                   # one chunk, the step changed at its scheduled iterations
+                if done in switch:
+                    self.set_numerics(cfl_imp=switch[done])
+                nxt = min([i for i in switch if done < i < end] + [end])
+                hist.append(self.iterate(nxt - done))
+                done = nxt
+            h = np.concatenate(hist)
+            if callback is not None:
+                callback(done, h)
+            if np.any(h.max(axis=1) < tol):
+                return h
+        return np.concatenate(hist) if hist else np.empty((0, 6))
+
     def residual(self):
         """Explicit operator: micro flux F (torch, [nc][nv]) for G and R, macro flux F [nc][6] (numpy)."""
         FG = self.torch.empty_like(self.G)

@@ -219,6 +219,26 @@ def test_maximum_velocity_count():
     assert e.value.status == -6
 
 
+def test_converge_applies_the_step_schedule_and_stops_at_the_criterion():
+    """Solver.converge: the implicit-step schedule takes effect at its iteration (the same history, bit for bit, as
+    switching by hand), and the run stops at the first chunk whose residual is below the paper's 1e-10."""
+    c = configs.cavity_case(n=2, nv_side=6)
+    s1 = solver(c)
+    s1.init_equilibrium(c["W0"])
+    h1 = s1.converge(tol=1e-10, max_iter=600, cfl_schedule=[(0, 2.0), (40, 0.0)], chunk=50)
+    say("converged after", len(h1), "iterations, residual", h1[-1].max())
+    assert h1[-1].max() < 1e-10 and len(h1) % 50 == 0 and len(h1) < 600
+    if len(h1) > 50:
+        assert np.all(h1[: len(h1) - 50].max(axis=1) >= 1e-10)  # not reached before the last chunk
+    s2 = solver(c)
+    s2.init_equilibrium(c["W0"])
+    s2.set_numerics(cfl_imp=2.0)
+    a = s2.iterate(40)
+    s2.set_numerics(cfl_imp=0.0)
+    b = s2.iterate(len(h1) - 40)
+    assert np.array_equal(np.concatenate([a, b]), h1)
+
+
 def test_determinism_bitwise():
     c = configs.small_sphere_case()
     outs = []
