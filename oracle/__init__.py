@@ -76,6 +76,8 @@ def _load():
     lib.orc_equilibrium.argtypes = [d, d, d, C.c_int64, d, d, d, d]
     lib.orc_face_collision.argtypes = [C.c_int64, d, d, d, d, C.c_double, d, d, d, d]
     lib.orc_euler_flux.argtypes = [d, d, d, d]
+    lib.orc_venkat_psi.restype = C.c_double
+    lib.orc_venkat_psi.argtypes = [C.c_double, C.c_double, C.c_double]
     lib.orc_euler_flux_jvp.argtypes = [d, d, d, d, d]
     _lib = lib
     return lib
@@ -136,6 +138,11 @@ def face_collision(u, w, Gbar, Rbar, s: float, gas: dict):
     macro = dict(rho=m[0], U=m[1:4].copy(), T=m[4], Ttr=m[5], Trot=m[6], tau=m[7], q_tr=m[8:11].copy(),
                  q_rot=m[11:14].copy(), sumR=m[14], Erot=m[15])
     return Gf, Rf, macro
+
+
+def venkat_psi(d1: float, d2: float, eps2: float) -> float:
+    """Venkatakrishnan's function of one face, as the oracle's limiter (Eq. 46) uses it."""
+    return float(_load().orc_venkat_psi(float(d1), float(d2), float(eps2)))
 
 
 def euler_flux(W, n, gas: dict, dW=None):

@@ -345,6 +345,15 @@ void rykov_equilibrium(const Prim<S>& p, const S* qtr, const S* qrot, const doub
   }
 }
 
+// Venkatakrishnan's limiter function of one face (the published method the paper cites for Eq. 46):
+// d2 = grad(phi) . (x_f - x_i) is the unlimited change towards the face, d1 the room to the stencil's
+// extremum on that side, eps2 the smoothing constant;
+//   psi = [(d1^2 + eps2) d2 + 2 d2^2 d1] / [d2 (d1^2 + 2 d2^2 + d1 d2 + eps2)],  psi = 1 when d2 = 0.
+template <class S> S venkat_psi(const S& d1, const S& d2, const S& eps2) {
+  if (re(d2) == 0.0) return S(1.0);
+  return ((sq(d1) + eps2) * d2 + 2.0 * sq(d2) * d1) / (d2 * (sq(d1) + 2.0 * sq(d2) + d1 * d2 + eps2));
+}
+
 // u.n with the tie rule: |u.n| <= snap |u| counts as 0 (reading: u.n = 0 is not "> 0", so the
 // upwind cell is x_j, Eq. 46, and the boundary ghost side is used).
 inline double u_dot_n(const Geom& g, int64_t k, const double* n, double snap) {
@@ -561,12 +570,8 @@ template <class S> struct Solver {
               int64_t f = geo.cf[4 * i + a];
               S d2 = 0.0;
               for (int d = 0; d < 3; ++d) d2 += gr[d] * (geo.xf[3 * f + d] - geo.xc[3 * i + d]);
-              S psi = 1.0;
-              if (re(d2) != 0.0) {
-                S d1 = re(d2) > 0.0 ? S(pmax - pi) : S(pmin - pi);
-                psi = ((sq(d1) + eps2) * d2 + 2.0 * sq(d2) * d1) /
-                      (d2 * (sq(d1) + 2.0 * sq(d2) + d1 * d2 + eps2));
-              }
+              S d1 = re(d2) > 0.0 ? S(pmax - pi) : S(pmin - pi);
+              S psi = venkat_psi(d1, d2, eps2);
               if (re(psi) < re(L)) L = psi;  // reading: L = min(1, min_f psi_f)
             }
             // limiter = 2: the same L in the iteration, held fixed in derivatives (frozen limiter), so a
@@ -1221,6 +1226,9 @@ void orc_face_collision(int64_t nv, const double* u, const double* w, const doub
   macro[14] = fs.sumR;
   macro[15] = fs.Erot;
 }
+
+// Venkatakrishnan's function of one face (the function the limiter of Eq. 46 takes the minimum of)
+double orc_venkat_psi(double d1, double d2, double eps2) { return venkat_psi(d1, d2, eps2); }
 
 // Euler flux and its matrix-free / exact increments for a single state (pins of Eq. 40, 42)
 void orc_euler_flux(const double* W, const double* n, const double* gas, double* out) {
