@@ -122,7 +122,8 @@ typedef struct {
 /* Last error message of this thread. */
 const char* cis_last_error(void);
 
-/* Mesh of tetrahedra.  xyz [n_nodes][3]; tet [n_cells][4] node ids; btri [n_b][3] boundary triangles with
+/* Mesh of tetrahedra: the unstructured physical mesh of Sec. 3.1 (cells V_i, interfaces A_ij with unit normals
+   n_ij from cell i to cell j, interface midpoints x_ij of Eq. 46).  xyz [n_nodes][3]; tet [n_cells][4] node ids; btri [n_b][3] boundary triangles with
    tags btag [n_b] (every open face must be tagged).  color_offsets [n_colors+1]: cells
    color_offsets[c] .. color_offsets[c+1]-1 form colour c; no two cells of one colour may share a face
    (checked; the sweeps run colour by colour).  NULL means one cell per colour is not allowed: colours are
@@ -141,8 +142,13 @@ void cis_dvs_destroy(cis_dvs* dvs);
 cis_status cis_state_required_bytes(const cis_mesh* mesh, const cis_dvs* dvs, int32_t precision,
                                     cis_buffer_sizes* out);
 
-/* Create a state on the current HIP device.  `stream` is a hipStream_t (NULL = default stream).
-   The state borrows mesh and dvs, which must outlive it. */
+/* Create a state on the current HIP device: the distributions G, R and the macroscopic W, q of every cell for
+   Steps 2-6 of Sec. 3.5, with the geometry of Step 1 (local steps dt_i by the CFL condition, s_ij = min(dt_i,
+   dt_j) of Eq. 45, least-squares weights of Eq. 46) prepared on the host.  `stream` is a hipStream_t (NULL =
+   default stream).  The state borrows mesh and dvs, which must outlive it.  The initial field is set by
+   cis_state_init_equilibrium (Step 1) or cis_state_set.  Errors: CIS_E_INVALID_ARG (NULL buffers, numerics or
+   gas constants out of range, a boundary tag without a condition), CIS_E_UNSUPPORTED (too many velocities),
+   CIS_E_MESH (singular least-squares matrix), CIS_E_DEVICE. */
 cis_status cis_state_create(const cis_mesh* mesh, const cis_dvs* dvs, const cis_gas* gas, const cis_numerics* num,
                             const cis_bc* bc, int32_t n_bc, int32_t precision, const cis_device_buffers* buf,
                             void* stream, cis_state** out);
@@ -192,6 +198,45 @@ typedef struct {
    force (host [3], or NULL) and heat (host, or NULL) receive the integrated loads. */
 cis_status cis_wall_loads(cis_state* s, int32_t tag, int64_t* n_faces, cis_wall_face* faces, double* force,
                           double* heat);
+
+/* Free-stream references of the wall coefficients (Sec. 4, Eqs. 70-72): dynamic pressure
+   q_inf = rho_inf |U_inf|^2 / 2 and pressure p_inf = rho_inf R T_inf.  A_ref > 0 also asks for the force,
+   moment and heat-load coefficients, with the moment about x_ref scaled by L_ref.  Drag is along U_inf; lift
+   is along the part of lift_dir normal to U_inf (all zero: e_z, or e_y when U_inf is along z). */
+typedef struct {
+  double rho_inf, U_inf[3], T_inf;
+  double A_ref, L_ref, x_ref[3], lift_dir[3];
+} cis_wall_ref;
+
+/* Per wall face: C_p = (p - p_inf)/q_inf (Eq. 70), C_tau = |tau|/q_inf (Eq. 71), C_h = q/(q_inf |U_inf|)
+   (Eq. 72), from the face loads of cis_wall_loads. */
+typedef struct {
+  double Cp, Ctau, Ch;
+} cis_wall_coef;
+
+/* Integrated loads of one wall: force F = sum_f A_f (p n + tau), moment M = sum_f (x_f - x_ref) x A_f (p n + tau),
+   heat load sum_f A_f q; with A_ref > 0 also CF = F/(q_inf A_ref), C_d = CF.e_drag, C_l = CF.e_lift,
+   CM = M/(q_inf A_ref L_ref), the pitching moment C_m = CM.(e_lift x e_drag) and CQ = heat/(q_inf |U_inf| A_ref)
+   (zero when A_ref = 0). */
+typedef struct {
+  double force[3], moment[3], heat;
+  double e_drag[3], e_lift[3];
+  double CF[3], Cd, Cl, CM[3], Cm, CQ;
+} cis_wall_totals;
+
+/* Wall coefficients of Eqs. 70-72 and the force and moment coefficients from per-face loads (host arithmetic
+   only; R is the gas constant of p_inf).  coef (host, [n_faces], or NULL) receives the per-face coefficients
+   in the order of faces; totals (host, or NULL) the integrated values.  CIS_E_INVALID_ARG for NULL
+   faces with n_faces > 0, non-positive rho_inf, |U_inf|, T_inf or R, A_ref < 0, L_ref <= 0 with A_ref > 0,
+   or a lift direction parallel to U_inf. */
+cis_status cis_wall_coefficients_of_loads(const cis_wall_face* faces, int64_t n_faces, double R,
+                                          const cis_wall_ref* ref, cis_wall_coef* coef, cis_wall_totals* totals);
+
+/* The same for the faces of wall `tag` of the current state: runs the face pass (as cis_wall_loads), then
+   cis_wall_coefficients_of_loads with the state's gas constant.  *n_faces (or NULL) receives the face count;
+   coef, if set, must hold that many records (call once with coef = NULL to size it). */
+cis_status cis_wall_coefficients(cis_state* s, int32_t tag, const cis_wall_ref* ref, int64_t* n_faces,
+                                 cis_wall_coef* coef, cis_wall_totals* totals);
 
 /* Small internal arrays of the last iteration, copied to host (for stage-by-stage checks):
    which = 0: dW~ [n_cells][6] (Eq. 43 solution), 1: W~ [n_cells][6], 2: macro flux F [n_cells][6] (Eq. 37),

@@ -28,6 +28,7 @@ EXPORTS = [
     "cis_state_init_equilibrium", "cis_state_set", "cis_state_get", "cis_iterate", "cis_residual", "cis_moments",
     "cis_wall_heat_flux", "cis_debug_stage", "cis_profile_enable", "cis_profile_read", "cis_state_set_bc",
     "cis_steady_residual", "cis_residual_vjp", "cis_adjoint_required_bytes", "cis_adjoint_solve", "cis_wall_loads",
+    "cis_wall_coefficients_of_loads", "cis_wall_coefficients",
 ]
 STAGE_NAMES = ["recon", "face", "macro", "residual", "micro", "update"]
 
@@ -69,6 +70,21 @@ class AdjointInfo(C.Structure):
 class WallFace(C.Structure):
     _fields_ = [("x", C.c_double * 3), ("area", C.c_double), ("n", C.c_double * 3), ("p", C.c_double),
                 ("tau", C.c_double * 3), ("q", C.c_double)]
+
+
+class WallRef(C.Structure):
+    _fields_ = [("rho_inf", C.c_double), ("U_inf", C.c_double * 3), ("T_inf", C.c_double), ("A_ref", C.c_double),
+                ("L_ref", C.c_double), ("x_ref", C.c_double * 3), ("lift_dir", C.c_double * 3)]
+
+
+class WallCoef(C.Structure):
+    _fields_ = [("Cp", C.c_double), ("Ctau", C.c_double), ("Ch", C.c_double)]
+
+
+class WallTotals(C.Structure):
+    _fields_ = [("force", C.c_double * 3), ("moment", C.c_double * 3), ("heat", C.c_double),
+                ("e_drag", C.c_double * 3), ("e_lift", C.c_double * 3), ("CF", C.c_double * 3), ("Cd", C.c_double),
+                ("Cl", C.c_double), ("CM", C.c_double * 3), ("Cm", C.c_double), ("CQ", C.c_double)]
 
 
 class DeviceBuffers(C.Structure):
@@ -143,6 +159,11 @@ def load(allow_build: bool = True):
     lib.cis_profile_read.argtypes = [P, d, i64]
     lib.cis_wall_loads.restype = st
     lib.cis_wall_loads.argtypes = [P, C.c_int32, i64, P, d, d]
+    lib.cis_wall_coefficients_of_loads.restype = st
+    lib.cis_wall_coefficients_of_loads.argtypes = [P, C.c_int64, C.c_double, C.POINTER(WallRef), P,
+                                                   C.POINTER(WallTotals)]
+    lib.cis_wall_coefficients.restype = st
+    lib.cis_wall_coefficients.argtypes = [P, C.c_int32, C.POINTER(WallRef), i64, P, C.POINTER(WallTotals)]
     lib.cis_state_set_bc.restype = st
     lib.cis_state_set_bc.argtypes = [P, C.POINTER(Bc), C.c_int32]
     lib.cis_steady_residual.restype = st
@@ -323,12 +344,13 @@ class Solver:
         return hist
 
     def converge(self, tol: float = 1e-10, max_iter: int = 10000, cfl_schedule=None, chunk: int = 100,
-                 callback=None) -> np.ndarray:
+                 callback=None):
         """Iterate until the global average residual (Step 7; the largest of its six components) falls below
         `tol`, the paper's steady-state criterion (1e-10, Sec. 4), or `max_iter` iterations have run.
         cfl_schedule: optional (iteration, cfl_imp) pairs, each applied from that iteration on (a small implicit
         step while a shock forms from rest, a larger one afterwards).  The residual is checked every `chunk`
-        iterations; callback(iteration, history) runs after each chunk.  Returns the residual history."""
+        iterations; callback(iteration, history) runs after each chunk.  Returns (history, converged): the
+        residual history and whether `tol` was reached (False when the run stopped at max_iter)."""
         switch = {int(i): float(c) for i, c in (cfl_schedule or ())}
         hist = []
         done = 0
@@ -344,8 +366,8 @@ class Solver:
             if callback is not None:
                 callback(done, h)
             if np.any(h.max(axis=1) < tol):
-                return h
-        return np.concatenate(hist) if hist else np.empty((0, 6))
+                return h, True
+        return (np.concatenate(hist) if hist else np.empty((0, 6))), False
 
     def residual(self):
         """Explicit operator: micro flux F (torch, [nc][nv]) for G and R, macro flux F [nc][6] (numpy)."""
@@ -371,6 +393,19 @@ class Solver:
         rec = np.ctypeslib.as_array(C.cast(arr, C.POINTER(C.c_double)), shape=(max(n.value, 1), 12))[: n.value].copy()
         return dict(x=rec[:, 0:3], area=rec[:, 3], n=rec[:, 4:7], p=rec[:, 7], tau=rec[:, 8:11], q=rec[:, 11],
                     force=F, heat=Q.value)
+
+    def wall_coefficients(self, tag: int, rho_inf: float, U_inf, T_inf: float, A_ref: float = None,
+                          L_ref: float = 1.0, x_ref=(0.0, 0.0, 0.0), lift_dir=None) -> dict:
+        """Wall coefficients of `tag` (cis_wall_coefficients): C_p, C_tau, C_h per face (Eqs. 70-72) and, with
+        A_ref, the force, moment and heat-load coefficients; see wall_coefficients() for the keys."""
+        ref = _wall_ref(rho_inf, U_inf, T_inf, A_ref, L_ref, x_ref, lift_dir)
+        n = C.c_int64(0)
+        _check(self.lib.cis_wall_coefficients(self.h, int(tag), C.byref(ref), C.byref(n), None, None))
+        coef = (WallCoef * max(n.value, 1))()
+        tot = WallTotals()
+        _check(self.lib.cis_wall_coefficients(self.h, int(tag), C.byref(ref), C.byref(n), C.cast(coef, C.c_void_p),
+                                              C.byref(tot)))
+        return _coef_dict(coef, n.value, tot, bool(A_ref))
 
     def profile(self, enable: bool = True):
         """Enable (and reset) per-stage hipEvent timing of iterate()."""
@@ -477,7 +512,8 @@ def _steady_residual_function():
         """R(x; p) and J as a differentiable function of (p, G, R, W, q); backward is cis_residual_vjp.
 
         forward copies G, R, W, q into the solver's state buffers and moves its boundary conditions to p
-        (CPU float64 [3]: T_w of wall_tag, rho_inf and |U_inf| of ff_tag)."""
+        (CPU float64 [3]: T_w of wall_tag, rho_inf and |U_inf| of ff_tag).  backward restores the p and state of
+        its own forward before taking the product, and leaves the solver there."""
 
         @staticmethod
         def forward(ctx, solver, wall_tag, ff_tag, p, G, R, W, q):
@@ -490,6 +526,7 @@ def _steady_residual_function():
                 solver.q.copy_(q)
             rG, rR, rW, rq, J = solver.steady_residual(wall_tag)
             ctx.solver, ctx.tags = solver, (wall_tag, ff_tag)
+            ctx.p = p.detach().cpu().numpy().copy()
             ctx.save_for_backward(G, R, W, q)
             return rG, rR, rW, rq, torch.tensor(J, dtype=torch.float64)
 
@@ -497,6 +534,8 @@ def _steady_residual_function():
         def backward(ctx, vG, vR, vW, vq, vJ):
             solver = ctx.solver
             G, R, W, q = ctx.saved_tensors
+            # the product is taken at this graph's p and state, whatever the solver holds now
+            solver.set_params(ctx.p, *ctx.tags)
             with torch.no_grad():
                 solver.G.copy_(G)
                 solver.R.copy_(R)
@@ -521,35 +560,36 @@ def steady_residual_fn(solver, wall_tag, ff_tag, p, G, R, W, q):
     return _SR.apply(solver, wall_tag, ff_tag, p, G, R, W, q)
 
 
+def _wall_ref(rho_inf, U_inf, T_inf, A_ref, L_ref, x_ref, lift_dir) -> WallRef:
+    return WallRef(float(rho_inf), (C.c_double * 3)(*[float(x) for x in U_inf]), float(T_inf), float(A_ref or 0.0),
+                   float(L_ref), (C.c_double * 3)(*[float(x) for x in x_ref]),
+                   (C.c_double * 3)(*([0.0, 0.0, 0.0] if lift_dir is None else [float(x) for x in lift_dir])))
+
+
+def _coef_dict(coef, n: int, tot: WallTotals, with_ref: bool) -> dict:
+    rec = np.ctypeslib.as_array(C.cast(coef, C.POINTER(C.c_double)), shape=(max(n, 1), 3))[:n].copy()
+    out = dict(Cp=rec[:, 0], Ctau=rec[:, 1], Ch=rec[:, 2], force=np.array(tot.force), moment=np.array(tot.moment),
+               heat=tot.heat, e_drag=np.array(tot.e_drag), e_lift=np.array(tot.e_lift))
+    if with_ref:
+        out.update(CF=np.array(tot.CF), Cd=tot.Cd, Cl=tot.Cl, CM=np.array(tot.CM), Cm=tot.Cm, CQ=tot.CQ)
+    return out
+
+
 def wall_coefficients(loads: dict, rho_inf: float, U_inf, T_inf: float, R: float = 0.5, A_ref: float = None,
                       L_ref: float = 1.0, x_ref=(0.0, 0.0, 0.0), lift_dir=None) -> dict:
-    """Wall coefficients from Solver.wall_loads, with q_inf = rho_inf |U_inf|^2 / 2 and p_inf = rho_inf R T_inf.
-
-    Per wall face (Eqs. 70-72): C_p = (p - p_inf) / q_inf, C_tau = |tau| / q_inf, C_h = q / (q_inf |U_inf|).
-    With a reference area A_ref (and length L_ref), from the force F = sum_f A_f (p n + tau) on the wall and its
-    moment M = sum_f (x_f - x_ref) x A_f (p n + tau):  CF = F / (q_inf A_ref); drag Cd = CF . e_D with
-    e_D = U_inf / |U_inf|; lift Cl = CF . e_L with e_L the unit part of lift_dir normal to e_D (default: z, or y
-    when z is along U_inf); CM = M / (q_inf A_ref L_ref) and the pitching moment Cm = CM . (e_L x e_D); and the
-    heat-load coefficient CQ = heat / (q_inf |U_inf| A_ref).
-    """
-    U = np.asarray(U_inf, dtype=float)
-    Um = float(np.linalg.norm(U))
-    qd = 0.5 * rho_inf * Um * Um
-    out = dict(Cp=(loads["p"] - rho_inf * R * T_inf) / qd, Ctau=np.linalg.norm(loads["tau"], axis=1) / qd,
-               Ch=loads["q"] / (qd * Um))
-    if A_ref:
-        eD = U / Um
-        eL = np.array([0.0, 0.0, 1.0]) if lift_dir is None else np.asarray(lift_dir, dtype=float)
-        eL = eL - (eL @ eD) * eD
-        if np.linalg.norm(eL) < 1e-12 and lift_dir is None:
-            eL = np.array([0.0, 1.0, 0.0]) - eD[1] * eD
-        eL = eL / np.linalg.norm(eL)
-        f = loads["area"][:, None] * (loads["p"][:, None] * loads["n"] + loads["tau"])
-        M = np.cross(loads["x"] - np.asarray(x_ref, dtype=float), f).sum(axis=0)
-        out["CF"] = loads["force"] / (qd * A_ref)
-        out["Cd"] = float(out["CF"] @ eD)
-        out["Cl"] = float(out["CF"] @ eL)
-        out["CM"] = M / (qd * A_ref * L_ref)
-        out["Cm"] = float(out["CM"] @ np.cross(eL, eD))
-        out["CQ"] = loads["heat"] / (qd * Um * A_ref)
-    return out
+    """Wall coefficients from per-face loads (the dict of Solver.wall_loads), computed by
+    cis_wall_coefficients_of_loads: per face C_p = (p - p_inf)/q_inf, C_tau = |tau|/q_inf, C_h = q/(q_inf |U_inf|)
+    (Eqs. 70-72) with q_inf = rho_inf |U_inf|^2/2 and p_inf = rho_inf R T_inf; with a reference area A_ref (and
+    length L_ref, moment point x_ref, lift direction lift_dir) also CF, Cd, Cl, CM, Cm and CQ."""
+    lib = load()
+    n = len(loads["p"])
+    arr = (WallFace * max(n, 1))()
+    for f in range(n):
+        arr[f] = WallFace((C.c_double * 3)(*loads["x"][f]), float(loads["area"][f]), (C.c_double * 3)(*loads["n"][f]),
+                          float(loads["p"][f]), (C.c_double * 3)(*loads["tau"][f]), float(loads["q"][f]))
+    ref = _wall_ref(rho_inf, U_inf, T_inf, A_ref, L_ref, x_ref, lift_dir)
+    coef = (WallCoef * max(n, 1))()
+    tot = WallTotals()
+    _check(lib.cis_wall_coefficients_of_loads(C.cast(arr, C.c_void_p), n, float(R), C.byref(ref),
+                                              C.cast(coef, C.c_void_p), C.byref(tot)))
+    return _coef_dict(coef, n, tot, bool(A_ref))

@@ -225,6 +225,46 @@ cis_status dev_dots(cis_state* s, const double* V, int64_t n, int nvec, const do
   return CIS_OK;
 }
 
+// Face pass on the current state, then the per-face wall loads of `tag` (Eqs. 70-72 numerators) from the face
+// macro fluxes, with n from the gas into the wall; F and Q receive the integrated force and heat load.
+cis_status wall_faces(cis_state* s, int32_t tag, std::vector<cis_wall_face>& out, double* F, double* Q) {
+  const cis_mesh* m = s->mesh;
+  cis_status st = dispatch(s, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_recon<T>(s->dev, s->buf, s->stream);
+    launch_face<T>(s->dev, s->buf, s->work, s->stream);
+    return device_check("wall loads");
+  });
+  if (st != CIS_OK) return st;
+  std::vector<double> fm(6 * m->nf);
+  HIP_TRY(hipMemcpyAsync(fm.data(), s->work.face_mac, fm.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  out.clear();
+  F[0] = F[1] = F[2] = 0.0;
+  *Q = 0.0;
+  for (int64_t f = 0; f < m->nf; ++f) {
+    if (m->face_cell[2 * f + 1] >= 0 || m->face_tag[f] != tag) continue;
+    const double A = m->fA[f];
+    const double* n = &m->fn[3 * f];
+    const double* mac = &fm[6 * f];  // A sum_k w (u.n) (G, u G, |u|^2/2 G + R, R)
+    const double mom[3] = {mac[1] / A, mac[2] / A, mac[3] / A};
+    const double p = mom[0] * n[0] + mom[1] * n[1] + mom[2] * n[2];
+    cis_wall_face o;
+    for (int d = 0; d < 3; ++d) {
+      o.x[d] = m->xf[3 * f + d];
+      o.n[d] = n[d];
+      o.tau[d] = mom[d] - p * n[d];
+    }
+    o.area = A;
+    o.p = p;
+    o.q = mac[4] / A;
+    out.push_back(o);
+    for (int d = 0; d < 3; ++d) F[d] += mac[1 + d];
+    *Q += mac[4];
+  }
+  return CIS_OK;
+}
+
 int64_t adjoint_doubles(const cis_state* s, int32_t restart) {
   const int64_t N = 2 * s->mesh->nc * s->dvs->n + 12 * s->mesh->nc;
   return ((int64_t)restart + 4) * N + ((int64_t)restart + 2) * (dot_partials() + 1) +
@@ -856,46 +896,98 @@ cis_status cis_wall_heat_flux(cis_state* s, int32_t tag, double* Q) {
 cis_status cis_wall_loads(cis_state* s, int32_t tag, int64_t* n_faces, cis_wall_face* faces, double* force,
                           double* heat) {
   if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
-  const cis_mesh* m = s->mesh;
-  cis_status st = dispatch(s, [&](auto* tp) {
-    using T = std::remove_pointer_t<decltype(tp)>;
-    launch_recon<T>(s->dev, s->buf, s->stream);
-    launch_face<T>(s->dev, s->buf, s->work, s->stream);
-    return device_check("wall_loads");
-  });
+  std::vector<cis_wall_face> wf;
+  double F[3], Q;
+  cis_status st = wall_faces(s, tag, wf, F, &Q);
   if (st != CIS_OK) return st;
-  std::vector<double> fm(6 * m->nf);
-  HIP_TRY(hipMemcpyAsync(fm.data(), s->work.face_mac, fm.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  int64_t cnt = 0;
-  double F[3] = {0.0, 0.0, 0.0}, Q = 0.0;
-  for (int64_t f = 0; f < m->nf; ++f) {
-    if (m->face_cell[2 * f + 1] >= 0 || m->face_tag[f] != tag) continue;
-    const double A = m->fA[f];
-    const double* n = &m->fn[3 * f];
-    const double* mac = &fm[6 * f];  // A sum_k w (u.n) (G, u G, |u|^2/2 G + R, R)
-    const double mom[3] = {mac[1] / A, mac[2] / A, mac[3] / A};
-    const double p = mom[0] * n[0] + mom[1] * n[1] + mom[2] * n[2];
-    if (faces) {
-      cis_wall_face& o = faces[cnt];
-      for (int d = 0; d < 3; ++d) {
-        o.x[d] = m->xf[3 * f + d];
-        o.n[d] = n[d];
-        o.tau[d] = mom[d] - p * n[d];
-      }
-      o.area = A;
-      o.p = p;
-      o.q = mac[4] / A;
-    }
-    for (int d = 0; d < 3; ++d) F[d] += mac[1 + d];
-    Q += mac[4];
-    ++cnt;
-  }
-  if (n_faces) *n_faces = cnt;
+  if (faces) std::copy(wf.begin(), wf.end(), faces);
+  if (n_faces) *n_faces = (int64_t)wf.size();
   if (force)
     for (int d = 0; d < 3; ++d) force[d] = F[d];
   if (heat) *heat = Q;
   return CIS_OK;
+}
+
+cis_status cis_wall_coefficients_of_loads(const cis_wall_face* faces, int64_t n_faces, double R,
+                                          const cis_wall_ref* ref, cis_wall_coef* coef, cis_wall_totals* totals) {
+  if ((n_faces > 0 && !faces) || n_faces < 0 || !ref) return fail(CIS_E_INVALID_ARG, "NULL argument or bad count");
+  const double* U = ref->U_inf;
+  const double Um = std::sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+  if (!(ref->rho_inf > 0.0) || !(Um > 0.0) || !std::isfinite(Um) || !(ref->T_inf > 0.0) || !(R > 0.0) ||
+      !(ref->A_ref >= 0.0) || (ref->A_ref > 0.0 && !(ref->L_ref > 0.0)) || !finite_all(ref->x_ref, 3) ||
+      !finite_all(ref->lift_dir, 3))
+    return fail(CIS_E_INVALID_ARG, "reference values out of range");
+  const double qd = 0.5 * ref->rho_inf * Um * Um;  // free-stream dynamic pressure
+  const double p_inf = ref->rho_inf * R * ref->T_inf;
+  double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0}, Q = 0.0;
+  for (int64_t f = 0; f < n_faces; ++f) {
+    const cis_wall_face& w = faces[f];
+    const double tmag = std::sqrt(w.tau[0] * w.tau[0] + w.tau[1] * w.tau[1] + w.tau[2] * w.tau[2]);
+    if (coef) {
+      coef[f].Cp = (w.p - p_inf) / qd;    // Eq. 70
+      coef[f].Ctau = tmag / qd;           // Eq. 71
+      coef[f].Ch = w.q / (qd * Um);       // Eq. 72
+    }
+    double fa[3], r[3];
+    for (int d = 0; d < 3; ++d) {
+      fa[d] = w.area * (w.p * w.n[d] + w.tau[d]);
+      r[d] = w.x[d] - ref->x_ref[d];
+      F[d] += fa[d];
+    }
+    M[0] += r[1] * fa[2] - r[2] * fa[1];
+    M[1] += r[2] * fa[0] - r[0] * fa[2];
+    M[2] += r[0] * fa[1] - r[1] * fa[0];
+    Q += w.area * w.q;
+  }
+  if (!totals) return CIS_OK;
+  cis_wall_totals& t = *totals;
+  std::memset(&t, 0, sizeof(t));
+  for (int d = 0; d < 3; ++d) {
+    t.force[d] = F[d];
+    t.moment[d] = M[d];
+  }
+  t.heat = Q;
+  // drag along U_inf; lift along the part of lift_dir normal to it (default e_z, or e_y when U_inf is along z)
+  double eD[3] = {U[0] / Um, U[1] / Um, U[2] / Um}, eL[3];
+  const bool dflt = ref->lift_dir[0] == 0.0 && ref->lift_dir[1] == 0.0 && ref->lift_dir[2] == 0.0;
+  auto project = [&](const double* v) {
+    const double a = v[0] * eD[0] + v[1] * eD[1] + v[2] * eD[2];
+    for (int d = 0; d < 3; ++d) eL[d] = v[d] - a * eD[d];
+    return std::sqrt(eL[0] * eL[0] + eL[1] * eL[1] + eL[2] * eL[2]);
+  };
+  const double ez[3] = {0.0, 0.0, 1.0}, ey[3] = {0.0, 1.0, 0.0};
+  double len = project(dflt ? ez : ref->lift_dir);
+  if (dflt && len < 1e-12) len = project(ey);
+  if (!(len > 1e-12)) return fail(CIS_E_INVALID_ARG, "lift direction is parallel to U_inf");
+  for (int d = 0; d < 3; ++d) {
+    eL[d] /= len;
+    t.e_drag[d] = eD[d];
+    t.e_lift[d] = eL[d];
+  }
+  if (ref->A_ref > 0.0) {
+    const double fs = 1.0 / (qd * ref->A_ref), ms = fs / ref->L_ref;
+    for (int d = 0; d < 3; ++d) {
+      t.CF[d] = F[d] * fs;
+      t.CM[d] = M[d] * ms;
+    }
+    t.Cd = t.CF[0] * eD[0] + t.CF[1] * eD[1] + t.CF[2] * eD[2];
+    t.Cl = t.CF[0] * eL[0] + t.CF[1] * eL[1] + t.CF[2] * eL[2];
+    const double ep[3] = {eL[1] * eD[2] - eL[2] * eD[1], eL[2] * eD[0] - eL[0] * eD[2], eL[0] * eD[1] - eL[1] * eD[0]};
+    t.Cm = t.CM[0] * ep[0] + t.CM[1] * ep[1] + t.CM[2] * ep[2];
+    t.CQ = Q * fs / Um;
+  }
+  return CIS_OK;
+}
+
+cis_status cis_wall_coefficients(cis_state* s, int32_t tag, const cis_wall_ref* ref, int64_t* n_faces,
+                                 cis_wall_coef* coef, cis_wall_totals* totals) {
+  if (!s || !ref) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  std::vector<cis_wall_face> wf;
+  double F[3], Q;
+  cis_status st = wall_faces(s, tag, wf, F, &Q);
+  if (st != CIS_OK) return st;
+  if (n_faces) *n_faces = (int64_t)wf.size();
+  return cis_wall_coefficients_of_loads(wf.data(), (int64_t)wf.size(), s->gas.R, ref, coef, totals);
 }
 
 cis_status cis_profile_enable(cis_state* s, int32_t enable) {

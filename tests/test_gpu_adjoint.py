@@ -236,6 +236,36 @@ def test_steady_residual_autograd_function():
     assert np.allclose(p.grad.numpy(), gp, rtol=1e-12, atol=0.0)
 
 
+def test_steady_residual_backward_uses_its_own_forward_parameters():
+    """Two forwards at p + h and at p before one backward: the backward of the first graph is the product at
+    p + h and its state, not at the boundary conditions the solver holds last."""
+    import torch
+    from paper_2303_10846_amd.binding import steady_residual_fn
+    make, wt, ft = CASES["open_box_lim1"]
+    o, s, (G, R, W, q) = _pair(make(), 4)
+    dev = s.device
+    p0 = s.params(wt, ft)
+    p1 = p0 * np.array([1.05, 0.97, 1.03])
+    rng = np.random.default_rng(9)
+    x1 = [torch.from_numpy(x).to(dev).requires_grad_(True) for x in (G, R, W, q)]
+    x0 = [torch.from_numpy(x * (1.0 + 1e-3 * rng.standard_normal(x.shape))).to(dev) for x in (G, R, W, q)]
+    pt1 = torch.tensor(p1, dtype=torch.float64, requires_grad=True)
+    out1 = steady_residual_fn(s, wt, ft, pt1, *x1)
+    steady_residual_fn(s, wt, ft, torch.tensor(p0, dtype=torch.float64), *x0)   # the solver now holds p0, x0
+    v = [torch.from_numpy(rng.standard_normal(t.shape)).to(dev) for t in out1[:4]]
+    loss = sum((a * b).sum() for a, b in zip(v, out1[:4])) + 0.7 * out1[4].to(dev)
+    loss.backward()
+    # reference: the VJP with the solver set to p1 and x1 by hand
+    s.set_params(p1, wt, ft)
+    with torch.no_grad():
+        for dst, src in zip((s.G, s.R, s.W, s.q), x1):
+            dst.copy_(src)
+    gG, gR, gW, gq, gp = s.residual_vjp(*v, cJ=0.7, wall_tag=wt, ff_tag=ft)
+    for t, g in zip(x1, (gG, gR, gW, gq)):
+        assert nrel(t.grad.cpu().numpy(), g.cpu().numpy()) < 1e-12
+    assert np.allclose(pt1.grad.numpy(), gp, rtol=1e-12, atol=0.0)
+
+
 def test_mixed_precision_state_rejects_the_adjoint():
     from paper_2303_10846_amd.binding import CisError
     c = configs.cavity_case(n=2, nv_side=4)

@@ -225,9 +225,9 @@ def test_converge_applies_the_step_schedule_and_stops_at_the_criterion():
     c = configs.cavity_case(n=2, nv_side=6)
     s1 = solver(c)
     s1.init_equilibrium(c["W0"])
-    h1 = s1.converge(tol=1e-10, max_iter=600, cfl_schedule=[(0, 2.0), (40, 0.0)], chunk=50)
+    h1, ok = s1.converge(tol=1e-10, max_iter=600, cfl_schedule=[(0, 2.0), (40, 0.0)], chunk=50)
     say("converged after", len(h1), "iterations, residual", h1[-1].max())
-    assert h1[-1].max() < 1e-10 and len(h1) % 50 == 0 and len(h1) < 600
+    assert ok and h1[-1].max() < 1e-10 and len(h1) % 50 == 0 and len(h1) < 600
     if len(h1) > 50:
         assert np.all(h1[: len(h1) - 50].max(axis=1) >= 1e-10)  # not reached before the last chunk
     s2 = solver(c)
@@ -237,6 +237,11 @@ def test_converge_applies_the_step_schedule_and_stops_at_the_criterion():
     s2.set_numerics(cfl_imp=0.0)
     b = s2.iterate(len(h1) - 40)
     assert np.array_equal(np.concatenate([a, b]), h1)
+    # a run that stops at max_iter says so
+    s3 = solver(c)
+    s3.init_equilibrium(c["W0"])
+    h3, ok3 = s3.converge(tol=1e-10, max_iter=60, chunk=50)
+    assert not ok3 and len(h3) == 60 and h3[-1].max() >= 1e-10
 
 
 def test_determinism_bitwise():
@@ -369,6 +374,24 @@ def test_wall_loads_match_oracle_face_fluxes():
     assert np.all(np.isfinite(cf["Cp"])) and cf["Cd"] > 0.0
     # a sphere at zero incidence: lift and pitching moment about its centre are small beside the drag
     assert abs(cf["Cl"]) < 0.05 * cf["Cd"] and abs(cf["Cm"]) < 0.05 * cf["Cd"]
+    # cis_wall_coefficients on the state against the Eqs. 70-72 normalisation of the oracle's face fluxes
+    U = np.asarray(c["U_inf"], dtype=float)
+    Um = float(np.linalg.norm(U))
+    qd = 0.5 * 1.0 * Um * Um
+    A_ref, L_ref, x_ref = 0.25 * np.pi, 0.5, np.array([0.1, -0.2, 0.05])
+    co = s.wall_coefficients(1, 1.0, U, 1.0, A_ref=A_ref, L_ref=L_ref, x_ref=x_ref, lift_dir=(0.0, 1.0, 0.0))
+    assert nrel(co["Cp"][ol], (p - 1.0 * 0.5 * 1.0) / qd) < TOL
+    assert nrel(co["Ctau"][ol], np.linalg.norm(tau, axis=1) / qd) < TOL
+    assert nrel(co["Ch"][ol], q / (qd * Um)) < TOL
+    Fo = fm[wall, 1:4].sum(axis=0)
+    Mo = np.cross(g["xf"].reshape(-1, 3)[wall] - x_ref, fm[wall, 1:4]).sum(axis=0)
+    eD, eL = U / Um, np.array([0.0, 1.0, 0.0])
+    assert nrel(co["CF"], Fo / (qd * A_ref)) < TOL
+    assert abs(co["Cd"] - Fo @ eD / (qd * A_ref)) <= TOL * abs(Fo @ eD / (qd * A_ref))
+    assert abs(co["Cl"] - Fo @ eL / (qd * A_ref)) <= TOL * np.max(np.abs(Fo)) / (qd * A_ref)
+    assert nrel(co["CM"], Mo / (qd * A_ref * L_ref)) < TOL
+    assert abs(co["Cm"] - co["CM"] @ np.cross(eL, eD)) <= 1e-14 * np.max(np.abs(co["CM"]))
+    assert abs(co["CQ"] - fm[wall, 4].sum() / (qd * Um * A_ref)) <= TOL * abs(co["CQ"])
 
 
 def test_no_micro_sweeps_means_zero_increments():

@@ -1,4 +1,5 @@
-"""Wall coefficients (Eqs. 70-72 and the force and moment coefficients) from per-face loads: host logic only.
+"""Wall coefficients (Eqs. 70-72 and the force and moment coefficients) from per-face loads: the library's host
+arithmetic (cis_wall_coefficients_of_loads), which needs no GPU.
 
 Synthetic loads on the six unit faces of a cube of side 1 centred at the origin, with n pointing from the gas
 into the body: a uniform pressure gives no net force and no moment; a shear tau0 e_z on the face x = +1/2 gives
@@ -58,6 +59,22 @@ def test_shear_gives_lift_and_pitching_moment():
 
 def test_lift_direction_defaults_to_y_when_the_flow_is_along_z():
     L = _cube_loads(p0=1.0, tau0=0.0)
-    L["force"] = np.array([0.0, 0.7, 0.0])
+    L["tau"][0] = [0.0, 0.7, 0.0]                                       # a shear along y on the face x = +1/2
     c = wall_coefficients(L, 1.0, (0.0, 0.0, 2.0), 1.0, A_ref=1.0)
+    assert np.allclose(c["force"], [0.0, 0.7, 0.0], rtol=0, atol=1e-15)
     assert abs(c["Cl"] - 0.7 / 2.0) < 1e-15 and abs(c["Cd"]) < 1e-15
+    assert np.allclose(c["e_lift"], [0.0, 1.0, 0.0]) and np.allclose(c["e_drag"], [0.0, 0.0, 1.0])
+
+
+def test_bad_references_are_rejected():
+    import pytest
+    from paper_2303_10846_amd.binding import CisError
+    L = _cube_loads(p0=1.0, tau0=0.0)
+    for kw in (dict(rho_inf=0.0), dict(U_inf=(0.0, 0.0, 0.0)), dict(T_inf=-1.0)):
+        args = dict(rho_inf=1.0, U_inf=(1.0, 0.0, 0.0), T_inf=1.0)
+        args.update(kw)
+        with pytest.raises(CisError) as e:
+            wall_coefficients(L, args["rho_inf"], args["U_inf"], args["T_inf"], A_ref=1.0)
+        assert e.value.status == -1
+    with pytest.raises(CisError):
+        wall_coefficients(L, 1.0, (1.0, 0.0, 0.0), 1.0, A_ref=1.0, lift_dir=(2.0, 0.0, 0.0))
