@@ -48,21 +48,48 @@ def stage_bytes(nc, nf, nv, es, micro_cells):
     }
 
 
+# Algorithmic words per (cell, velocity) of the scope table's byte model (one word = one G or R value):
+# the face pass reads phi^n and writes the micro flux F (2 + 2), the residual reads phi^n and F and writes Res
+# (6), each micro relaxation reads Res and the upstream increment and writes the increment (6 per relaxed cell),
+# the update reads phi and dphi and writes phi (6).  Four half-sweeps give the model's 40 words per iteration.
+MODEL_WORDS = {"face": 4, "residual": 6, "micro_per_relaxation": 6, "update": 6}
+MODEL_WORDS_PER_ITER = 40
+
+
+def model_bytes(nc, nv, es, micro_cells):
+    """Algorithmic bytes per iteration of each stage by the scope table's per-(cell, velocity) words.  The
+    face pass (reconstruction + face kernels) is charged to the face kernel, which it is timed against."""
+    return {
+        "face": MODEL_WORDS["face"] * nc * nv * es,
+        "residual": MODEL_WORDS["residual"] * nc * nv * es,
+        "micro": MODEL_WORDS["micro_per_relaxation"] * micro_cells * nv * es,
+        "update": MODEL_WORDS["update"] * nc * nv * es,
+    }
+
+
 STAGE_KERNEL = {"recon": "k_recon", "face": "k_face", "residual": "k_residual", "micro": "k_micro_sweep",
                 "update": "k_update"}
 
 
-def roofline(stage, precision, alg_bytes_iter, ms_iter, launches_iter, workload="sphere"):
-    """Roofline of the dominant stage: algorithmic bytes per launch over the average launch duration (hipEvents
-    on the library's stream), and the counter-measured HBM bytes per launch when the committed rocprofv3
-    summary still matches the kernel sources."""
+def roofline(stage, precision, alg_bytes_iter, ms_iter, launches_iter, workload="sphere", kernel_bytes_iter=None):
+    """Roofline of one stage: algorithmic bytes per launch (the scope table's per-(cell, velocity) words, as
+    alg_bytes_iter) over the average launch duration (hipEvents on the library's stream), and the
+    counter-measured HBM bytes per launch when the committed rocprofv3 summary still matches the kernel sources.
+    kernel_bytes_iter, if given, is the same stage under the per-kernel model (every value the kernel itself
+    reads or writes, once), reported beside it as `kernel_model`."""
     from paper_2303_10846_amd import prof_summary
     per_launch = alg_bytes_iter / launches_iter
     t_launch = ms_iter * 1e-3 / launches_iter
     ach = per_launch / t_launch / 1e9
     out = {"kernel": STAGE_KERNEL[stage], "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": ach / HBM_PEAK_GBS, "traffic": None, "launches_per_iter": launches_iter,
-           "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": t_launch * 1e6}
+           "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": t_launch * 1e6,
+           "byte_model": "scope table words per (cell, velocity)"}
+    if kernel_bytes_iter is not None:
+        kb = kernel_bytes_iter / launches_iter
+        out["kernel_model"] = {"bytes_per_launch": kb, "achieved": kb / t_launch / 1e9,
+                               "frac": kb / t_launch / 1e9 / HBM_PEAK_GBS,
+                               "basis": "every value the kernel reads or writes, once"}
     path = os.path.join(ROOT, "profiles", f"{stage}_{precision}_{workload}_counters.txt")
     if os.path.exists(path):
         c = prof_summary.read_counters(path)
@@ -126,23 +153,36 @@ def run_path(case, precision, steps, warmup, converge_iters, workload="sphere"):
     to_level = {f"{lv:.0e}": (int(np.argmax(res <= lv)) + 1 if np.any(res <= lv) else None) for lv in (1e-4, 1e-5, 1e-6)}
     pairs = s.nc * s.nv
     es = 8 if precision == "fp64" else 4
-    sb = stage_bytes(s.nc, s.nf, s.nv, es, sweep_cells(case["mesh"]["color_offsets"], case["num"]["n_micro"]))
+    mcells = sweep_cells(case["mesh"]["color_offsets"], case["num"]["n_micro"])
+    sb = stage_bytes(s.nc, s.nf, s.nv, es, mcells)
+    mb = model_bytes(s.nc, s.nv, es, mcells)
     stages = {}
     for k, (ms, nl) in prof.items():
         e = dict(ms_per_iter=ms / steps, launches_per_iter=nl / steps)
         if k in sb:
-            e["algorithmic_GB_per_iter"] = sb[k] / 1e9
-            e["achieved_GBs"] = sb[k] * steps / (ms * 1e-3) / 1e9 if ms > 0 else None
+            e["kernel_GB_per_iter"] = sb[k] / 1e9
+            e["kernel_GBs"] = sb[k] * steps / (ms * 1e-3) / 1e9 if ms > 0 else None
+        if k in mb:
+            e["algorithmic_GB_per_iter"] = mb[k] / 1e9
+            e["achieved_GBs"] = mb[k] * steps / (ms * 1e-3) / 1e9 if ms > 0 else None
         stages[k] = e
-    hbm = {k: v for k, v in stages.items() if k in sb}
+    hbm = {k: v for k, v in stages.items() if k in mb}
     dom = max(hbm, key=lambda k: hbm[k]["ms_per_iter"])
-    roof = roofline(dom, precision, sb[dom], prof[dom][0] / steps, prof[dom][1] / steps, workload)
+    roof = roofline(dom, precision, mb[dom], prof[dom][0] / steps, prof[dom][1] / steps, workload, sb[dom])
     # the micro sweep (the HBM-bound implicit sweep) beside the dominant kernel when that is another one
-    roof_sweep = (roofline("micro", precision, sb["micro"], prof["micro"][0] / steps, prof["micro"][1] / steps,
-                           workload) if dom != "micro" and "micro" in prof and prof["micro"][1] else None)
+    roof_sweep = (roofline("micro", precision, mb["micro"], prof["micro"][0] / steps, prof["micro"][1] / steps,
+                           workload, sb["micro"]) if dom != "micro" and "micro" in prof and prof["micro"][1]
+                  else None)
+    # the whole iteration against the scope table's 40 words per (cell, velocity)
+    t_iter = t / steps
+    it_bytes = MODEL_WORDS_PER_ITER * pairs * es
+    roof_iter = {"bound": "hbm", "achieved": it_bytes / t_iter / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": it_bytes / t_iter / 1e9 / HBM_PEAK_GBS, "bytes_per_iteration": it_bytes,
+                 "words_per_pair": MODEL_WORDS_PER_ITER, "ms_per_iteration": 1e3 * t_iter}
     out = dict(value=pairs * steps / t, ms_per_step=1e3 * t / steps, pairs=pairs, n_cells=s.nc, n_faces=s.nf,
                n_vel=s.nv, residual_last=float(hist[-1].max()), iterations=max(done, warmup + 2 * steps),
-               stages=stages, roofline=roof, roofline_sweep=roof_sweep, Qw=Qw, W=W, iterations_to=to_level)
+               stages=stages, roofline=roof, roofline_sweep=roof_sweep, roofline_iteration=roof_iter, Qw=Qw, W=W,
+               iterations_to=to_level)
     del s
     torch.cuda.empty_cache()
     return out
@@ -491,6 +531,7 @@ def main():
                    "precision": main_key, "n_macro_sweeps": case["num"]["n_macro"],
                    "n_micro_sweeps": case["num"]["n_micro"]},
         "roofline": r["roofline"],
+        "roofline_iteration": r["roofline_iteration"],
         "stages": r["stages"],
     }
     if r["roofline_sweep"]:
@@ -501,7 +542,8 @@ def main():
     if "fp64" in res and main_key != "fp64":
         f = res["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "roofline": f["roofline"],
-                        "roofline_micro_sweep": f["roofline_sweep"], "stages": f["stages"]}
+                        "roofline_micro_sweep": f["roofline_sweep"], "roofline_iteration": f["roofline_iteration"],
+                        "stages": f["stages"]}
         Wm, Wd = r["W"], f["W"]
 
         def rho_T(W):

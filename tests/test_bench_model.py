@@ -42,6 +42,18 @@ def test_stage_bytes_model():
     assert sb["update"] == 6 * nc * nv * es
 
 
+def test_scope_table_byte_model():
+    nc, nv, es, mc = 10, 7, 4, 30
+    mb = bench.model_bytes(nc, nv, es, mc)
+    assert mb["face"] == 4 * nc * nv * es           # face pass: read phi (G, R), write F (G, R)
+    assert mb["residual"] == 6 * nc * nv * es
+    assert mb["micro"] == 6 * mc * nv * es
+    assert mb["update"] == 6 * nc * nv * es
+    # four full half-sweeps (mc = 4 nc) give the model's 40 words per (cell, velocity)
+    full = bench.model_bytes(nc, nv, es, 4 * nc)
+    assert sum(full.values()) == bench.MODEL_WORDS_PER_ITER * nc * nv * es
+
+
 def test_roofline_carries_the_contract_keys():
     r = bench.roofline("micro", "mixed", 9.0e9, 2.0, 9.0, workload="no-such-workload")
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
@@ -50,6 +62,8 @@ def test_roofline_carries_the_contract_keys():
     assert r["traffic"] is None                                   # no committed counters for this workload
     assert abs(r["achieved"] - 9.0e9 / 9 / (2.0e-3 / 9) / 1e9) < 1e-9
     assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-12
+    r2 = bench.roofline("face", "mixed", 3.0e9, 3.0, 1.0, workload="no-such-workload", kernel_bytes_iter=6.0e9)
+    assert abs(r2["achieved"] - 1000.0) < 1e-9 and abs(r2["kernel_model"]["achieved"] - 2000.0) < 1e-9
 
 
 def test_more_than_one_gpu_exits_with_a_message():
