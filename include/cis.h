@@ -167,6 +167,16 @@ cis_status cis_state_get(cis_state* s, void* G, void* R, double* W, double* q);
    (1/N_c) sum_i |W_i^{n+1} - W_i^n| per component after each iteration (Step 7). */
 cis_status cis_iterate(cis_state* s, int32_t n_iter, double* res_hist);
 
+/* cis_iterate for callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc): the same kernels and results, bitwise, but no hipMalloc, hipFree, event or
+   other allocation.  The residual partial sums, the residual history and the positivity flags live in a fixed
+   device array of the library (about 205 KB per GPU, held until the process ends) instead of the state's
+   own, so n_iter is limited to 0..4096 per call (CIS_E_INVALID_ARG beyond, before any device work).  Every
+   call on one GPU shares that array: calls that overlap on one GPU (two host threads, or states on different
+   streams) race and must be serialised by the caller.  Per-stage profiling (cis_profile_enable) does not
+   apply.  res_hist (host, [n_iter][6], or NULL) as for cis_iterate; synchronises the state's stream. */
+cis_status cis_iterate_noalloc(cis_state* s, int32_t n_iter, double* res_hist);
+
 /* Explicit operator on the current state (Steps 2-3): micro flux F [n_cells][n_vel] (Eq. 31) into the
    device arrays FG, FR (state precision) and macro flux F [n_cells][6] (Eq. 37) into host Fmac (or NULL). */
 cis_status cis_residual(cis_state* s, void* FG_dev, void* FR_dev, double* Fmac_host);

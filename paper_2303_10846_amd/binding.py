@@ -28,7 +28,7 @@ EXPORTS = [
     "cis_state_init_equilibrium", "cis_state_set", "cis_state_get", "cis_iterate", "cis_residual", "cis_moments",
     "cis_wall_heat_flux", "cis_debug_stage", "cis_profile_enable", "cis_profile_read", "cis_state_set_bc",
     "cis_steady_residual", "cis_residual_vjp", "cis_adjoint_required_bytes", "cis_adjoint_solve", "cis_wall_loads",
-    "cis_wall_coefficients_of_loads", "cis_wall_coefficients",
+    "cis_wall_coefficients_of_loads", "cis_wall_coefficients", "cis_iterate_noalloc",
 ]
 STAGE_NAMES = ["recon", "face", "macro", "residual", "micro", "update"]
 
@@ -145,6 +145,8 @@ def load(allow_build: bool = True):
     lib.cis_state_get.argtypes = [P, P, P, d, d]
     lib.cis_iterate.restype = st
     lib.cis_iterate.argtypes = [P, C.c_int32, d]
+    lib.cis_iterate_noalloc.restype = st
+    lib.cis_iterate_noalloc.argtypes = [P, C.c_int32, d]
     lib.cis_residual.restype = st
     lib.cis_residual.argtypes = [P, P, P, d]
     lib.cis_moments.restype = st
@@ -341,6 +343,12 @@ class Solver:
     def iterate(self, n: int = 1) -> np.ndarray:
         hist = np.empty((n, 6))
         _check(self.lib.cis_iterate(self.h, int(n), _dp(hist)))
+        return hist
+
+    def iterate_noalloc(self, n: int = 1) -> np.ndarray:
+        """iterate() through cis_iterate_noalloc: no device allocation, n <= 4096 per call."""
+        hist = np.empty((n, 6))
+        _check(self.lib.cis_iterate_noalloc(self.h, int(n), _dp(hist)))
         return hist
 
     def converge(self, tol: float = 1e-10, max_iter: int = 10000, cfl_schedule=None, chunk: int = 100,

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <unordered_map>
@@ -17,6 +18,17 @@
 #include "cis_internal.h"
 
 using namespace cis;
+
+// Device scratch of cis_iterate_noalloc, one copy per GPU, held until the process ends: the flags (4 int32 in
+// the first 256 bytes), the kResidualParts x 6 residual partial sums, and the residual history of up to
+// kNoAllocMaxIter iterations.  Host code never uses the name `scratch` as an address: it takes the device
+// address from hipGetSymbolAddress once per device (scratch_of_device) and passes that.
+static constexpr int32_t kNoAllocMaxIter = 4096;
+static constexpr size_t kScratchFlagDoubles = 32;
+static constexpr size_t kScratchPartDoubles = 6 * (size_t)kResidualParts;
+static constexpr size_t kScratchDoubles = kScratchFlagDoubles + kScratchPartDoubles + 6 * (size_t)kNoAllocMaxIter;
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -94,6 +106,7 @@ struct cis_state {
   std::vector<cis_bc> bcs;
   int32_t precision = CIS_FP64;
   hipStream_t stream = nullptr;
+  int device = 0;  // the HIP device current at cis_state_create
   Dev dev{};
   Bufs buf{};
   Work work{};
@@ -262,6 +275,63 @@ cis_status wall_faces(cis_state* s, int32_t tag, std::vector<cis_wall_face>& out
     for (int d = 0; d < 3; ++d) F[d] += mac[1 + d];
     *Q += mac[4];
   }
+  return CIS_OK;
+}
+
+// Steps 2-6, n_iter times, on the state's stream, with the work arrays `w`; mark(it, k) runs between the stages.
+template <class Mark> cis_status enqueue_iterations(cis_state* s, const Work& w, int32_t n_iter, Mark&& mark) {
+  const cis_mesh* m = s->mesh;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s->stream, w.flag, 4);
+  return dispatch(s, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    for (int32_t it = 0; it < n_iter; ++it) {
+      mark(it, 0);
+      launch_recon<T>(s->dev, s->buf, s->stream);
+      mark(it, 1);
+      launch_face<T>(s->dev, s->buf, w, s->stream);
+      mark(it, 2);
+      launch_macro(s->dev, s->buf, w, m->color_off.data(), m->n_colors, s->num.n_macro, s->stream);
+      mark(it, 3);
+      launch_residual<T>(s->dev, s->buf, w, s->buf.resG, s->buf.resR, 0, s->stream);
+      mark(it, 4);
+      launch_micro<T>(s->dev, s->buf, w, m->color_off.data(), m->n_colors, s->num.n_micro, s->stream);
+      mark(it, 5);
+      launch_update<T>(s->dev, s->buf, w, it, s->stream);
+      mark(it, 6);
+    }
+    return device_check("iterate");
+  });
+}
+
+// Copy the residual history (Step 7) of the last n_iter iterations and the positivity flags back; synchronises.
+cis_status finish_iterations(cis_state* s, const Work& w, int32_t n_iter, double* res_hist) {
+  int32_t flag[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(flag, w.flag, sizeof(flag), hipMemcpyDeviceToHost, s->stream));
+  if (res_hist)
+    HIP_TRY(hipMemcpyAsync(res_hist, w.res, 6 * (size_t)n_iter * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (flag[0]) return fail(CIS_E_NONFINITE, "non-finite or non-positive state (flag " + std::to_string(flag[0]) + ")");
+  return CIS_OK;
+}
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up on the first call for that device (with it current).
+cis_status scratch_of_device(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return fail(CIS_E_UNSUPPORTED, "device index beyond the scratch table");
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return fail(CIS_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
   return CIS_OK;
 }
 
@@ -546,6 +616,10 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   s->bcs.assign(bc, bc + n_bc);
   s->precision = precision;
   s->stream = (hipStream_t)stream;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(CIS_E_DEVICE, "hipGetDevice failed");
+  }
   const int64_t nc = m->nc, nf = m->nf, nv = dv->n;
 
   // geometry that depends on the DVS: dt_i = cfl h_i / max|u|, s_f, Delta l_f, least-squares weights
@@ -801,7 +875,6 @@ cis_status cis_iterate(cis_state* s, int32_t n_iter, double* res_hist) {
     s->work.res = nr;
     s->res_cap = n_iter;
   }
-  const cis_mesh* m = s->mesh;
   std::vector<hipEvent_t> ev;
   if (s->profile) {
     ev.resize(7 * (size_t)n_iter, nullptr);
@@ -810,27 +883,9 @@ cis_status cis_iterate(cis_state* s, int32_t n_iter, double* res_hist) {
   auto mark = [&](int32_t it, int k) {
     if (s->profile) (void)hipEventRecord(ev[7 * (size_t)it + k], s->stream);
   };
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s->stream, s->work.flag, 4);
-  cis_status st = dispatch(s, [&](auto* tp) {
-    using T = std::remove_pointer_t<decltype(tp)>;
-    for (int32_t it = 0; it < n_iter; ++it) {
-      mark(it, 0);
-      launch_recon<T>(s->dev, s->buf, s->stream);
-      mark(it, 1);
-      launch_face<T>(s->dev, s->buf, s->work, s->stream);
-      mark(it, 2);
-      launch_macro(s->dev, s->buf, s->work, m->color_off.data(), m->n_colors, s->num.n_macro, s->stream);
-      mark(it, 3);
-      launch_residual<T>(s->dev, s->buf, s->work, s->buf.resG, s->buf.resR, 0, s->stream);
-      mark(it, 4);
-      launch_micro<T>(s->dev, s->buf, s->work, m->color_off.data(), m->n_colors, s->num.n_micro, s->stream);
-      mark(it, 5);
-      launch_update<T>(s->dev, s->buf, s->work, it, s->stream);
-      mark(it, 6);
-    }
-    return device_check("iterate");
-  });
+  cis_status st = enqueue_iterations(s, s->work, n_iter, mark);
   if (s->profile) {
+    const cis_mesh* m = s->mesh;
     (void)hipStreamSynchronize(s->stream);
     const int64_t nmac = (int64_t)sweep_sequence(m->color_off.data(), m->n_colors, s->num.n_macro).size();
     const int64_t nmic = (int64_t)sweep_sequence(m->color_off.data(), m->n_colors, s->num.n_micro).size();
@@ -845,14 +900,26 @@ cis_status cis_iterate(cis_state* s, int32_t n_iter, double* res_hist) {
     for (auto& e : ev) (void)hipEventDestroy(e);
   }
   if (st != CIS_OK) return st;
-  int32_t flag[4] = {0, 0, 0, 0};
-  std::vector<double> hist(6 * (size_t)n_iter);
-  HIP_TRY(hipMemcpyAsync(flag, s->work.flag, sizeof(flag), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipMemcpyAsync(hist.data(), s->work.res, hist.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  if (res_hist) std::copy(hist.begin(), hist.end(), res_hist);
-  if (flag[0]) return fail(CIS_E_NONFINITE, "non-finite or non-positive state (flag " + std::to_string(flag[0]) + ")");
-  return CIS_OK;
+  return finish_iterations(s, s->work, n_iter, res_hist);
+}
+
+cis_status cis_iterate_noalloc(cis_state* s, int32_t n_iter, double* res_hist) {
+  if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
+  if (n_iter < 0 || n_iter > kNoAllocMaxIter)
+    return fail(CIS_E_INVALID_ARG, "n_iter must be in 0.." + std::to_string(kNoAllocMaxIter) +
+                                       " for cis_iterate_noalloc (its residual history lives in a fixed device array)");
+  if (n_iter == 0) return CIS_OK;
+  double* sp = nullptr;
+  cis_status st = scratch_of_device(s->device, &sp);
+  if (st != CIS_OK) return st;
+  // the state's work arrays, with the residual partials, the history and the flags in this device's scratch
+  Work w = s->work;
+  w.flag = reinterpret_cast<int32_t*>(sp);
+  w.respart = sp + kScratchFlagDoubles;
+  w.res = sp + kScratchFlagDoubles + kScratchPartDoubles;
+  st = enqueue_iterations(s, w, n_iter, [](int32_t, int) {});
+  if (st != CIS_OK) return st;
+  return finish_iterations(s, w, n_iter, res_hist);
 }
 
 cis_status cis_residual(cis_state* s, void* FG, void* FR, double* Fmac) {

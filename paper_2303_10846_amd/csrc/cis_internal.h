@@ -60,6 +60,10 @@ struct Dev {
   int limiter;
 };
 
+// Step 7's residual is reduced in two stages over a fixed partition of the cells: kResidualParts partial sums of
+// 6 doubles each (Work::respart), then one workgroup adds them in order.
+constexpr int kResidualParts = 256;
+
 struct Work {
   double* face_mac;  // [nf][6]
   double* cell_prim; // [nc][8]: rho U T T_tr tau 0
@@ -74,7 +78,7 @@ struct Work {
   double* eq;        // [nc][ER]
   double* cellres;   // [nc][6]
   double* res;       // [hist][6]
-  double* respart;   // [256][6] partial sums of the residual
+  double* respart;   // [kResidualParts][6] partial sums of the residual
   int32_t* flag;     // [4]
   double* gpf;       // [nf][3] per-face parameter adjoints of the VJP
 };

@@ -1320,7 +1320,7 @@ template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update
   }
 }
 
-constexpr int kResParts = 256;
+constexpr int kResParts = kResidualParts;
 
 // Step 7, stage 1: partial sums of |W^{n+1} - W^n| over a fixed cell partition (deterministic), positivity check
 __global__ __launch_bounds__(kBlock) void k_reduce_res_part(int64_t nc, const double* cellres, double* part,
