@@ -74,7 +74,10 @@ typedef struct {
    lim_K    : Venkatakrishnan constant, eps^2 = (K h)^3 max_stencil|phi|^2.
    limiter  : 0 off; 1 Venkatakrishnan, differentiated by cis_residual_vjp on the branch the state takes;
               2 the same limiter in the iteration, held fixed (frozen) by cis_residual_vjp, whose product is
-              then the derivative of the scheme with the limiter values of the current state.
+              then the derivative of the scheme with the limiter values of the current state;
+              3 frozen values: the values stored by cis_limiter_freeze are used in place of the limiter in every
+              reconstruction (and are constants of cis_residual_vjp).  Refused until cis_limiter_freeze has
+              attached them.
    snap     : |u.n| <= snap |u| counts as u.n = 0 (upwind side x_j, Eq. 46).
    n_macro, n_micro : forward+backward sweep pairs of the macro (Eq. 43) and micro (Eq. 33) PR-SGS. */
 typedef struct {
@@ -154,6 +157,15 @@ cis_status cis_state_create(const cis_mesh* mesh, const cis_dvs* dvs, const cis_
                             void* stream, cis_state** out);
 cis_status cis_state_set_numerics(cis_state* s, const cis_numerics* num);
 void cis_state_destroy(cis_state* s);
+
+/* Limiter freezing.  Computes Venkatakrishnan's limiter values L of the current state (Eq. 46, as limiter 1, with
+   the state's lim_K) for every (cell, velocity) of G and of R into L, caller-owned device memory of
+   2 * n_cells * n_vel values in the state's precision ([G | R], each [n_cells][n_vel]), and attaches L to the
+   state: with numerics.limiter = 3 the reconstruction then uses these values instead of recomputing them, so
+   the scheme near a steady state is a smooth function of phi (the min over faces and the stencil extrema no
+   longer switch).  L must stay valid while attached; the face buffers are overwritten.  L = NULL detaches
+   (refused while limiter 3 is in use).  Errors: CIS_E_INVALID_ARG, CIS_E_DEVICE. */
+cis_status cis_limiter_freeze(cis_state* s, void* L);
 
 /* Step 1: phi = phi*(W0, q = 0) in every cell (Eqs. 17-23).  W0 is host [6] (per_cell = 0) or
    [n_cells][6] (per_cell = 1). */

@@ -67,6 +67,7 @@ def _load():
     lib.orc_steady_residual.argtypes = [P, C.c_int32, d, d, d, d, d]
     lib.orc_steady_residual_jvp.argtypes = [P, C.c_int32, C.c_int32, d, d, d, d, d, C.c_double, d, d, d, d, d]
     lib.orc_set_num.argtypes = [P, d]
+    lib.orc_freeze_limiter.argtypes = [P]
     lib.orc_stage.restype = C.c_int64
     lib.orc_stage.argtypes = [P, C.c_int32, d]
     lib.orc_wall_heat_flux.restype = C.c_double
@@ -242,6 +243,11 @@ class Oracle:
         self.num.update(changes)
         self._num = num_array(self.num)
         self.lib.orc_set_num(self.sol, _dp(self._num))
+
+    def freeze_limiter(self):
+        """Store the limiter values of the current state and switch to limiter 3, which uses them."""
+        self.lib.orc_freeze_limiter(self.sol)
+        self.set_num(limiter=3)
 
     def explicit(self):
         """Steps 2-3 on the current state (fills FG, FR, Fmac, Qface, gradG, gradR, ff*)."""

@@ -476,6 +476,8 @@ template <class S> struct Solver {
   std::vector<S> G, R, W, q;  // state: phi [nc][nv]; W, q [nc][6]
   // stage outputs of the last pass
   std::vector<S> gradG, gradR;  // L * grad(phi), [nc][nv][3]
+  std::vector<double> LfG, LfR; // limiter = 3: frozen limiter values, [nc][nv]
+  bool capture = false;         // store the limiter values of the next reconstruction into LfG, LfR
   std::vector<S> ffG, ffR;      // face flux A (u.n) phi_f, [nf][nv]
   std::vector<S> ffmac;         // face macro flux A sum_k w (u.n) Phi phi_f, [nf][6]
   std::vector<S> Qface;         // A sum_k w (u.n)(|u|^2/2 G_f + R_f) on boundary faces, [nf]
@@ -537,11 +539,17 @@ template <class S> struct Solver {
     size_t P = size_t(nc) * nv;
     gradG.assign(3 * P, 0.0);
     gradR.assign(3 * P, 0.0);
+    if (capture) {
+      LfG.assign(P, 1.0);
+      LfR.assign(P, 1.0);
+    }
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < nc; ++i) {
       for (int which = 0; which < 2; ++which) {
         const std::vector<S>& phi = which == 0 ? G : R;
         std::vector<S>& out = which == 0 ? gradG : gradR;
+        std::vector<double>& Lf = which == 0 ? LfG : LfR;
+        const int lim = capture ? 1 : num.limiter;
         const double* Mi = &geo.Minv[9 * i];
         double kh3 = std::pow(num.lim_K * geo.h[i], 3.0);
         for (int64_t k = 0; k < nv; ++k) {
@@ -565,7 +573,10 @@ template <class S> struct Solver {
           // eps^2 is a function of phi: it carries the derivative of max(|phi_max|, |phi_min|)^2
           S scale = std::fabs(re(pmax)) >= std::fabs(re(pmin)) ? pmax : pmin;
           S eps2 = kh3 * scale * scale;
-          if (num.limiter) {
+          if (lim == 3) {
+            // frozen values (limiter freezing): a constant of every derivative
+            L = S(Lf[size_t(i) * nv + k]);
+          } else if (lim) {
             for (int a = 0; a < 4; ++a) {
               int64_t f = geo.cf[4 * i + a];
               S d2 = 0.0;
@@ -576,7 +587,8 @@ template <class S> struct Solver {
             }
             // limiter = 2: the same L in the iteration, held fixed in derivatives (frozen limiter), so a
             // complex step carries none of it
-            if (num.limiter == 2) L = S(re(L));
+            if (lim == 2) L = S(re(L));
+            if (capture) Lf[size_t(i) * nv + k] = re(L);
           }
           for (int d = 0; d < 3; ++d) out[3 * (size_t(i) * nv + k) + d] = L * gr[d];
         }
@@ -1046,6 +1058,14 @@ int32_t orc_iterate(void* sp, int32_t n, double* res_hist) {
   return 0;
 }
 
+// Limiter freezing: store the limiter values (limiter 1's) of the current state; limiter = 3 then uses them.
+void orc_freeze_limiter(void* sp) {
+  auto* s = static_cast<Solver<double>*>(sp);
+  s->capture = true;
+  s->reconstruct_gradients();
+  s->capture = false;
+}
+
 // Replace the numerics constants (e.g. the implicit time step between iterations)
 void orc_set_num(void* sp, const double* num) { static_cast<Solver<double>*>(sp)->num = Num(num); }
 
@@ -1113,6 +1133,8 @@ int32_t orc_cs_gradient(void* sp, int32_t param, int32_t wall_tag, int32_t ff_ta
       for (int d = 0; d < 3; ++d) b.U[d] *= (m + cplx(0.0, hstep)) / m;
     }
   }
+  c.LfG = s->LfG;
+  c.LfR = s->LfR;
   for (size_t x = 0; x < c.G.size(); ++x) {
     c.G[x] = s->G[x];
     c.R[x] = s->R[x];
@@ -1170,6 +1192,8 @@ void orc_steady_residual_jvp(void* sp, int32_t wall_tag, int32_t ff_tag, const d
       for (int d = 0; d < 3; ++d) b.U[d] *= (m + ih * up[2]) / m;
     }
   }
+  c.LfG = s->LfG;
+  c.LfR = s->LfR;
   for (size_t x = 0; x < c.G.size(); ++x) {
     c.G[x] = s->G[x] + ih * uG[x];
     c.R[x] = s->R[x] + ih * uR[x];

@@ -28,7 +28,7 @@ EXPORTS = [
     "cis_state_init_equilibrium", "cis_state_set", "cis_state_get", "cis_iterate", "cis_residual", "cis_moments",
     "cis_wall_heat_flux", "cis_debug_stage", "cis_profile_enable", "cis_profile_read", "cis_state_set_bc",
     "cis_steady_residual", "cis_residual_vjp", "cis_adjoint_required_bytes", "cis_adjoint_solve", "cis_wall_loads",
-    "cis_wall_coefficients_of_loads", "cis_wall_coefficients", "cis_iterate_noalloc",
+    "cis_wall_coefficients_of_loads", "cis_wall_coefficients", "cis_iterate_noalloc", "cis_limiter_freeze",
 ]
 STAGE_NAMES = ["recon", "face", "macro", "residual", "micro", "update"]
 
@@ -145,6 +145,8 @@ def load(allow_build: bool = True):
     lib.cis_state_get.argtypes = [P, P, P, d, d]
     lib.cis_iterate.restype = st
     lib.cis_iterate.argtypes = [P, C.c_int32, d]
+    lib.cis_limiter_freeze.restype = st
+    lib.cis_limiter_freeze.argtypes = [P, P]
     lib.cis_iterate_noalloc.restype = st
     lib.cis_iterate_noalloc.argtypes = [P, C.c_int32, d]
     lib.cis_residual.restype = st
@@ -311,6 +313,21 @@ class Solver:
         self.num.update(changes)
         self._num_s = numerics_struct(self.num)
         _check(self.lib.cis_state_set_numerics(self.h, C.byref(self._num_s)))
+
+    def freeze_limiter(self):
+        """Store the limiter values of the current state (cis_limiter_freeze) and switch to limiter 3, which
+        reconstructs with them.  Returns the [2, nc, nv] tensor of values (G then R)."""
+        t = self.torch
+        self.L_frozen = t.empty(2, self.nc, self.nv, dtype=self.dtype, device=self.device)
+        _check(self.lib.cis_limiter_freeze(self.h, C.c_void_p(self.L_frozen.data_ptr())))
+        self.set_numerics(limiter=3)
+        return self.L_frozen
+
+    def unfreeze_limiter(self, limiter: int = 1):
+        """Back to a computed limiter (1 by default) and detach the frozen values."""
+        self.set_numerics(limiter=limiter)
+        _check(self.lib.cis_limiter_freeze(self.h, None))
+        self.L_frozen = None
 
     def init_equilibrium(self, W0):
         W0 = np.ascontiguousarray(W0, dtype=np.float64)

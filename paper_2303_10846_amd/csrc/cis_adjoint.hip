@@ -463,7 +463,8 @@ template <bool HasV> __global__ __launch_bounds__(kBlock) void k_face_vjp(Dev d,
 
 __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ src, const double* __restrict__ fadj,
                                      double* gout, int64_t i, int64_t k, const int32_t* nb, const int32_t* fc,
-                                     const double* geo, double kh3, const Vel& v, const double* un) {
+                                     const double* geo, double kh3, const Vel& v, const double* un,
+                                     const double* Lfrozen) {
   const int64_t nv = d.nv;
   // adjoint of phi_bar gathered from the faces of which this cell is the upwind side
   double pself = 0.0, gbx = 0.0, gby = 0.0, gbz = 0.0;
@@ -508,7 +509,9 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
   double L = 1.0, d1m = 0.0, d2m = 0.0, eps2 = 0.0;
   int amin = -1, isel = -1;
   double psel = 0.0;
-  if (d.limiter) {
+  if (d.limiter == 3) {
+    L = Lfrozen[i * nv + k];  // frozen values: constants of the linearisation
+  } else if (d.limiter) {
     const bool use_max = fabs(pmax) > fabs(pmin);
     psel = use_max ? pmax : pmin;
     isel = use_max ? imax : imin;
@@ -541,8 +544,8 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
     }
   };
   double grx = L * gbx, gry = L * gby, grz = L * gbz;
-  // the limiter's own derivative; limiter = 2 holds L fixed (frozen-limiter linearisation)
-  if (amin >= 0 && d.limiter != 2) {
+  // the limiter's own derivative; limiter = 2 holds L fixed (frozen-limiter linearisation), limiter = 3 stores it
+  if (amin >= 0 && d.limiter == 1) {
     const double Lb = gbx * gx + gby * gy + gbz * gz;
     const double d1 = d1m, d2 = d2m;
     const double N = (d1 * d1 + eps2) * d2 + 2.0 * d2 * d2 * d1;
@@ -594,8 +597,10 @@ __global__ __launch_bounds__(kBlock) void k_recon_vjp(Dev d, Bufs b, AdjArgs a) 
     const double* s = geo + CG_FACE + CG_SLOT * q;
     un[q] = udotn(v, s[2], s[3], s[4], d.snap);
   }
-  recon_vjp_one(d, (const double*)b.G, (const double*)b.faceG, a.gG, i, k, nb, fc, geo, kh3, v, un);
-  recon_vjp_one(d, (const double*)b.R, (const double*)b.faceR, a.gR, i, k, nb, fc, geo, kh3, v, un);
+  const double* LG = (const double*)d.lim_frozen;
+  const double* LR = LG ? LG + d.nc * nv : nullptr;
+  recon_vjp_one(d, (const double*)b.G, (const double*)b.faceG, a.gG, i, k, nb, fc, geo, kh3, v, un, LG);
+  recon_vjp_one(d, (const double*)b.R, (const double*)b.faceR, a.gR, i, k, nb, fc, geo, kh3, v, un, LR);
 }
 
 void launch_vjp(const Dev& d, const Bufs& b, const AdjArgs& a, hipStream_t st) {

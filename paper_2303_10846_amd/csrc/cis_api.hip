@@ -150,7 +150,7 @@ cis_status check_numerics(const cis_numerics* n) {
   if (!n) return fail(CIS_E_INVALID_ARG, "numerics is NULL");
   if (!(n->cfl > 0.0) || !(n->inv_dt >= 0.0) || !(n->cfl_imp >= 0.0) || !(n->lim_K >= 0.0) || !(n->snap >= 0.0) ||
       n->n_macro < 0 || n->n_micro < 0 || n->n_macro > 100000 || n->n_micro > 100000 || n->limiter < 0 ||
-      n->limiter > 2)
+      n->limiter > 3)
     return fail(CIS_E_INVALID_ARG, "numerics out of range");
   return CIS_OK;
 }
@@ -585,6 +585,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   if (precision != CIS_FP64 && precision != CIS_MIXED) return fail(CIS_E_INVALID_ARG, "unknown precision");
   cis_status st = check_numerics(num);
   if (st != CIS_OK) return st;
+  if (num->limiter == 3) return fail(CIS_E_INVALID_ARG, "limiter 3 needs frozen values: cis_limiter_freeze first");
   if (!buf->G || !buf->R || !buf->dG || !buf->dR || !buf->resG || !buf->resR || !buf->faceG || !buf->faceR || !buf->W ||
       !buf->q || !buf->upwind)
     return fail(CIS_E_INVALID_ARG, "a device buffer is NULL");
@@ -775,6 +776,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   d.gas = GasC{gas->R,      gas->gamma,  gas->Z,         gas->delta, gas->omega0,
                gas->omega1, gas->mu_ref, gas->omega_vhs, gas->T_ref, gas->C_s};
   d.umax = dv->umax;
+  d.lim_frozen = nullptr;
   fill_dev_numerics(s);
   s->buf = Bufs{buf->G, buf->R, buf->dG, buf->dR, buf->resG, buf->resR, buf->faceG, buf->faceR, buf->W, buf->q};
   launch_upwind_codes(d, s->stream);
@@ -791,6 +793,8 @@ cis_status cis_state_set_numerics(cis_state* s, const cis_numerics* num) {
   cis_status st = check_numerics(num);
   if (st != CIS_OK) return st;
   if (num->cfl != s->num.cfl) return fail(CIS_E_UNSUPPORTED, "cfl (face step s_ij) is fixed at state creation");
+  if (num->limiter == 3 && !s->dev.lim_frozen)
+    return fail(CIS_E_INVALID_ARG, "limiter 3 needs frozen values: cis_limiter_freeze first");
   const bool recode = num->snap != s->num.snap;
   s->num = *num;
   fill_dev_numerics(s);
@@ -806,6 +810,24 @@ void cis_state_destroy(cis_state* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
   delete s;
+}
+
+cis_status cis_limiter_freeze(cis_state* s, void* L) {
+  if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
+  if (!L) {
+    if (s->num.limiter == 3) return fail(CIS_E_INVALID_ARG, "limiter 3 is in use: set another limiter first");
+    s->dev.lim_frozen = nullptr;
+    return CIS_OK;
+  }
+  cis_status st = dispatch(s, [&](auto* tp) {
+    using T = std::remove_pointer_t<decltype(tp)>;
+    launch_recon<T>(s->dev, s->buf, s->stream, L);
+    return device_check("limiter freeze");
+  });
+  if (st != CIS_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->dev.lim_frozen = L;
+  return CIS_OK;
 }
 
 cis_status cis_state_init_equilibrium(cis_state* s, const double* W0, int32_t per_cell) {

@@ -57,7 +57,8 @@ struct Dev {
   const double* bc;          // [nbc][BCW]
   GasC gas;
   double snap, lim_K, inv_dt, cfl_imp, umax;
-  int limiter;
+  int limiter;               // 0 off, 1 Venkatakrishnan, 2 the same (held fixed by the VJP), 3 frozen values
+  const void* lim_frozen;    // limiter 3: [2][nc][nv] stored limiter values of G then R (state precision)
 };
 
 // Step 7's residual is reduced in two stages over a fixed partition of the cells: kResidualParts partial sums of
@@ -91,7 +92,8 @@ struct Bufs {
 // Launchers (all enqueue on `st`); T = double or float selects the precision mode.
 template <class T> void launch_init_eq(const Dev& d, const Bufs& b, const double* W0, int per_cell, double* eqtmp,
                                        hipStream_t st);
-template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st);
+// cap != nullptr: also store the limiter values (limiter 1's, whatever d.limiter is) into cap, [2][nc][nv]
+template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st, void* cap = nullptr);
 template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st);
 void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors,
                   int n_macro, hipStream_t st);

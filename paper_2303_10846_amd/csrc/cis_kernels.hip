@@ -137,11 +137,12 @@ __device__ inline double lim_div(double a, double b) { return a / b; }
 __device__ inline float lim_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // One distribution at one velocity: limited least-squares gradient of the cell and the upwind face values
-// (written at dst + frow[a] + k).
+// (written at dst + frow[a] + k).  limiter 3 takes L from the frozen row Lin; Lcap (if set) receives L.
 template <class T>
 __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const T* wx, const T* wy, const T* wz,
                                    const T* fx, const T* fy, const T* fz, const T* sf, T kh3, int limiter,
-                                   const bool* up, T ux, T uy, T uz, T* dst, const int64_t* frow, int k) {
+                                   const bool* up, T ux, T uy, T uz, T* dst, const int64_t* frow, int k,
+                                   const T* Lin, T* Lcap) {
   T gx = 0, gy = 0, gz = 0, pmax = phi, pmin = phi;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -154,7 +155,9 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
     pmin = pn[a] < pmin ? pn[a] : pmin;
   }
   T L = 1;
-  if (limiter) {
+  if (limiter == 3) {
+    L = Lin[k];
+  } else if (limiter) {
     const T scale = fabs(pmax) > fabs(pmin) ? fabs(pmax) : fabs(pmin);
     const T eps2 = kh3 * scale * scale;
     // Venkatakrishnan's function with the common factor d2 divided out of both parts:
@@ -170,6 +173,7 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
       }
     }
   }
+  if (Lcap) Lcap[k] = L;
   gx *= L;
   gy *= L;
   gz *= L;
@@ -182,7 +186,7 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
 
 // Every load of a thread's velocities is issued before its first store (the stores could alias later loads
 // as far as the compiler knows); per-cell geometry is converted once into registers.
-template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b) {
+template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b, T* cap) {
   constexpr int U = kVptOne;
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
@@ -227,8 +231,13 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   double kh3d = d.lim_K * geo[2];
   kh3d = kh3d * kh3d * kh3d;
   const T kh3 = (T)kh3d;
-  const int limiter = d.limiter;
+  const int limiter = cap ? 1 : d.limiter;
   const int64_t self = i * nv;
+  const int64_t P = d.nc * nv;
+  const T* LinG = limiter == 3 ? (const T*)d.lim_frozen + self : nullptr;
+  const T* LinR = limiter == 3 ? LinG + P : nullptr;
+  T* capG = cap ? cap + self : nullptr;
+  T* capR = cap ? cap + P + self : nullptr;
   const int nvi = (int)nv;
   const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
   T pG[U], pR[U], nG[U][4], nR[U][4], tx[U], ty[U], tz[U];
@@ -271,13 +280,15 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   for (int u = 0; u < U; ++u) {
     const int k = k0 + u * kBlock;
     if (k >= nvi) continue;
-    recon_write<T>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FG, frow, k);
-    recon_write<T>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FR, frow, k);
+    recon_write<T>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FG, frow, k,
+                   LinG, capG);
+    recon_write<T>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FR, frow, k,
+                   LinR, capR);
   }
 }
 
-template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_recon<T>, cell_chunk_grid_u<kVptOne>(d.nc, d.nv), dim3(kBlock), 0, st, d, b);
+template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st, void* cap) {
+  hipLaunchKernelGGL(k_recon<T>, cell_chunk_grid_u<kVptOne>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, (T*)cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -1371,8 +1382,8 @@ int max_velocities() { return 16384; }
 // explicit instantiations
 template void launch_init_eq<double>(const Dev&, const Bufs&, const double*, int, double*, hipStream_t);
 template void launch_init_eq<float>(const Dev&, const Bufs&, const double*, int, double*, hipStream_t);
-template void launch_recon<double>(const Dev&, const Bufs&, hipStream_t);
-template void launch_recon<float>(const Dev&, const Bufs&, hipStream_t);
+template void launch_recon<double>(const Dev&, const Bufs&, hipStream_t, void*);
+template void launch_recon<float>(const Dev&, const Bufs&, hipStream_t, void*);
 template void launch_face<double>(const Dev&, const Bufs&, const Work&, hipStream_t);
 template void launch_face<float>(const Dev&, const Bufs&, const Work&, hipStream_t);
 template void launch_residual<double>(const Dev&, const Bufs&, const Work&, void*, void*, int, hipStream_t);

@@ -46,6 +46,7 @@ CASES = {
     "small_sphere": (lambda: configs.small_sphere_case(), 1, 2),
     "open_box_sutherland": (lambda: _sutherland(_open_box(1), 0.8), 1, 2),   # Eq. 14 viscosity, limiter on
     "open_box_frozen": (lambda: _open_box(2), 1, 2),                          # limiter held fixed in the VJP
+    "open_box_stored": (lambda: dict(_open_box(1), freeze=True), 1, 2),       # stored values (limiter 3)
 }
 
 
@@ -55,12 +56,17 @@ def _sutherland(case, C_s):
 
 
 def _pair(case, warm):
+    """Oracle and GPU state after `warm` oracle iterations; case["freeze"]: then both freeze their limiter
+    values at that state (limiter 3)."""
     o = oracle.Oracle(case)
     o.init_equilibrium(case["W0"])
     o.iterate(warm)
     G, R, W, q = o.get_state()
     s = solver(case)
     s.set_state(G, R, W, q)
+    if case.get("freeze"):
+        o.freeze_limiter()
+        s.freeze_limiter()
     return o, s, (G, R, W, q)
 
 

@@ -126,6 +126,34 @@ def test_one_iteration_stage_by_stage_fp64(name):
     assert np.max(np.abs(hs - ho)) <= 1e-11 * np.max(np.abs(ho)) + 1e-20
 
 
+def test_frozen_limiter_values_fp64():
+    """Limiter freezing (limiter 3): the values stored by cis_limiter_freeze equal the limiter of the state they
+    were taken at, so the explicit operator there is that of limiter 1; on a later state they stay fixed, and the
+    GPU iteration with them matches the oracle's frozen iteration."""
+    say("case open box frozen limiter")
+    c = configs.open_box_case(n=3, nv_side=6)
+    o, s = _pair(c, warm=4)
+    FG1, FR1, Fm1 = s.residual()
+    o.freeze_limiter()
+    L = s.freeze_limiter().cpu().numpy()
+    assert 0.0 <= L.min() < 0.9 and L.max() <= 1.0
+    FG3, FR3, Fm3 = s.residual()
+    assert np.array_equal(FG1.cpu().numpy(), FG3.cpu().numpy()) and np.array_equal(Fm1, Fm3)
+    o.iterate(5)
+    s.iterate(5)
+    Go, Ro, Wo, qo = o.get_state()
+    Gs, Rs, Ws, qs = s.get_state()
+    assert nrel(Gs, Go) < TOL and nrel(Rs, Ro) < TOL and colrel(Ws, Wo) < TOL and colrel(qs, qo) < TOL
+    o.explicit()
+    FG, _, Fm = s.residual()
+    assert nrel(FG.cpu().numpy(), o.stage("FG")) < TOL and colrel(Fm, o.stage("Fmac")) < TOL
+    # the stored values did not move, and detaching them is refused while limiter 3 is in use
+    assert np.array_equal(s.L_frozen.cpu().numpy(), L)
+    assert s.lib.cis_limiter_freeze(s.h, None) == -1
+    s.unfreeze_limiter()
+    assert s.num["limiter"] == 1
+
+
 def test_lu_sgs_settings_one_pair_each_fp64():
     """LU-SGS for both implicit systems: one forward + backward pair from zero (n_macro = n_micro = 1), which for
     Eq. 33 is the LU-SGS step (D + L) D^-1 (D + U) dphi = Res; stage-by-stage against the oracle."""
@@ -333,6 +361,43 @@ def test_mixed_micro_sweep_vector_widths(dims):
     eW = colrel(Wm, o.get_state()[2])
     say(f"mixed vs FP64 oracle: dG {eG:.2e} dR {eR:.2e} W {eW:.2e}")
     assert eG < 1e-4 and eR < 1e-4 and eW < 1e-4
+
+
+def test_mixed_vector_kernels_on_the_small_sphere_stage_by_stage():
+    """The mixed path's vector kernels (four velocities per thread: the small sphere's DVS has 1 288 points) against
+    the FP64 oracle, stage by stage, on a state ten iterations from rest, where the flow is far from steady and Res
+    is not dominated by cancellation.  Both sides start from the same FP32-rounded distributions, so every
+    difference is FP32 arithmetic in the kernels.  Bars (normwise, against the largest oracle value of each array):
+    the micro flux F and Res are sums of a few FP32 products whose terms are at most ~10x the result, so ~10 units
+    of FP32 rounding (6e-8) times that: 2e-5; the increments and the updated moments inherit Res's error (the
+    diagonal is FP64): 2e-5 and 2e-6."""
+    say("case small_sphere mixed stage by stage")
+    c = configs.small_sphere_case()
+    assert len(c["u"]) % 4 == 0
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(10)
+    G, R, W, q = o.get_state()
+    G32, R32 = G.astype(np.float32), R.astype(np.float32)
+    o.set_state(G32.astype(np.float64), R32.astype(np.float64), W, q)
+    s = solver(c, precision="mixed")
+    s.set_state(G32, R32, W, q)
+    # explicit operator: micro flux (Eq. 31) and macro flux (Eq. 37)
+    FG, FR, Fm = s.residual()
+    o.explicit()
+    eF = max(nrel(FG.cpu().numpy(), o.stage("FG")), nrel(FR.cpu().numpy(), o.stage("FR")))
+    eFm = colrel(Fm, o.stage("Fmac"))
+    # one iteration: Res (Eq. 33 right-hand side), the increments, the update
+    s.set_state(G32, R32, W, q)
+    s.iterate(1)
+    o.iterate(1)
+    eRes = max(nrel(s.resG.cpu().numpy(), o.stage("ResG")), nrel(s.resR.cpu().numpy(), o.stage("ResR")))
+    ed = max(nrel(s.dG.cpu().numpy(), o.stage("dG")), nrel(s.dR.cpu().numpy(), o.stage("dR")))
+    Wm, qm = s.moments()
+    _, _, Wo, qo = o.get_state()
+    eW = colrel(Wm, Wo)
+    say(f"mixed vector kernels vs FP64 oracle: F {eF:.2e} Fmac {eFm:.2e} Res {eRes:.2e} dphi {ed:.2e} W {eW:.2e}")
+    assert eF < 2e-5 and eFm < 2e-5 and eRes < 2e-5 and ed < 2e-5 and eW < 2e-6
 
 
 def test_wall_loads_match_oracle_face_fluxes():

@@ -384,3 +384,65 @@ def test_matrix_free_macro_increment_solves_the_nonlinear_eq43():
     # and it differs from the linear (exact Jacobian) solve by the second-order flux terms only
     x = np.linalg.solve(M, b).reshape(-1, 6)
     assert 1e-12 < rel(dW, x) < 1e-2
+
+
+# ---------------------------------------------------------------------------
+# Limiter freezing (limiter = 3): stored Venkatakrishnan values in place of the limiter
+# ---------------------------------------------------------------------------
+
+def test_frozen_limiter_reuses_the_values_of_the_state_it_was_frozen_at():
+    """At the state it was frozen at, limiter 3 reconstructs exactly as limiter 1; at another state it scales the
+    unlimited least-squares gradient by the stored values, not by the limiter of the new state."""
+    c = configs.cavity_case(n=3, nv_side=4)
+    o1 = oracle.Oracle(c, num=dict(c["num"], limiter=1))
+    o3 = oracle.Oracle(c, num=dict(c["num"], limiter=1))
+    o0 = oracle.Oracle(c, num=dict(c["num"], limiter=0))
+    G, R, W, q = _random_state(o1, c, seed=21)
+    for o in (o1, o3):
+        o.set_state(G, R, W, q)
+    o3.freeze_limiter()
+    o1.explicit()
+    o3.explicit()
+    for st in ("gradG", "gradR", "FG", "FR", "Fmac"):
+        assert np.array_equal(o1.stage(st), o3.stage(st)), st
+    # the stored values, recovered from the limited and unlimited gradients at the freezing state
+    o0.set_state(G, R, W, q)
+    o0.explicit()
+    gu, gl = o0.stage("gradG"), o1.stage("gradG")
+    nz = np.abs(gu) > 1e-10 * np.abs(gu).max()
+    Lg = np.where(nz[..., 0], gl[..., 0] / np.where(nz[..., 0], gu[..., 0], 1.0), 1.0)
+    assert Lg.min() < 0.9
+    # another state: limiter 3 keeps the stored values
+    rng = np.random.default_rng(22)
+    G2 = G * (1.0 + 0.1 * rng.uniform(-1, 1, G.shape))
+    for o in (o0, o1, o3):
+        o.set_state(G2, R, W, q)
+        o.explicit()
+    gu2, gl2, g3 = o0.stage("gradG"), o1.stage("gradG"), o3.stage("gradG")
+    assert rel(g3[nz[..., 0]], (Lg[..., None] * gu2)[nz[..., 0]]) < 1e-12
+    assert rel(g3, gl2) > 1e-3   # the recomputed limiter would differ
+
+
+def test_frozen_limiter_scheme_is_smooth_complex_step_matches_central_differences():
+    """With the limiter values frozen the steady residual is a smooth function of the state: its complex-step
+    derivative along a random direction matches central differences to the truncation error."""
+    c = configs.open_box_case(n=2, nv_side=5)
+    o = oracle.Oracle(c, num=dict(c["num"], limiter=1))
+    o.init_equilibrium(c["W0"])
+    o.iterate(6)
+    o.freeze_limiter()
+    G, R, W, q = o.get_state()
+    rng = np.random.default_rng(23)
+    u = [rng.standard_normal(x.shape) * np.abs(x).max() for x in (G, R, W, q)]
+    up = np.zeros(3)
+    jG, jR, jW, jq, jJ = o.steady_residual_jvp(*u, up)
+    h = 1e-6
+    outs = []
+    for sg in (1.0, -1.0):
+        o.set_state(*[x + sg * h * du for x, du in zip((G, R, W, q), u)])
+        outs.append(o.steady_residual(1))
+    o.set_state(G, R, W, q)
+    for m, jx in enumerate((jG, jR, jW, jq)):
+        fd = (outs[0][m] - outs[1][m]) / (2 * h)
+        assert rel(jx, fd) < 1e-6, m
+    assert abs(jJ - (outs[0][4] - outs[1][4]) / (2 * h)) <= 1e-6 * abs(jJ)
