@@ -368,9 +368,11 @@ def test_mixed_vector_kernels_on_the_small_sphere_stage_by_stage():
     the FP64 oracle, stage by stage, on a state ten iterations from rest, where the flow is far from steady and Res
     is not dominated by cancellation.  Both sides start from the same FP32-rounded distributions, so every
     difference is FP32 arithmetic in the kernels.  Bars (normwise, against the largest oracle value of each array):
-    the micro flux F and Res are sums of a few FP32 products whose terms are at most ~10x the result, so ~10 units
-    of FP32 rounding (6e-8) times that: 2e-5; the increments and the updated moments inherit Res's error (the
-    diagonal is FP64): 2e-5 and 2e-6."""
+    the micro flux F and Res are sums of a few FP32 products whose terms are up to ~10x the result, so some tens
+    of units of FP32 rounding (6e-8) of the largest term: measured F 6.6e-7, Fmac 7.1e-7, Res 1.4e-6; bar 4e-6
+    (F) and 6e-6 (Res).  The increments inherit Res's error through an FP64 diagonal (measured 1.0e-6, bar 6e-6)
+    and the updated moments are FP64 sums of them (measured 1.7e-7, bar 1e-6).  A wrong upwind bit, neighbour
+    or equilibrium coefficient gives errors of order one."""
     say("case small_sphere mixed stage by stage")
     c = configs.small_sphere_case()
     assert len(c["u"]) % 4 == 0
@@ -397,7 +399,7 @@ def test_mixed_vector_kernels_on_the_small_sphere_stage_by_stage():
     _, _, Wo, qo = o.get_state()
     eW = colrel(Wm, Wo)
     say(f"mixed vector kernels vs FP64 oracle: F {eF:.2e} Fmac {eFm:.2e} Res {eRes:.2e} dphi {ed:.2e} W {eW:.2e}")
-    assert eF < 2e-5 and eFm < 2e-5 and eRes < 2e-5 and ed < 2e-5 and eW < 2e-6
+    assert eF < 4e-6 and eFm < 4e-6 and eRes < 6e-6 and ed < 6e-6 and eW < 1e-6
 
 
 def test_wall_loads_match_oracle_face_fluxes():
