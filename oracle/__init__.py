@@ -48,7 +48,7 @@ def _load():
     i64 = C.POINTER(C.c_int64)
     i32 = C.POINTER(C.c_int32)
     lib.orc_geom_create.restype = P
-    lib.orc_geom_create.argtypes = [d, C.c_int64, i32, C.c_int64, i32, i32, C.c_int64, d, d, C.c_int64,
+    lib.orc_geom_create.argtypes = [d, C.c_int64, i32, i32, C.c_int64, i32, i32, C.c_int64, d, d, C.c_int64,
                                     C.c_double, i32]
     lib.orc_geom_destroy.argtypes = [P]
     lib.orc_threads.restype = C.c_int32
@@ -160,6 +160,23 @@ def euler_flux(W, n, gas: dict, dW=None):
 # Whole-mesh solver
 # ---------------------------------------------------------------------------
 
+def general_cells(mesh: dict):
+    """(cells [nc][8], kinds [nc], bface [nb][4]) of a mesh dict: a tetrahedral mesh ("tets", "btri") or a mixed
+    one ("cells" [nc][8] padded with -1, "kinds" = node count per cell, "bface" [nb][4] padded with -1)."""
+    if "cells" in mesh:
+        cells = np.ascontiguousarray(mesh["cells"], dtype=np.int32)
+        kinds = np.ascontiguousarray(mesh["kinds"], dtype=np.int32)
+        bface = np.ascontiguousarray(mesh["bface"], dtype=np.int32)
+        return cells, kinds, bface
+    tets = np.asarray(mesh["tets"], dtype=np.int32)
+    cells = np.full((len(tets), 8), -1, dtype=np.int32)
+    cells[:, :4] = tets
+    btri = np.asarray(mesh["btri"], dtype=np.int32)
+    bface = np.full((len(btri), 4), -1, dtype=np.int32)
+    bface[:, :3] = btri
+    return cells, np.full(len(tets), 4, dtype=np.int32), bface
+
+
 class Oracle:
     """Oracle solver on one case (a dict from ``paper_2303_10846_amd.cases``)."""
 
@@ -168,8 +185,7 @@ class Oracle:
         self.lib = lib
         m = case["mesh"]
         self.xyz = _f64(m["xyz"])
-        self.tets = np.ascontiguousarray(m["tets"], dtype=np.int32)
-        self.btri = np.ascontiguousarray(m["btri"], dtype=np.int32)
+        self.cells, self.kinds, self.bface = general_cells(m)
         self.btag = np.ascontiguousarray(m["btag"], dtype=np.int32)
         self.u = _f64(case["u"])
         self.w = _f64(case["w"])
@@ -178,15 +194,15 @@ class Oracle:
         self.bcs = list(case["bcs"] if bcs is None else bcs)
         st = C.c_int32(0)
         ip = C.POINTER(C.c_int32)
-        self.geo = lib.orc_geom_create(_dp(self.xyz), len(self.xyz), self.tets.ctypes.data_as(ip), len(self.tets),
-                                       self.btri.ctypes.data_as(ip), self.btag.ctypes.data_as(ip), len(self.btri),
-                                       _dp(self.u), _dp(self.w), len(self.u), float(self.num["cfl"]),
-                                       C.byref(st))
+        self.geo = lib.orc_geom_create(_dp(self.xyz), len(self.xyz), self.cells.ctypes.data_as(ip),
+                                       self.kinds.ctypes.data_as(ip), len(self.cells), self.bface.ctypes.data_as(ip),
+                                       self.btag.ctypes.data_as(ip), len(self.bface), _dp(self.u), _dp(self.w),
+                                       len(self.u), float(self.num["cfl"]), C.byref(st))
         if not self.geo:
             raise ValueError(f"oracle: mesh/DVS rejected (status {st.value})")
-        cnt = np.zeros(4, dtype=np.int64)
+        cnt = np.zeros(5, dtype=np.int64)
         lib.orc_geom_counts(self.geo, cnt.ctypes.data_as(C.POINTER(C.c_int64)))
-        self.nc, self.nf, self.n_interior, self.nv = (int(x) for x in cnt)
+        self.nc, self.nf, self.n_interior, self.nv, self.mf = (int(x) for x in cnt)
         self._gas = gas_array(self.gas)
         self._num = num_array(self.num)
         self._bc = bc_array(self.bcs)
@@ -206,7 +222,7 @@ class Oracle:
     def geometry(self) -> dict:
         nc, nf = self.nc, self.nf
         out = dict(V=np.empty(nc), xc=np.empty((nc, 3)), h=np.empty(nc), dt=np.empty(nc),
-                   cf=np.empty((nc, 4), dtype=np.int64), fo=np.empty(nf, dtype=np.int64),
+                   cf=np.empty((nc, self.mf), dtype=np.int64), fo=np.empty(nf, dtype=np.int64),
                    fn=np.empty(nf, dtype=np.int64), ftag=np.empty(nf, dtype=np.int32), A=np.empty(nf),
                    n=np.empty((nf, 3)), xf=np.empty((nf, 3)), s=np.empty(nf))
         i64 = C.POINTER(C.c_int64)

@@ -79,7 +79,9 @@ template <class S> struct Bc {
 struct Geom {
   int64_t nc = 0, nf = 0, nv = 0;
   std::vector<double> V, xc, h, dt;  // cells
-  std::vector<int64_t> cf;           // [nc][4] faces of each cell
+  int mf = 4;                        // face slots per cell (4 when every cell is a tetrahedron, else 6)
+  std::vector<int> nfc;              // faces of each cell
+  std::vector<int64_t> cf;           // [nc][mf] faces of each cell (-1 past nfc)
   std::vector<int64_t> fo, fn;       // owner, neighbour (-1 on the boundary)
   std::vector<int> ftag;             // boundary tag (0 interior)
   std::vector<double> A, n, xf, s, dl;
@@ -112,41 +114,176 @@ inline bool inv3(const double* M, double* I) {
   return true;
 }
 
-int build_geom(Geom& g, const double* xyz, int64_t nn, const int32_t* tet, int64_t nc, const int32_t* btri,
-               const int32_t* btag, int64_t nb, const double* u, const double* w, int64_t nv, double cfl) {
+// Local faces of the cell kinds (by node count): tetrahedron (the face opposite local vertex a), pyramid
+// (base quad 0-3, apex 4), prism (triangles 0-2 and 3-5) and hexahedron (quads 0-3 and 4-7); quads in cyclic
+// order.
+struct LocalFaces {
+  int n;
+  int size[6];
+  int node[6][4];
+};
+const LocalFaces* local_faces(int kind) {
+  static const LocalFaces tet = {4, {3, 3, 3, 3}, {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}}};
+  static const LocalFaces pyr = {5, {4, 3, 3, 3, 3}, {{0, 1, 2, 3}, {0, 1, 4}, {1, 2, 4}, {2, 3, 4}, {3, 0, 4}}};
+  static const LocalFaces pri = {5, {3, 3, 4, 4, 4}, {{0, 1, 2}, {3, 4, 5}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}}};
+  static const LocalFaces hex = {6, {4, 4, 4, 4, 4, 4},
+                                 {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}}};
+  switch (kind) {
+    case 4: return &tet;
+    case 5: return &pyr;
+    case 6: return &pri;
+    case 8: return &hex;
+    default: return nullptr;
+  }
+}
+
+using FaceKey = std::array<int32_t, 4>;  // sorted node ids, -1 in the last place for a triangle
+FaceKey face_key(const int32_t* nodes, int n) {
+  FaceKey k = {nodes[0], nodes[1], nodes[2], n == 4 ? nodes[3] : -1};
+  std::sort(k.begin(), k.begin() + n);
+  return k;
+}
+
+// Vector area and centroid of a face with nodes p[0..n-1] in cyclic order (n = 3 or 4).  A quad need not be
+// planar: its vector area is half the cross product of its diagonals (the vector area of the closed polygon,
+// so every closed cell has sum_f A n = 0 exactly), and its centroid the average of the centroids of the four
+// triangles it makes with its node average, weighted by their areas along the face normal.
+void face_geometry(const double* const* p, int n, double* S, double* xf) {
+  if (n == 3) {
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+      e1[k] = p[1][k] - p[0][k];
+      e2[k] = p[2][k] - p[0][k];
+    }
+    cross3(e1, e2, S);
+    for (int k = 0; k < 3; ++k) {
+      S[k] *= 0.5;
+      xf[k] = (p[0][k] + p[1][k] + p[2][k]) / 3.0;
+    }
+    return;
+  }
+  double d1[3], d2[3], m[3];
+  for (int k = 0; k < 3; ++k) {
+    d1[k] = p[2][k] - p[0][k];
+    d2[k] = p[3][k] - p[1][k];
+    m[k] = 0.25 * (p[0][k] + p[1][k] + p[2][k] + p[3][k]);
+  }
+  cross3(d1, d2, S);
+  for (int k = 0; k < 3; ++k) S[k] *= 0.5;
+  const double len = std::sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+  double wsum = 0.0, acc[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < 4; ++q) {
+    const double* a = p[q];
+    const double* b = p[(q + 1) % 4];
+    double e1[3], e2[3], t[3];
+    for (int k = 0; k < 3; ++k) {
+      e1[k] = b[k] - a[k];
+      e2[k] = m[k] - a[k];
+    }
+    cross3(e1, e2, t);
+    const double wq = 0.5 * (t[0] * S[0] + t[1] * S[1] + t[2] * S[2]) / len;
+    wsum += wq;
+    for (int k = 0; k < 3; ++k) acc[k] += wq * (a[k] + b[k] + m[k]) / 3.0;
+  }
+  for (int k = 0; k < 3; ++k) xf[k] = acc[k] / wsum;
+}
+
+// Geometry of the physical mesh.  cells [nc][8] node ids (unused places ignored), kinds [nc] = node count
+// (4 tetrahedron, 5 pyramid, 6 prism, 8 hexahedron); bface [nb][4] boundary faces (-1 in the last place for a
+// triangle) with tags btag.
+int build_geom(Geom& g, const double* xyz, int64_t nn, const int32_t* cells, const int32_t* kinds, int64_t nc,
+               const int32_t* bface, const int32_t* btag, int64_t nb, const double* u, const double* w, int64_t nv,
+               double cfl) {
   g.nc = nc;
   g.nv = nv;
   g.V.assign(nc, 0.0);
   g.xc.assign(3 * nc, 0.0);
+  g.mf = 4;
   for (int64_t i = 0; i < nc; ++i) {
-    const double* p[4];
-    for (int a = 0; a < 4; ++a) {
-      if (tet[4 * i + a] < 0 || tet[4 * i + a] >= nn) return -2;
-      p[a] = xyz + 3 * tet[4 * i + a];
-    }
-    double d1[3], d2[3], d3[3], c[3];
-    for (int k = 0; k < 3; ++k) {
-      d1[k] = p[1][k] - p[0][k];
-      d2[k] = p[2][k] - p[0][k];
-      d3[k] = p[3][k] - p[0][k];
-    }
-    cross3(d2, d3, c);
-    double vol = std::fabs(d1[0] * c[0] + d1[1] * c[1] + d1[2] * c[2]) / 6.0;
-    if (!(vol > 0.0)) return -2;
-    g.V[i] = vol;
-    for (int k = 0; k < 3; ++k) g.xc[3 * i + k] = 0.25 * (p[0][k] + p[1][k] + p[2][k] + p[3][k]);
+    const LocalFaces* lf = local_faces(kinds[i]);
+    if (!lf) return -2;
+    g.mf = std::max(g.mf, lf->n);
+    for (int a = 0; a < kinds[i]; ++a)
+      if (cells[8 * i + a] < 0 || cells[8 * i + a] >= nn) return -2;
   }
-  // faces: the face opposite local vertex a of tet i is the sorted triple of the other three
-  std::map<std::array<int32_t, 3>, std::pair<int64_t, int>> seen;
-  std::vector<std::array<int32_t, 3>> fkey;
-  g.cf.assign(4 * nc, -1);
+  g.nfc.assign(nc, 0);
   for (int64_t i = 0; i < nc; ++i) {
-    for (int a = 0; a < 4; ++a) {
-      std::array<int32_t, 3> key;
-      int m = 0;
-      for (int b = 0; b < 4; ++b)
-        if (b != a) key[m++] = tet[4 * i + b];
-      std::sort(key.begin(), key.end());
+    const int32_t* cn = cells + 8 * i;
+    const int kind = kinds[i];
+    const LocalFaces* lf = local_faces(kind);
+    g.nfc[i] = lf->n;
+    if (kind == 4) {
+      // tetrahedron: volume |det| / 6, centroid the mean of the vertices
+      const double* p[4];
+      for (int a = 0; a < 4; ++a) p[a] = xyz + 3 * cn[a];
+      double d1[3], d2[3], d3[3], c[3];
+      for (int k = 0; k < 3; ++k) {
+        d1[k] = p[1][k] - p[0][k];
+        d2[k] = p[2][k] - p[0][k];
+        d3[k] = p[3][k] - p[0][k];
+      }
+      cross3(d2, d3, c);
+      double vol = std::fabs(d1[0] * c[0] + d1[1] * c[1] + d1[2] * c[2]) / 6.0;
+      if (!(vol > 0.0)) return -2;
+      g.V[i] = vol;
+      for (int k = 0; k < 3; ++k) g.xc[3 * i + k] = 0.25 * (p[0][k] + p[1][k] + p[2][k] + p[3][k]);
+      continue;
+    }
+    // other kinds: tetrahedra from the node average p0 to the triangles of every face (a quad fanned about its
+    // node average); volume the sum of theirs, centroid their volume-weighted centroids
+    double p0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < kind; ++a)
+      for (int k = 0; k < 3; ++k) p0[k] += xyz[3 * cn[a] + k] / kind;
+    double vol = 0.0, acc[3] = {0.0, 0.0, 0.0};
+    for (int fa = 0; fa < lf->n; ++fa) {
+      const int n = lf->size[fa];
+      const double* p[4];
+      for (int q = 0; q < n; ++q) p[q] = xyz + 3 * cn[lf->node[fa][q]];
+      double m[3] = {0.0, 0.0, 0.0};
+      for (int q = 0; q < n; ++q)
+        for (int k = 0; k < 3; ++k) m[k] += p[q][k] / n;
+      const int ntri = n == 3 ? 1 : 4;
+      double vs[4], cs[4][3], vface = 0.0;
+      for (int t = 0; t < ntri; ++t) {
+        const double* a = n == 3 ? p[0] : p[t];
+        const double* b = n == 3 ? p[1] : p[(t + 1) % 4];
+        const double* c = n == 3 ? p[2] : m;
+        double e1[3], e2[3], e3[3], x[3];
+        for (int k = 0; k < 3; ++k) {
+          e1[k] = b[k] - a[k];
+          e2[k] = c[k] - a[k];
+          e3[k] = p0[k] - a[k];
+        }
+        cross3(e1, e2, x);
+        vs[t] = -(x[0] * e3[0] + x[1] * e3[1] + x[2] * e3[2]) / 6.0;
+        for (int k = 0; k < 3; ++k) cs[t][k] = 0.25 * (a[k] + b[k] + c[k] + p0[k]);
+        vface += vs[t];
+      }
+      const double sg = vface >= 0.0 ? 1.0 : -1.0;  // orientation of the local node order
+      for (int t = 0; t < ntri; ++t) {
+        if (!(sg * vs[t] > 0.0)) return -2;  // folded or degenerate cell
+        vol += sg * vs[t];
+        for (int k = 0; k < 3; ++k) acc[k] += sg * vs[t] * cs[t][k];
+      }
+    }
+    g.V[i] = vol;
+    for (int k = 0; k < 3; ++k) g.xc[3 * i + k] = acc[k] / vol;
+  }
+  // faces, matched by their sorted node ids
+  std::map<FaceKey, std::pair<int64_t, int>> seen;
+  std::vector<std::array<int32_t, 4>> fnodes;  // the nodes of every face in cyclic order (-1: triangle)
+  g.cf.assign((size_t)g.mf * nc, -1);
+  auto cyc = [&](int64_t i, int a) {
+    const LocalFaces* lf = local_faces(kinds[i]);
+    std::array<int32_t, 4> v = {-1, -1, -1, -1};
+    for (int q = 0; q < lf->size[a]; ++q) v[q] = cells[8 * i + lf->node[a][q]];
+    return v;
+  };
+  for (int64_t i = 0; i < nc; ++i) {
+    const LocalFaces* lf = local_faces(kinds[i]);
+    for (int a = 0; a < lf->n; ++a) {
+      std::array<int32_t, 4> v = cyc(i, a);
+      FaceKey key = face_key(v.data(), lf->size[a]);
       auto it = seen.find(key);
       if (it == seen.end()) {
         seen[key] = {i, a};
@@ -156,18 +293,17 @@ int build_geom(Geom& g, const double* xyz, int64_t nn, const int32_t* tet, int64
         g.fo.push_back(it->second.first);
         g.fn.push_back(i);
         g.ftag.push_back(0);
-        fkey.push_back(key);
-        g.cf[4 * it->second.first + it->second.second] = f;
-        g.cf[4 * i + a] = f;
+        fnodes.push_back(cyc(it->second.first, it->second.second));
+        g.cf[(size_t)g.mf * it->second.first + it->second.second] = f;
+        g.cf[(size_t)g.mf * i + a] = f;
         it->second.first = -1;
       }
     }
   }
-  std::map<std::array<int32_t, 3>, int32_t> btags;
+  std::map<FaceKey, int32_t> btags;
   for (int64_t b = 0; b < nb; ++b) {
-    std::array<int32_t, 3> key = {btri[3 * b], btri[3 * b + 1], btri[3 * b + 2]};
-    std::sort(key.begin(), key.end());
-    btags[key] = btag[b];
+    const int n = bface[4 * b + 3] < 0 ? 3 : 4;
+    btags[face_key(bface + 4 * b, n)] = btag[b];
   }
   for (auto& kv : seen) {
     if (kv.second.first < 0) continue;
@@ -177,23 +313,21 @@ int build_geom(Geom& g, const double* xyz, int64_t nn, const int32_t* tet, int64
     g.fo.push_back(kv.second.first);
     g.fn.push_back(-1);
     g.ftag.push_back(bt->second);
-    fkey.push_back(kv.first);
-    g.cf[4 * kv.second.first + kv.second.second] = f;
+    fnodes.push_back(cyc(kv.second.first, kv.second.second));
+    g.cf[(size_t)g.mf * kv.second.first + kv.second.second] = f;
   }
   g.nf = (int64_t)g.fo.size();
   g.A.assign(g.nf, 0.0);
   g.n.assign(3 * g.nf, 0.0);
   g.xf.assign(3 * g.nf, 0.0);
   for (int64_t f = 0; f < g.nf; ++f) {
-    const double* a = xyz + 3 * fkey[f][0];
-    const double* b = xyz + 3 * fkey[f][1];
-    const double* c = xyz + 3 * fkey[f][2];
-    double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-    double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const int n = fnodes[f][3] < 0 ? 3 : 4;
+    const double* p[4];
+    for (int q = 0; q < n; ++q) p[q] = xyz + 3 * fnodes[f][q];
     double nn3[3];
-    cross3(e1, e2, nn3);
+    face_geometry(p, n, nn3, &g.xf[3 * f]);
+    for (int k = 0; k < 3; ++k) nn3[k] *= 2.0;  // twice the vector area, as the triangle's cross product
     double len = std::sqrt(nn3[0] * nn3[0] + nn3[1] * nn3[1] + nn3[2] * nn3[2]);
-    for (int k = 0; k < 3; ++k) g.xf[3 * f + k] = (a[k] + b[k] + c[k]) / 3.0;
     // n points out of the owner cell (from cell i to cell j, Sec. 3.1)
     const double* xo = &g.xc[3 * g.fo[f]];
     double dot = 0.0;
@@ -216,8 +350,8 @@ int build_geom(Geom& g, const double* xyz, int64_t nn, const int32_t* tet, int64
   // closure check: sum_f A n = 0 per cell
   for (int64_t i = 0; i < nc; ++i) {
     double acc[3] = {0, 0, 0}, asum = 0.0;
-    for (int a = 0; a < 4; ++a) {
-      int64_t f = g.cf[4 * i + a];
+    for (int a = 0; a < g.nfc[i]; ++a) {
+      int64_t f = g.cf[(size_t)g.mf * i + a];
       double sg = (g.fo[f] == i) ? 1.0 : -1.0;
       for (int k = 0; k < 3; ++k) acc[k] += sg * g.A[f] * g.n[3 * f + k];
       asum += g.A[f];
@@ -239,7 +373,7 @@ int build_geom(Geom& g, const double* xyz, int64_t nn, const int32_t* tet, int64
   g.dt.assign(nc, 0.0);
   for (int64_t i = 0; i < nc; ++i) {
     double asum = 0.0;
-    for (int a = 0; a < 4; ++a) asum += g.A[g.cf[4 * i + a]];
+    for (int a = 0; a < g.nfc[i]; ++a) asum += g.A[g.cf[(size_t)g.mf * i + a]];
     g.h[i] = 6.0 * g.V[i] / asum;
     g.dt[i] = cfl * g.h[i] / g.umax;
   }
@@ -263,8 +397,8 @@ int build_geom(Geom& g, const double* xyz, int64_t nn, const int32_t* tet, int64
   g.Minv.assign(9 * nc, 0.0);
   for (int64_t i = 0; i < nc; ++i) {
     double M[9] = {0};
-    for (int a = 0; a < 4; ++a) {
-      int64_t f = g.cf[4 * i + a];
+    for (int a = 0; a < g.nfc[i]; ++a) {
+      int64_t f = g.cf[(size_t)g.mf * i + a];
       int64_t j = (g.fo[f] == i) ? g.fn[f] : g.fo[f];
       double d[3];
       for (int k = 0; k < 3; ++k) d[k] = (j >= 0 ? g.xc[3 * j + k] : g.xf[3 * f + k]) - g.xc[3 * i + k];
@@ -556,8 +690,8 @@ template <class S> struct Solver {
           S pi = phi[size_t(i) * nv + k];
           S b[3] = {0.0, 0.0, 0.0};
           S pmax = pi, pmin = pi;
-          for (int a = 0; a < 4; ++a) {
-            int64_t f = geo.cf[4 * i + a];
+          for (int a = 0; a < geo.nfc[i]; ++a) {
+            int64_t f = geo.cf[(size_t)geo.mf * i + a];
             int64_t j = (geo.fo[f] == i) ? geo.fn[f] : geo.fo[f];
             if (j < 0) continue;
             S pj = phi[size_t(j) * nv + k];
@@ -577,8 +711,8 @@ template <class S> struct Solver {
             // frozen values (limiter freezing): a constant of every derivative
             L = S(Lf[size_t(i) * nv + k]);
           } else if (lim) {
-            for (int a = 0; a < 4; ++a) {
-              int64_t f = geo.cf[4 * i + a];
+            for (int a = 0; a < geo.nfc[i]; ++a) {
+              int64_t f = geo.cf[(size_t)geo.mf * i + a];
               S d2 = 0.0;
               for (int d = 0; d < 3; ++d) d2 += gr[d] * (geo.xf[3 * f + d] - geo.xc[3 * i + d]);
               S d1 = re(d2) > 0.0 ? S(pmax - pi) : S(pmin - pi);
@@ -689,8 +823,8 @@ template <class S> struct Solver {
     Fmac.assign(6 * nc, 0.0);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nc; ++i) {
-      for (int a = 0; a < 4; ++a) {
-        int64_t f = geo.cf[4 * i + a];
+      for (int a = 0; a < geo.nfc[i]; ++a) {
+        int64_t f = geo.cf[(size_t)geo.mf * i + a];
         double sg = geo.fo[f] == i ? 1.0 : -1.0;  // n_ij points out of cell i
         for (int64_t k = 0; k < nv; ++k) {
           FG[size_t(i) * nv + k] += sg * ffG[size_t(f) * nv + k] / geo.V[i];
@@ -727,8 +861,8 @@ template <class S> struct Solver {
     std::vector<S> D(nc), Res(6 * nc);
     for (int64_t i = 0; i < nc; ++i) {
       S acc = 0.0;
-      for (int a = 0; a < 4; ++a) {
-        int64_t f = geo.cf[4 * i + a];
+      for (int a = 0; a < geo.nfc[i]; ++a) {
+        int64_t f = geo.cf[(size_t)geo.mf * i + a];
         acc += 0.5 * geo.A[f] / geo.V[i] * rf[f];
       }
       D[i] = inv_dt_cell(i) + acc;
@@ -739,8 +873,8 @@ template <class S> struct Solver {
     auto relax = [&](int64_t i) {
       S acc[6];
       for (int d = 0; d < 6; ++d) acc[d] = Res[6 * i + d];
-      for (int a = 0; a < 4; ++a) {
-        int64_t f = geo.cf[4 * i + a];
+      for (int a = 0; a < geo.nfc[i]; ++a) {
+        int64_t f = geo.cf[(size_t)geo.mf * i + a];
         int64_t j = (geo.fo[f] == i) ? geo.fn[f] : geo.fo[f];
         if (j < 0) continue;  // no increment across a boundary face
         double sg = geo.fo[f] == i ? 1.0 : -1.0;
@@ -811,8 +945,8 @@ template <class S> struct Solver {
         for (int64_t k = k0; k < k1; ++k) {
           S diag = inv_dt_cell(i) + 1.0 / tau_t[i];
           S accG = ResG[size_t(i) * nv + k], accR = ResR[size_t(i) * nv + k];
-          for (int a = 0; a < 4; ++a) {
-            int64_t f = geo.cf[4 * i + a];
+          for (int a = 0; a < geo.nfc[i]; ++a) {
+            int64_t f = geo.cf[(size_t)geo.mf * i + a];
             double sg = geo.fo[f] == i ? 1.0 : -1.0;
             double n[3] = {sg * geo.n[3 * f], sg * geo.n[3 * f + 1], sg * geo.n[3 * f + 2]};
             double un = u_dot_n(geo, k, n, num.snap);
@@ -969,11 +1103,13 @@ template <class S> void copy_out(const std::vector<S>& v, double* out) {
 // ---------------------------------------------------------------------------
 extern "C" {
 
-void* orc_geom_create(const double* xyz, int64_t nn, const int32_t* tet, int64_t nc, const int32_t* btri,
-                      const int32_t* btag, int64_t nb, const double* u, const double* w, int64_t nv, double cfl,
-                      int32_t* status) {
+// cells [nc][8] node ids with kinds [nc] (4 tetrahedron, 5 pyramid, 6 prism, 8 hexahedron); bface [nb][4]
+// boundary faces (-1 in the last place for a triangle) with tags btag.
+void* orc_geom_create(const double* xyz, int64_t nn, const int32_t* cells, const int32_t* kinds, int64_t nc,
+                      const int32_t* bface, const int32_t* btag, int64_t nb, const double* u, const double* w,
+                      int64_t nv, double cfl, int32_t* status) {
   Geom* g = new Geom();
-  int st = build_geom(*g, xyz, nn, tet, nc, btri, btag, nb, u, w, nv, cfl);
+  int st = build_geom(*g, xyz, nn, cells, kinds, nc, bface, btag, nb, u, w, nv, cfl);
   if (status) *status = st;
   if (st != 0) {
     delete g;
@@ -990,7 +1126,7 @@ int32_t orc_threads(int32_t n) {
   return omp_get_max_threads();
 }
 
-// counts: nc, nf, n_interior, nv
+// counts: nc, nf, n_interior, nv, face slots per cell
 void orc_geom_counts(void* gp, int64_t* out) {
   Geom* g = static_cast<Geom*>(gp);
   int64_t ni = 0;
@@ -999,6 +1135,7 @@ void orc_geom_counts(void* gp, int64_t* out) {
   out[1] = g->nf;
   out[2] = ni;
   out[3] = g->nv;
+  out[4] = g->mf;
 }
 
 void orc_geom_arrays(void* gp, double* V, double* xc, double* h, double* dt, int64_t* cf, int64_t* fo, int64_t* fn,

@@ -56,43 +56,57 @@ def _bc(tag, kind, rho=1.0, U=(0.0, 0.0, 0.0), T=1.0):
     return dict(tag=int(tag), kind=int(kind), rho=float(rho), U=[float(x) for x in U], T=float(T))
 
 
+def _box(kind, n, seed, tag_of_plane=None):
+    """Box mesh of n^3 grid cells: "tet" (6 Kuhn tetrahedra each), "hex" (the hexahedra themselves) or "mixed"
+    (hexahedra, pyramids and tetrahedra)."""
+    if kind == "tet":
+        return _mesh.kuhn_box_mesh(n=n, seed=seed, tag_of_plane=tag_of_plane)
+    if kind == "hex":
+        return _mesh.hex_box_mesh(n=n, seed=seed, tag_of_plane=tag_of_plane)
+    if kind == "mixed":
+        return _mesh.mixed_box_mesh(n=n, seed=seed, tag_of_plane=tag_of_plane)
+    raise ValueError(f"unknown mesh kind {kind}")
+
+
 def cavity_case(seed: int = 0, n: int = 6, nv_side: int = 8, kn: float = 0.1, lid_speed: float = 0.15,
-                n_iter: int = 200):
-    """3-D lid-driven cubic cavity: n^3 hexes x 6 Kuhn tets, Cartesian nv_side^3 DVS on [-4,4]^3."""
-    m = _mesh.kuhn_box_mesh(n=n, seed=seed)
+                n_iter: int = 200, kind: str = "tet"):
+    """3-D lid-driven cubic cavity: n^3 hexes x 6 Kuhn tets (kind "hex": the hexes, "mixed": hexes, pyramids and
+    tets), Cartesian nv_side^3 DVS on [-4,4]^3."""
+    m = _box(kind, n, seed)
     u, w = _dvs.cartesian_dvs(nv_side, 4.0)
     gas = gas_n2(kn, 3.0)
     bcs = [_bc(1, WALL, U=(0, 0, 0), T=1.0), _bc(2, WALL, U=(lid_speed, 0, 0), T=1.0)]
     W0 = rest_state()
-    return dict(name=f"cavity{n}^3x6_dvs{nv_side}^3_kn{kn}_seed{seed}", mesh=m, u=u, w=w, gas=gas,
+    return dict(name=f"cavity{n}^3_{kind}_dvs{nv_side}^3_kn{kn}_seed{seed}", mesh=m, u=u, w=w, gas=gas,
                 num=numerics_default(), bcs=bcs, W0=W0, n_iter=n_iter)
 
 
-def freestream_box_case(seed: int = 0, n: int = 3, U=(0.3, -0.1, 0.2), dvs=None, kn: float = 0.1):
+def freestream_box_case(seed: int = 0, n: int = 3, U=(0.3, -0.1, 0.2), dvs=None, kn: float = 0.1,
+                        kind: str = "tet"):
     """All-far-field box: a uniform free stream must give a zero residual."""
-    m = _mesh.kuhn_box_mesh(n=n, seed=seed, tag_of_plane=lambda a, s: 2)
+    m = _box(kind, n, seed, tag_of_plane=lambda a, s: 2)
     if dvs is None:
         u, w = _dvs.cartesian_dvs(8, 4.0)
     else:
         u, w = dvs
     gas = gas_n2(kn, 3.0)
     bcs = [_bc(2, FARFIELD, rho=1.0, U=U, T=1.0)]
-    return dict(name=f"freestream_box{n}", mesh=m, u=u, w=w, gas=gas, num=numerics_default(), bcs=bcs,
+    return dict(name=f"freestream_box{n}_{kind}", mesh=m, u=u, w=w, gas=gas, num=numerics_default(), bcs=bcs,
                 W0=rest_state(1.0, U, 1.0), n_iter=1)
 
 
 def open_box_case(seed: int = 0, n: int = 3, U=(0.3, 0.0, 0.0), T_wall: float = 1.5, nv_side: int = 6,
-                  kn: float = 0.1):
+                  kn: float = 0.1, kind: str = "tet"):
     """Box with a diffuse wall at z = 0 (tag 1) and far field on the other five sides (tag 2).
 
     Unlike the closed cavity, whose steady states form a family parameterised by
     the total mass, this problem has a unique steady state.
     """
-    m = _mesh.kuhn_box_mesh(n=n, seed=seed, tag_of_plane=lambda a, s: 1 if (a == 2 and s == 0) else 2)
+    m = _box(kind, n, seed, tag_of_plane=lambda a, s: 1 if (a == 2 and s == 0) else 2)
     u, w = _dvs.cartesian_dvs(nv_side, 4.0)
     gas = gas_n2(kn, 3.0)
     bcs = [_bc(1, WALL, U=(0, 0, 0), T=T_wall), _bc(2, FARFIELD, rho=1.0, U=U, T=1.0)]
-    return dict(name=f"open_box{n}", mesh=m, u=u, w=w, gas=gas, num=numerics_default(), bcs=bcs,
+    return dict(name=f"open_box{n}_{kind}", mesh=m, u=u, w=w, gas=gas, num=numerics_default(), bcs=bcs,
                 W0=rest_state(1.0, U, 1.0), n_iter=100)
 
 

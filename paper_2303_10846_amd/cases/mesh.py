@@ -1,7 +1,7 @@
-"""Seeded tetrahedral meshes for the synthetic workloads.
+"""Seeded tetrahedral, hexahedral and mixed meshes for the synthetic workloads.
 
-This module only builds inputs: node coordinates, tetrahedra, tagged boundary
-triangles and a colour-major cell order.  It holds none of the scheme's
+This module only builds inputs: node coordinates, cells, tagged boundary
+faces and a colour-major cell order.  It holds none of the scheme's
 arithmetic (no face geometry, no fluxes); the solver library and the CPU
 oracle each derive their own geometry from these arrays.
 
@@ -19,6 +19,9 @@ import numpy as np
 __all__ = [
     "folded_faces",
     "kuhn_box_mesh",
+    "hex_box_mesh",
+    "mixed_box_mesh",
+    "color_major_cells",
     "shell_mesh",
     "sphere_body",
     "capsule_body",
@@ -169,19 +172,26 @@ def color_major(xyz: np.ndarray, tets: np.ndarray, search_cells: int = 150_000):
     Cells keep their Morton order within a class.  Returns (tets_reordered, color_offsets) with
     color_offsets[c]..color_offsets[c+1] the cells of colour c.  No two cells of one colour share a face.
     """
-    nt = len(tets)
-    cen = xyz[tets].mean(axis=1)
+    morton = _morton_order(xyz[tets].mean(axis=1))
+    tets = tets[morton]
+    pairs, _ = _match_faces(tets)
+    order, offsets = _colour_major_order(pairs, len(tets), search_cells)
+    return np.ascontiguousarray(tets[order]), offsets
+
+
+def _morton_order(cen: np.ndarray) -> np.ndarray:
     lo = cen.min(axis=0)
     span = np.maximum(cen.max(axis=0) - lo, 1e-300)
     q = np.minimum(((cen - lo) / span * 1023.0).astype(np.int64), 1023)
-    code = np.zeros(nt, dtype=np.int64)
+    code = np.zeros(len(cen), dtype=np.int64)
     for b in range(10):
         for ax in range(3):
             code |= ((q[:, ax] >> b) & 1) << (3 * b + ax)
-    morton = np.argsort(code, kind="stable")
-    tets = tets[morton]
+    return np.argsort(code, kind="stable")
 
-    pairs, _ = _match_faces(tets)
+
+def _colour_major_order(pairs: np.ndarray, nt: int, search_cells: int):
+    """Steps 1-4 of color_major on cells already in Morton order: (cell order, colour offsets)."""
     nbr = [[] for _ in range(nt)]
     for a, b in pairs.tolist():
         nbr[a].append(b)
@@ -231,7 +241,195 @@ def color_major(xyz: np.ndarray, tets: np.ndarray, search_cells: int = 150_000):
     order = np.argsort(color, kind="stable")
     offsets = np.zeros(ncol + 1, dtype=np.int64)
     offsets[1:] = np.cumsum(np.bincount(color, minlength=ncol))
-    return np.ascontiguousarray(tets[order]), offsets
+    return order, offsets
+
+
+# --------------------------------------------------------------------------
+# Mixed-element meshes: cells [nc][8] padded with -1, kinds = node count (4 tetrahedron, 5 pyramid, 6 prism,
+# 8 hexahedron), boundary faces [nb][4] padded with -1 (a triangle has -1 in the last place)
+# --------------------------------------------------------------------------
+
+LOCAL_FACES = {
+    4: ((1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)),
+    5: ((0, 1, 2, 3), (0, 1, 4), (1, 2, 4), (2, 3, 4), (3, 0, 4)),
+    6: ((0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)),
+    8: ((0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)),
+}
+
+
+def _cell_face_lists(cells: np.ndarray, kinds: np.ndarray):
+    """Every face of every cell: (cyclic node lists [m][4] padded with -1, sorted keys [m][4], owner [m])."""
+    cyc, own = [], []
+    for i, (c, k) in enumerate(zip(cells.tolist(), kinds.tolist())):
+        for lf in LOCAL_FACES[k]:
+            v = [c[a] for a in lf] + [-1] * (4 - len(lf))
+            cyc.append(v)
+            own.append(i)
+    cyc = np.array(cyc, dtype=np.int64)
+    keys = cyc.copy()
+    tri = keys[:, 3] < 0
+    keys[tri, :3] = np.sort(keys[tri, :3], axis=1)
+    keys[~tri] = np.sort(keys[~tri], axis=1)
+    return cyc, keys, np.array(own, dtype=np.int64)
+
+
+def match_faces_cells(cells: np.ndarray, kinds: np.ndarray):
+    """(pairs [n_int][2] of cells sharing a face, boundary faces [n_b][4] as cyclic node lists)."""
+    cyc, keys, own = _cell_face_lists(cells, kinds)
+    order = np.lexsort(keys.T[::-1])
+    ks = keys[order]
+    same = np.all(ks[1:] == ks[:-1], axis=1)
+    if np.any(same[1:] & same[:-1]):
+        raise ValueError("non-manifold mesh: a face is shared by more than two cells")
+    first = np.nonzero(same)[0]
+    pairs = np.stack([own[order[first]], own[order[first + 1]]], axis=1)
+    in_pair = np.zeros(len(ks), dtype=bool)
+    in_pair[first] = True
+    in_pair[first + 1] = True
+    return pairs, cyc[order[~in_pair]]
+
+
+def color_major_cells(xyz: np.ndarray, cells: np.ndarray, kinds: np.ndarray, search_cells: int = 150_000):
+    """color_major for mixed cells: returns (cells, kinds) in colour-major order and the colour offsets."""
+    cen = np.array([xyz[c[:k]].mean(axis=0) for c, k in zip(cells, kinds)])
+    morton = _morton_order(cen)
+    cells, kinds = cells[morton], kinds[morton]
+    pairs, _ = match_faces_cells(cells, kinds)
+    order, offsets = _colour_major_order(pairs, len(cells), search_cells)
+    return np.ascontiguousarray(cells[order]), np.ascontiguousarray(kinds[order]), offsets
+
+
+def _sub_tet_volumes(xyz, cells, kinds):
+    """Signed volumes of the tetrahedra from each cell's node average to the triangles of its faces (quads fanned
+    about their node average), each face's in the orientation of its local node order; a valid cell has all of
+    one face's of one sign, and that sign the same for every face when the local orders are consistent."""
+    out = []
+    for c, k in zip(cells.tolist(), kinds.tolist()):
+        p0 = xyz[c[:k]].mean(axis=0)
+        vs = []
+        for lf in LOCAL_FACES[k]:
+            p = xyz[[c[a] for a in lf]]
+            tris = [p] if len(lf) == 3 else [np.array([p[q], p[(q + 1) % 4], p.mean(axis=0)]) for q in range(4)]
+            vs.append([float(np.cross(t[1] - t[0], t[2] - t[0]) @ (t[0] - p0)) / 6.0 for t in tris])
+        out.append(vs)
+    return out
+
+
+def _cells_valid(xyz, cells, kinds) -> bool:
+    for vs in _sub_tet_volumes(xyz, cells, kinds):
+        for face in vs:
+            if not (all(v > 0 for v in face) or all(v < 0 for v in face)):
+                return False
+    return True
+
+
+def _box_grid(n, seed, jitter, length):
+    h = length / n
+    m = n + 1
+    g = np.arange(m) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    xyz0 = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    ijk = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"), -1).reshape(-1, 3)
+    interior = np.all((ijk > 0) & (ijk < n), axis=1)
+    return xyz0, interior, (lambda i, j, k: (i * m + j) * m + k), h
+
+
+def _hex_nodes(nid, i, j, k):
+    return [nid(i, j, k), nid(i + 1, j, k), nid(i + 1, j + 1, k), nid(i, j + 1, k),
+            nid(i, j, k + 1), nid(i + 1, j, k + 1), nid(i + 1, j + 1, k + 1), nid(i, j + 1, k + 1)]
+
+
+def _finish_box(xyz, cells, kinds, length, tag_of_plane):
+    cells_c, kinds_c, offsets = color_major_cells(xyz, cells, kinds)
+    _, bcyc = match_faces_cells(cells_c, kinds_c)
+    fc = np.array([xyz[[v for v in f if v >= 0]].mean(axis=0) for f in bcyc])
+    tags = np.zeros(len(bcyc), dtype=np.int64)
+    for ax in range(3):
+        for side in (0, 1):
+            on = np.abs(fc[:, ax] - side * length) < 1e-12 * max(length, 1.0)
+            tags[on] = tag_of_plane(ax, side)
+    if np.any(tags == 0):
+        raise RuntimeError("unclassified boundary face")
+    return dict(xyz=xyz, cells=cells_c.astype(np.int64), kinds=kinds_c.astype(np.int64), bface=bcyc, btag=tags,
+                color_offsets=offsets)
+
+
+def hex_box_mesh(n: int = 6, seed: int = 0, jitter: float = 0.15, length: float = 1.0, tag_of_plane=None):
+    """n^3 hexahedra on [0,L]^3 (the paper's cavity mesh is hexahedral, Sec. 4.1).  Interior nodes are jittered by
+    U(-jitter*h, jitter*h)^3 from ``numpy.random.default_rng(seed)``, so faces are warped quadrilaterals; a draw
+    that folds a cell is redrawn.  Tags as kuhn_box_mesh."""
+    if tag_of_plane is None:
+        def tag_of_plane(axis, side):
+            return 2 if (axis == 2 and side == 1) else 1
+    xyz0, interior, nid, h = _box_grid(n, seed, jitter, length)
+    cells = np.array([_hex_nodes(nid, i, j, k) for i in range(n) for j in range(n) for k in range(n)],
+                     dtype=np.int64)
+    kinds = np.full(len(cells), 8, dtype=np.int64)
+    rng = np.random.default_rng(seed)
+    for _ in range(100):
+        xyz = xyz0.copy()
+        xyz[interior] += rng.uniform(-jitter * h, jitter * h, size=(int(interior.sum()), 3))
+        if _cells_valid(xyz, cells, kinds):
+            break
+    else:
+        raise RuntimeError("could not draw a valid jitter")
+    return _finish_box(xyz, cells, kinds, length, tag_of_plane)
+
+
+def mixed_box_mesh(n: int = 4, seed: int = 0, jitter: float = 0.1, length: float = 1.0, tag_of_plane=None):
+    """A conforming box mesh of hexahedra, pyramids and tetrahedra on [0,L]^3.  The n^3 grid cells with
+    i < n/2 are hexahedra; each other cell is cut into six pyramids on its faces with their apex at the cell's
+    node average, and every pyramid whose base is not shared with a hexahedron is cut again into two
+    tetrahedra along the base diagonal through the base's smallest node id (so both cells of a shared quad cut
+    it alike).  Interior grid nodes are jittered as in hex_box_mesh."""
+    if tag_of_plane is None:
+        def tag_of_plane(axis, side):
+            return 2 if (axis == 2 and side == 1) else 1
+    xyz0, interior, nid, h = _box_grid(n, seed, jitter, length)
+    half = n // 2
+    rng = np.random.default_rng(seed)
+    n_grid = len(xyz0)
+    for _ in range(100):
+        xyz = xyz0.copy()
+        xyz[interior] += rng.uniform(-jitter * h, jitter * h, size=(int(interior.sum()), 3))
+        pts = [xyz]
+        cells, kinds = [], []
+        napex = n_grid
+        for i in range(n):
+            for j in range(n):
+                for k in range(n):
+                    hx = _hex_nodes(nid, i, j, k)
+                    if i < half:
+                        cells.append(hx)
+                        kinds.append(8)
+                        continue
+                    apex = napex
+                    napex += 1
+                    pts.append(xyz[hx].mean(axis=0)[None, :])
+                    for a, lf in enumerate(LOCAL_FACES[8]):
+                        q = [hx[x] for x in lf]
+                        if a == 5 and i == half:          # the -x face, shared with a hexahedron
+                            cells.append(q + [apex, -1, -1, -1])
+                            kinds.append(5)
+                            continue
+                        lo = int(np.argmin(q))
+                        if lo in (0, 2):
+                            tets = [[q[0], q[1], q[2], apex], [q[0], q[2], q[3], apex]]
+                        else:
+                            tets = [[q[0], q[1], q[3], apex], [q[1], q[2], q[3], apex]]
+                        for t in tets:
+                            cells.append(t + [-1, -1, -1, -1])
+                            kinds.append(4)
+        allxyz = np.concatenate(pts, axis=0)
+        cells = np.array([c + [-1] * (8 - len(c)) for c in cells], dtype=np.int64)
+        kinds = np.array(kinds, dtype=np.int64)
+        if _cells_valid(allxyz, cells, kinds):
+            break
+    else:
+        raise RuntimeError("could not draw a valid jitter")
+    return _finish_box(allxyz, cells, kinds, length, tag_of_plane)
+
+
 
 
 # --------------------------------------------------------------------------
