@@ -75,9 +75,12 @@ typedef struct {
    limiter  : 0 off; 1 Venkatakrishnan, differentiated by cis_residual_vjp on the branch the state takes;
               2 the same limiter in the iteration, held fixed (frozen) by cis_residual_vjp, whose product is
               then the derivative of the scheme with the limiter values of the current state;
-              3 frozen values: the values stored by cis_limiter_freeze are used in place of the limiter in every
-              reconstruction (and are constants of cis_residual_vjp).  Refused until cis_limiter_freeze has
-              attached them.
+              3 stored values: the values attached by cis_limiter_freeze are used in place of the limiter in
+              every reconstruction (and are constants of cis_residual_vjp);
+              4 monotone freezing: every reconstruction takes the smaller of limiter 1's value and the stored
+              one, and stores it back, so the stored values only decrease (the steady residual, VJP and adjoint
+              refuse it: switch to 3 once the values have settled).
+              3 and 4 are refused until cis_limiter_freeze has attached values.
    snap     : |u.n| <= snap |u| counts as u.n = 0 (upwind side x_j, Eq. 46).
    n_macro, n_micro : forward+backward sweep pairs of the macro (Eq. 43) and micro (Eq. 33) PR-SGS. */
 typedef struct {
@@ -95,13 +98,14 @@ typedef struct {
 
 typedef struct {
   int64_t n_cells, n_faces, n_interior, n_boundary, n_colors;
+  int64_t max_faces; /* face slots per cell: 4 when every cell is a tetrahedron, else 6 */
 } cis_mesh_info_t;
 
 typedef struct {
   int64_t phi_bytes;   /* one [n_cells][n_vel] distribution array */
   int64_t face_bytes;  /* one [n_faces][n_vel] face array */
   int64_t cell6_bytes; /* one [n_cells][6] FP64 array (W or q) */
-  int64_t code_bytes;  /* the [n_cells][n_vel] uint8 upwind-code array */
+  int64_t code_bytes;  /* the [n_cells][n_vel] upwind-code array: uint8 (4 face slots) or uint16 (6) */
   int64_t total_bytes; /* sum over all cis_device_buffers members */
 } cis_buffer_sizes;
 
@@ -117,9 +121,10 @@ typedef struct {
   void* faceR;
   double* W;    /* [n_cells][6] */
   double* q;    /* [n_cells][6] */
-  uint8_t* upwind; /* [n_cells][n_vel], written by cis_state_create: for face slot a of cell i (its a-th face),
-                      bits 2a..2a+1 of entry (i, k) are 1 if u_k.n > 0 (out of the cell), 2 if u_k.n < 0, 0 if
-                      |u_k.n| is within the tie tolerance of zero (Eq. 46 upwinding, Eq. 33 diagonal) */
+  uint8_t* upwind; /* [n_cells][n_vel] uint8 (mesh with 4 face slots) or uint16 (6 slots) codes, written by
+                      cis_state_create: for face slot a of cell i (its a-th face), bits 2a..2a+1 of entry (i, k) are
+                      1 if u_k.n > 0 (out of the cell), 2 if u_k.n < 0, 0 if |u_k.n| is within the tie tolerance of
+                      zero or the slot is unused (Eq. 46 upwinding, Eq. 33 diagonal) */
 } cis_device_buffers;
 
 /* Last error message of this thread. */
@@ -135,6 +140,21 @@ const char* cis_last_error(void);
 cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* tet, int64_t n_cells,
                            const int32_t* btri, const int32_t* btag, int64_t n_b,
                            const int64_t* color_offsets, int64_t n_colors, cis_mesh** out);
+/* Mesh of mixed cells (the paper's meshes are hexahedral, Sec. 4): cells [n_cells][8] node ids (unused places
+   ignored) of the kinds kinds [n_cells] = node count: 4 tetrahedron, 5 pyramid (base quad 0-3 in cyclic order,
+   apex 4), 6 prism (triangles 0-2 and 3-5, with 0-3, 1-4, 2-5 edges), 8 hexahedron (quads 0-3 and 4-7 in
+   cyclic order, with 0-4, 1-5, 2-6, 3-7 edges).  bface [n_b][4] boundary faces (-1 in the last place of a
+   triangle) with tags btag.  A quad face need not be planar: its area vector is half the cross product of its
+   diagonals and its centroid the area-weighted centroid of the four triangles it makes with its node average;
+   a cell other than a tetrahedron has the volume and centroid of the tetrahedra from its node average to those
+   triangles.  Face slot a of a cell is its a-th local face: for a tetrahedron the face opposite local vertex a;
+   a pyramid: base, then (0,1,4), (1,2,4), (2,3,4), (3,0,4); a prism: (0,1,2), (3,4,5), (0,1,4,3), (1,2,5,4),
+   (2,0,3,5); a hexahedron: (0,1,2,3), (4,5,6,7), (0,1,5,4), (1,2,6,5), (2,3,7,6), (3,0,4,7).  Colours and errors as
+   for cis_mesh_create (plus CIS_E_INVALID_ARG for an unknown kind, CIS_E_MESH for a folded cell).  The steady
+   residual, VJP and adjoint run on tetrahedral meshes only (CIS_E_UNSUPPORTED otherwise). */
+cis_status cis_mesh_create_cells(const double* xyz, int64_t n_nodes, const int32_t* cells, const int32_t* kinds,
+                                 int64_t n_cells, const int32_t* bface, const int32_t* btag, int64_t n_b,
+                                 const int64_t* color_offsets, int64_t n_colors, cis_mesh** out);
 cis_status cis_mesh_info(const cis_mesh* mesh, cis_mesh_info_t* out);
 void cis_mesh_destroy(cis_mesh* mesh);
 
@@ -158,14 +178,16 @@ cis_status cis_state_create(const cis_mesh* mesh, const cis_dvs* dvs, const cis_
 cis_status cis_state_set_numerics(cis_state* s, const cis_numerics* num);
 void cis_state_destroy(cis_state* s);
 
-/* Limiter freezing.  Computes Venkatakrishnan's limiter values L of the current state (Eq. 46, as limiter 1, with
-   the state's lim_K) for every (cell, velocity) of G and of R into L, caller-owned device memory of
-   2 * n_cells * n_vel values in the state's precision ([G | R], each [n_cells][n_vel]), and attaches L to the
-   state: with numerics.limiter = 3 the reconstruction then uses these values instead of recomputing them, so
-   the scheme near a steady state is a smooth function of phi (the min over faces and the stencil extrema no
-   longer switch).  L must stay valid while attached; the face buffers are overwritten.  L = NULL detaches
-   (refused while limiter 3 is in use).  Errors: CIS_E_INVALID_ARG, CIS_E_DEVICE. */
-cis_status cis_limiter_freeze(cis_state* s, void* L);
+/* Limiter freezing.  L: caller-owned device memory of 2 * n_cells * n_vel values in the state's precision
+   ([G | R], each [n_cells][n_vel]).  compute != 0: Venkatakrishnan's limiter values of the current state (Eq. 46,
+   as limiter 1, with the state's lim_K) are written to L for every (cell, velocity) of G and of R (the face
+   buffers are overwritten); compute = 0: L's contents are taken as they are (values in [0, 1], e.g. those of
+   another state).  L is then attached to the state: with numerics.limiter = 3 the reconstruction uses these
+   values instead of recomputing them, so near a steady state the scheme is a smooth function of phi (the min
+   over faces and the stencil extrema no longer switch); with limiter 4 it also lowers them where the computed
+   limiter is smaller.  L must stay valid while attached.  L = NULL detaches (refused while limiter 3 or 4 is in
+   use).  Errors: CIS_E_INVALID_ARG, CIS_E_DEVICE. */
+cis_status cis_limiter_freeze(cis_state* s, void* L, int32_t compute);
 
 /* Step 1: phi = phi*(W0, q = 0) in every cell (Eqs. 17-23).  W0 is host [6] (per_cell = 0) or
    [n_cells][6] (per_cell = 1). */

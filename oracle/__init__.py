@@ -260,10 +260,11 @@ class Oracle:
         self._num = num_array(self.num)
         self.lib.orc_set_num(self.sol, _dp(self._num))
 
-    def freeze_limiter(self):
-        """Store the limiter values of the current state and switch to limiter 3, which uses them."""
+    def freeze_limiter(self, limiter: int = 3):
+        """Store the limiter values of the current state and switch to `limiter` (3 uses them; 4 also lowers them
+        where the computed limiter is smaller)."""
         self.lib.orc_freeze_limiter(self.sol)
-        self.set_num(limiter=3)
+        self.set_num(limiter=limiter)
 
     def explicit(self):
         """Steps 2-3 on the current state (fills FG, FR, Fmac, Qface, gradG, gradR, ff*)."""

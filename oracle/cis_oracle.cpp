@@ -722,7 +722,10 @@ template <class S> struct Solver {
             // limiter = 2: the same L in the iteration, held fixed in derivatives (frozen limiter), so a
             // complex step carries none of it
             if (lim == 2) L = S(re(L));
-            if (capture) Lf[size_t(i) * nv + k] = re(L);
+            // limiter = 4 (monotone freezing): the smaller of this value and the stored one, stored back
+            if (lim == 4 && Lf[size_t(i) * nv + k] < re(L)) L = S(Lf[size_t(i) * nv + k]);
+            if (lim == 4) L = S(re(L));
+            if (capture || lim == 4) Lf[size_t(i) * nv + k] = re(L);
           }
           for (int d = 0; d < 3; ++d) out[3 * (size_t(i) * nv + k) + d] = L * gr[d];
         }

@@ -29,6 +29,7 @@ EXPORTS = [
     "cis_wall_heat_flux", "cis_debug_stage", "cis_profile_enable", "cis_profile_read", "cis_state_set_bc",
     "cis_steady_residual", "cis_residual_vjp", "cis_adjoint_required_bytes", "cis_adjoint_solve", "cis_wall_loads",
     "cis_wall_coefficients_of_loads", "cis_wall_coefficients", "cis_iterate_noalloc", "cis_limiter_freeze",
+    "cis_mesh_create_cells",
 ]
 STAGE_NAMES = ["recon", "face", "macro", "residual", "micro", "update"]
 
@@ -56,7 +57,7 @@ class Bc(C.Structure):
 
 
 class MeshInfo(C.Structure):
-    _fields_ = [(k, C.c_int64) for k in ("n_cells", "n_faces", "n_interior", "n_boundary", "n_colors")]
+    _fields_ = [(k, C.c_int64) for k in ("n_cells", "n_faces", "n_interior", "n_boundary", "n_colors", "max_faces")]
 
 
 class BufferSizes(C.Structure):
@@ -120,6 +121,9 @@ def load(allow_build: bool = True):
     lib.cis_mesh_create.restype = st
     lib.cis_mesh_create.argtypes = [d, C.c_int64, i32, C.c_int64, i32, i32, C.c_int64, i64, C.c_int64,
                                     C.POINTER(P)]
+    lib.cis_mesh_create_cells.restype = st
+    lib.cis_mesh_create_cells.argtypes = [d, C.c_int64, i32, i32, C.c_int64, i32, i32, C.c_int64, i64, C.c_int64,
+                                          C.POINTER(P)]
     lib.cis_mesh_info.restype = st
     lib.cis_mesh_info.argtypes = [P, C.POINTER(MeshInfo)]
     lib.cis_mesh_destroy.restype = None
@@ -146,7 +150,7 @@ def load(allow_build: bool = True):
     lib.cis_iterate.restype = st
     lib.cis_iterate.argtypes = [P, C.c_int32, d]
     lib.cis_limiter_freeze.restype = st
-    lib.cis_limiter_freeze.argtypes = [P, P]
+    lib.cis_limiter_freeze.argtypes = [P, P, C.c_int32]
     lib.cis_iterate_noalloc.restype = st
     lib.cis_iterate_noalloc.argtypes = [P, C.c_int32, d]
     lib.cis_residual.restype = st
@@ -217,16 +221,25 @@ class Mesh:
         lib = load()
         self.lib = lib
         xyz = np.ascontiguousarray(mesh["xyz"], dtype=np.float64)
-        tets = np.ascontiguousarray(mesh["tets"], dtype=np.int32)
-        btri = np.ascontiguousarray(mesh["btri"], dtype=np.int32)
         btag = np.ascontiguousarray(mesh["btag"], dtype=np.int32)
         off = np.ascontiguousarray(mesh["color_offsets"], dtype=np.int64)
         self.color_offsets = off
         h = C.c_void_p()
         ip = C.POINTER(C.c_int32)
-        _check(lib.cis_mesh_create(_dp(xyz), len(xyz), tets.ctypes.data_as(ip), len(tets), btri.ctypes.data_as(ip),
-                                   btag.ctypes.data_as(ip), len(btri), off.ctypes.data_as(C.POINTER(C.c_int64)),
-                                   len(off) - 1, C.byref(h)))
+        if "cells" in mesh:
+            cells = np.ascontiguousarray(mesh["cells"], dtype=np.int32)
+            kinds = np.ascontiguousarray(mesh["kinds"], dtype=np.int32)
+            bface = np.ascontiguousarray(mesh["bface"], dtype=np.int32)
+            _check(lib.cis_mesh_create_cells(_dp(xyz), len(xyz), cells.ctypes.data_as(ip), kinds.ctypes.data_as(ip),
+                                             len(cells), bface.ctypes.data_as(ip), btag.ctypes.data_as(ip),
+                                             len(bface), off.ctypes.data_as(C.POINTER(C.c_int64)), len(off) - 1,
+                                             C.byref(h)))
+        else:
+            tets = np.ascontiguousarray(mesh["tets"], dtype=np.int32)
+            btri = np.ascontiguousarray(mesh["btri"], dtype=np.int32)
+            _check(lib.cis_mesh_create(_dp(xyz), len(xyz), tets.ctypes.data_as(ip), len(tets),
+                                       btri.ctypes.data_as(ip), btag.ctypes.data_as(ip), len(btri),
+                                       off.ctypes.data_as(C.POINTER(C.c_int64)), len(off) - 1, C.byref(h)))
         self.h = h
         info = MeshInfo()
         _check(lib.cis_mesh_info(h, C.byref(info)))
@@ -289,7 +302,9 @@ class Solver:
             self.faceG, self.faceR = mk(self.nf), mk(self.nf)
             self.W = torch.zeros(self.nc, 6, dtype=torch.float64, device=self.device)
             self.q = torch.zeros(self.nc, 6, dtype=torch.float64, device=self.device)
-            self.upwind = torch.empty(self.nc, self.nv, dtype=torch.uint8, device=self.device)
+            # upwind codes: one byte per (cell, velocity) for 4 face slots, two (int16 storage of uint16) for 6
+            self.upwind = torch.empty(self.nc, self.nv, dtype=torch.uint8 if self.mesh.info.max_faces == 4
+                                      else torch.int16, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         bufs = DeviceBuffers(*(t.data_ptr() for t in (self.G, self.R, self.dG, self.dR, self.resG, self.resR,
                                                       self.faceG, self.faceR, self.W, self.q, self.upwind)))
@@ -314,19 +329,24 @@ class Solver:
         self._num_s = numerics_struct(self.num)
         _check(self.lib.cis_state_set_numerics(self.h, C.byref(self._num_s)))
 
-    def freeze_limiter(self):
-        """Store the limiter values of the current state (cis_limiter_freeze) and switch to limiter 3, which
-        reconstructs with them.  Returns the [2, nc, nv] tensor of values (G then R)."""
+    def freeze_limiter(self, values=None, limiter: int = 3):
+        """Store limiter values (cis_limiter_freeze) and switch to `limiter` (3: reconstruct with them; 4: also lower
+        them where the computed limiter is smaller).  values: None takes those of the current state; otherwise a
+        [2, nc, nv] array (G then R), e.g. of another state.  Returns the device tensor of stored values."""
         t = self.torch
-        self.L_frozen = t.empty(2, self.nc, self.nv, dtype=self.dtype, device=self.device)
-        _check(self.lib.cis_limiter_freeze(self.h, C.c_void_p(self.L_frozen.data_ptr())))
-        self.set_numerics(limiter=3)
+        if values is None:
+            self.L_frozen = t.empty(2, self.nc, self.nv, dtype=self.dtype, device=self.device)
+        else:
+            self.L_frozen = t.as_tensor(values).to(device=self.device, dtype=self.dtype).reshape(
+                2, self.nc, self.nv).contiguous()
+        _check(self.lib.cis_limiter_freeze(self.h, C.c_void_p(self.L_frozen.data_ptr()), 1 if values is None else 0))
+        self.set_numerics(limiter=limiter)
         return self.L_frozen
 
     def unfreeze_limiter(self, limiter: int = 1):
         """Back to a computed limiter (1 by default) and detach the frozen values."""
         self.set_numerics(limiter=limiter)
-        _check(self.lib.cis_limiter_freeze(self.h, None))
+        _check(self.lib.cis_limiter_freeze(self.h, None, 0))
         self.L_frozen = None
 
     def init_equilibrium(self, W0):

@@ -17,7 +17,8 @@ import numpy as np
 from . import dvs as _dvs
 from . import mesh as _mesh
 
-__all__ = ["gas_n2", "numerics_default", "mu_ref_from_kn", "cavity_case", "sphere_case", "capsule_case",
+__all__ = ["gas_n2", "numerics_default", "mu_ref_from_kn", "cavity_case", "sphere_case", "sphere_hex_case",
+           "capsule_case",
            "freestream_box_case", "open_box_case", "small_sphere_case", "rest_state"]
 
 WALL = 1
@@ -111,13 +112,13 @@ def open_box_case(seed: int = 0, n: int = 3, U=(0.3, 0.0, 0.0), T_wall: float = 
 
 
 def _external_case(name, body, n_ang, n_rad, r_far, first_layer, mach, kn, z_rot, tw, nv_target,
-                   seed, n_iter, h_outer=None, refine_scale=1.0, smooth_passes=0, jitter=0.1):
+                   seed, n_iter, h_outer=None, refine_scale=1.0, smooth_passes=0, jitter=0.1, cells="tet"):
     gamma = 1.4
     R = 0.5
     uinf = mach * math.sqrt(gamma * R * 1.0)
     U = np.array([uinf, 0.0, 0.0])
     m = _mesh.shell_mesh(body, n_ang=n_ang, n_rad=n_rad, r_far=r_far, first_layer=first_layer, seed=seed,
-                         smooth_passes=smooth_passes, jitter=jitter)
+                         smooth_passes=smooth_passes, jitter=jitter, cells=cells)
     u, w = _dvs.paper_unstructured_dvs(U, 1.0, tw, mach, 5.0, h_outer=h_outer, target=nv_target,
                                        refine_scale=refine_scale)
     gas = gas_n2(kn, z_rot)
@@ -134,6 +135,13 @@ def sphere_case(seed: int = 0, n_ang: int = 10, n_rad: int = 7, nv_target: int =
     """Ma 5 flow over a unit-diameter sphere at Kn = 0.1, Tw/T_inf = 3 (~50k tets x ~4k velocities)."""
     return _external_case(f"sphere_ma5_kn0.1_{n_ang}x{n_rad}_seed{seed}", _mesh.sphere_body(0.5), n_ang, n_rad,
                           3.0, 0.03, 5.0, 0.1, 3.0, 3.0, nv_target, seed, n_iter)
+
+
+def sphere_hex_case(seed: int = 0, n_ang: int = 24, n_rad: int = 14, nv_target: int = 4096, n_iter: int = 200):
+    """The sphere case on the hexahedral O-grid itself (the paper's sphere mesh is hexahedral, Sec. 4.2):
+    6 x 24 x 24 x 14 = 48 384 hexahedra graded from 0.03 at the wall, the same DVS and flow."""
+    return _external_case(f"sphere_hex_ma5_kn0.1_{n_ang}x{n_rad}_seed{seed}", _mesh.sphere_body(0.5), n_ang, n_rad,
+                          3.0, 0.03, 5.0, 0.1, 3.0, 3.0, nv_target, seed, n_iter, cells="hex")
 
 
 def small_sphere_case(seed: int = 0, n_ang: int = 3, n_rad: int = 3, h_outer: float = 2.2, refine_scale: float = 2.0,

@@ -576,8 +576,9 @@ def _cubed_sphere_dirs(n: int):
 
 
 def shell_mesh(body, n_ang: int, n_rad: int, r_far: float, first_layer: float, seed: int = 0,
-               jitter: float = 0.1, smooth_passes: int = 0):
-    """Graded tetrahedral shell between a star-shaped body and a far-field sphere.
+               jitter: float = 0.1, smooth_passes: int = 0, cells: str = "tet"):
+    """Graded tetrahedral (or, with cells="hex", hexahedral) shell between a star-shaped body and a far-field
+    sphere.
 
     Nodes sit on rays of an equiangular cubed sphere; along each ray the layers
     grow geometrically from ``first_layer`` at the wall to the far-field radius.
@@ -587,6 +588,8 @@ def shell_mesh(body, n_ang: int, n_rad: int, r_far: float, first_layer: float, s
     U(-j, j)^3 jitter scaled by the local radial spacing; a draw that folds the mesh
     (two tets on one side of their shared face) or makes a volume non-positive is redrawn.
     ``smooth_passes`` rounds sharp body edges by smoothing the wall radius over the ray grid.
+    cells="hex" keeps the hexahedra of the O-grid (the paper's sphere mesh is hexahedral, Sec. 4.2), with the
+    same jitter, as a mixed-cell mesh dict.
     Tags: 1 = wall, 2 = far field.
     """
     inside, centre = body
@@ -661,6 +664,26 @@ def shell_mesh(body, n_ang: int, n_rad: int, r_far: float, first_layer: float, s
                                   nid(d00, k + 1), nid(d10, k + 1), nid(d11, k + 1), nid(d01, k + 1)])
     hexes = np.array(hexes, dtype=np.int64)
     quads = np.array([[0, 1, 2, 3], [4, 5, 6, 7], [0, 1, 5, 4], [1, 2, 6, 5], [2, 3, 7, 6], [3, 0, 4, 7]])
+
+    if cells == "hex":
+        kinds = np.full(len(hexes), 8, dtype=np.int64)
+        for _attempt in range(50):
+            xj = xyz.copy()
+            xj[interior] += rng.uniform(-jitter, jitter, size=(int(interior.sum()), 3)) * dr[interior, None]
+            if _cells_valid(xj, hexes, kinds):
+                break
+        else:
+            raise RuntimeError("shell mesh: folded hexahedra after 50 jitter draws")
+        cells_c, kinds_c, offsets = color_major_cells(xj, hexes, kinds)
+        _, bcyc = match_faces_cells(cells_c, kinds_c)
+        bl = layer[bcyc]
+        tags = np.zeros(len(bcyc), dtype=np.int64)
+        tags[np.all(bl == 0, axis=1)] = 1
+        tags[np.all(bl == n_rad, axis=1)] = 2
+        if np.any(tags == 0):
+            raise RuntimeError("shell mesh: unclassified boundary face")
+        return dict(xyz=xj, cells=cells_c, kinds=kinds_c, bface=bcyc, btag=tags, color_offsets=offsets,
+                    wall_radius=rb, centre=centre)
 
     for _attempt in range(50):
         xj = xyz.copy()

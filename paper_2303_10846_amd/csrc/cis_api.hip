@@ -45,22 +45,94 @@ cis_status fail(cis_status st, const std::string& msg) {
     if (e_ != hipSuccess) return fail(CIS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-struct TriKey {
-  int32_t a, b, c;
-  bool operator==(const TriKey& o) const { return a == o.a && b == o.b && c == o.c; }
+// A face identified by its node ids, sorted (a triangle has d = -1)
+struct FaceId {
+  int32_t a, b, c, d;
+  bool operator==(const FaceId& o) const { return a == o.a && b == o.b && c == o.c && d == o.d; }
 };
-struct TriHash {
-  size_t operator()(const TriKey& k) const {
+struct FaceIdHash {
+  size_t operator()(const FaceId& k) const {
     uint64_t h = (uint64_t)(uint32_t)k.a * 0x9E3779B97F4A7C15ull;
     h ^= (uint64_t)(uint32_t)k.b + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
     h ^= (uint64_t)(uint32_t)k.c + 0x94D049BB133111EBull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)(uint32_t)k.d + 0xD6E8FEB86659FD93ull + (h << 6) + (h >> 2);
     return (size_t)h;
   }
 };
-TriKey make_key(int32_t x, int32_t y, int32_t z) {
-  int32_t v[3] = {x, y, z};
-  std::sort(v, v + 3);
-  return {v[0], v[1], v[2]};
+FaceId face_id(const int32_t* v, int n) {
+  int32_t t[4] = {v[0], v[1], v[2], n == 4 ? v[3] : -1};
+  std::sort(t, t + n);
+  return {t[0], t[1], t[2], t[3]};
+}
+
+// Local faces of the cell kinds, by node count (4 tetrahedron: the face opposite local vertex a; 5 pyramid:
+// base quad 0-3 and apex 4; 6 prism: triangles 0-2 and 3-5; 8 hexahedron: quads 0-3 and 4-7), quads cyclic.
+// Slot a of a cell is its a-th local face.
+struct CellShape {
+  int faces;
+  int n[6];
+  int v[6][4];
+};
+const CellShape* cell_shape(int kind) {
+  static const CellShape shapes[4] = {
+      {4, {3, 3, 3, 3}, {{1, 2, 3}, {2, 3, 0}, {3, 0, 1}, {0, 1, 2}}},
+      {5, {4, 3, 3, 3, 3}, {{0, 1, 2, 3}, {0, 1, 4}, {1, 2, 4}, {2, 3, 4}, {3, 0, 4}}},
+      {5, {3, 3, 4, 4, 4}, {{0, 1, 2}, {3, 4, 5}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}}},
+      {6, {4, 4, 4, 4, 4, 4}, {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}}}};
+  switch (kind) {
+    case 4: return &shapes[0];
+    case 5: return &shapes[1];
+    case 6: return &shapes[2];
+    case 8: return &shapes[3];
+  }
+  return nullptr;
+}
+
+inline void cross(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Vector area S and centroid c of a polygon face (3 or 4 nodes, cyclic).  Fanned about the node average m: S is
+// the sum of the fan triangles' vector areas (for a quad, half the cross product of its diagonals: a closed cell
+// has sum S = 0 exactly), and c the mean of their centroids weighted by their areas along S.
+void polygon_face(const double* const* p, int n, double* S, double* c) {
+  if (n == 3) {
+    double e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) {
+      e1[d] = p[1][d] - p[0][d];
+      e2[d] = p[2][d] - p[0][d];
+      c[d] = (p[0][d] + p[1][d] + p[2][d]) / 3.0;
+    }
+    cross(e1, e2, S);
+    for (int d = 0; d < 3; ++d) S[d] *= 0.5;
+    return;
+  }
+  double m[3], tS[4][3];
+  for (int d = 0; d < 3; ++d) m[d] = 0.25 * (p[0][d] + p[1][d] + p[2][d] + p[3][d]);
+  for (int d = 0; d < 3; ++d) S[d] = 0.0;
+  for (int t = 0; t < 4; ++t) {
+    double e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) {
+      e1[d] = p[(t + 1) % 4][d] - p[t][d];
+      e2[d] = m[d] - p[t][d];
+    }
+    cross(e1, e2, tS[t]);
+    for (int d = 0; d < 3; ++d) {
+      tS[t][d] *= 0.5;
+      S[d] += tS[t][d];
+    }
+  }
+  const double SS = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
+  double wsum = 0.0;
+  for (int d = 0; d < 3; ++d) c[d] = 0.0;
+  for (int t = 0; t < 4; ++t) {
+    const double wt = (tS[t][0] * S[0] + tS[t][1] * S[1] + tS[t][2] * S[2]) / SS;  // area fraction along S
+    wsum += wt;
+    for (int d = 0; d < 3; ++d) c[d] += wt * (p[t][d] + p[(t + 1) % 4][d] + m[d]) / 3.0;
+  }
+  for (int d = 0; d < 3; ++d) c[d] /= wsum;
 }
 
 template <class T> cis_status dmalloc(T** p, size_t n) {
@@ -86,6 +158,7 @@ __global__ void k_zero_i32(int32_t* p, int n) {
 
 struct cis_mesh {
   int64_t nc = 0, nf = 0, n_int = 0, n_b = 0, n_colors = 0;
+  int mf = 4;  // face slots per cell: 4 when every cell is a tetrahedron, else kMaxFaces
   std::vector<int64_t> color_off;
   std::vector<int32_t> spatial;  // cells in Morton order of their centroids (traversal order off the sweeps)
   std::vector<int32_t> cell_nb, cell_face, face_cell, face_tag;
@@ -150,7 +223,7 @@ cis_status check_numerics(const cis_numerics* n) {
   if (!n) return fail(CIS_E_INVALID_ARG, "numerics is NULL");
   if (!(n->cfl > 0.0) || !(n->inv_dt >= 0.0) || !(n->cfl_imp >= 0.0) || !(n->lim_K >= 0.0) || !(n->snap >= 0.0) ||
       n->n_macro < 0 || n->n_micro < 0 || n->n_macro > 100000 || n->n_micro > 100000 || n->limiter < 0 ||
-      n->limiter > 3)
+      n->limiter > 4)
     return fail(CIS_E_INVALID_ARG, "numerics out of range");
   return CIS_OK;
 }
@@ -354,42 +427,121 @@ cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* te
   *out = nullptr;
   if (!xyz || !tet || n_nodes <= 0 || n_cells <= 0 || n_cells > INT32_MAX || n_b < 0 || (n_b > 0 && (!btri || !btag)))
     return fail(CIS_E_INVALID_ARG, "bad mesh arrays");
+  std::vector<int32_t> cells(8 * (size_t)n_cells, -1), kinds((size_t)n_cells, 4), bface(4 * (size_t)n_b, -1);
+  for (int64_t i = 0; i < n_cells; ++i)
+    for (int a = 0; a < 4; ++a) cells[8 * i + a] = tet[4 * i + a];
+  for (int64_t b = 0; b < n_b; ++b)
+    for (int a = 0; a < 3; ++a) bface[4 * b + a] = btri[3 * b + a];
+  return cis_mesh_create_cells(xyz, n_nodes, cells.data(), kinds.data(), n_cells, bface.data(), btag, n_b,
+                               color_offsets, n_colors, out);
+}
+
+cis_status cis_mesh_create_cells(const double* xyz, int64_t n_nodes, const int32_t* cells, const int32_t* kinds,
+                                 int64_t n_cells, const int32_t* bface, const int32_t* btag, int64_t n_b,
+                                 const int64_t* color_offsets, int64_t n_colors, cis_mesh** out) {
+  if (!out) return fail(CIS_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!xyz || !cells || !kinds || n_nodes <= 0 || n_cells <= 0 || n_cells > INT32_MAX || n_b < 0 ||
+      (n_b > 0 && (!bface || !btag)))
+    return fail(CIS_E_INVALID_ARG, "bad mesh arrays");
   if (!color_offsets || n_colors <= 0) return fail(CIS_E_INVALID_ARG, "colour offsets are required");
   if (color_offsets[0] != 0 || color_offsets[n_colors] != n_cells)
     return fail(CIS_E_INVALID_ARG, "colour offsets must run from 0 to n_cells");
   for (int64_t c = 0; c < n_colors; ++c)
     if (color_offsets[c + 1] < color_offsets[c]) return fail(CIS_E_INVALID_ARG, "colour offsets must not decrease");
   if (!finite_all(xyz, 3 * (size_t)n_nodes)) return fail(CIS_E_MESH, "non-finite node coordinate");
-  for (int64_t x = 0; x < 4 * n_cells; ++x)
-    if (tet[x] < 0 || tet[x] >= n_nodes) return fail(CIS_E_MESH, "tet node id out of range");
+  int mf = 4;
+  for (int64_t i = 0; i < n_cells; ++i) {
+    const CellShape* sh = cell_shape(kinds[i]);
+    if (!sh) return fail(CIS_E_INVALID_ARG, "cell kind must be 4, 5, 6 or 8 (nodes)");
+    if (sh->faces > 4) mf = kMaxFaces;
+    for (int a = 0; a < kinds[i]; ++a)
+      if (cells[8 * i + a] < 0 || cells[8 * i + a] >= n_nodes) return fail(CIS_E_MESH, "cell node id out of range");
+  }
+  for (int64_t b = 0; b < n_b; ++b) {
+    const int n = bface[4 * b + 3] < 0 ? 3 : 4;
+    for (int a = 0; a < n; ++a)
+      if (bface[4 * b + a] < 0 || bface[4 * b + a] >= n_nodes) return fail(CIS_E_MESH, "boundary node id out of range");
+  }
 
   auto* m = new cis_mesh();
   m->nc = n_cells;
+  m->mf = mf;
   m->n_colors = n_colors;
   m->color_off.assign(color_offsets, color_offsets + n_colors + 1);
-  m->cell_face.assign(4 * n_cells, -1);
-  m->cell_nb.assign(4 * n_cells, -1);
+  m->cell_face.assign((size_t)mf * n_cells, -1);
+  m->cell_nb.assign((size_t)mf * n_cells, kNoFace);
   m->V.resize(n_cells);
   m->xc.resize(3 * n_cells);
-  // cells
+  // cells: a tetrahedron directly (|det|/6, vertex mean); another kind as the tetrahedra from its node average
+  // to the triangles of its faces (quads fanned about their node average)
   for (int64_t i = 0; i < n_cells; ++i) {
-    const double* p0 = xyz + 3 * tet[4 * i];
-    const double* p1 = xyz + 3 * tet[4 * i + 1];
-    const double* p2 = xyz + 3 * tet[4 * i + 2];
-    const double* p3 = xyz + 3 * tet[4 * i + 3];
-    double a[3], b[3], c[3];
-    for (int d = 0; d < 3; ++d) {
-      a[d] = p1[d] - p0[d];
-      b[d] = p2[d] - p0[d];
-      c[d] = p3[d] - p0[d];
+    const int32_t* cn = cells + 8 * i;
+    if (kinds[i] == 4) {
+      const double* p0 = xyz + 3 * cn[0];
+      const double* p1 = xyz + 3 * cn[1];
+      const double* p2 = xyz + 3 * cn[2];
+      const double* p3 = xyz + 3 * cn[3];
+      double a[3], b[3], c[3];
+      for (int d = 0; d < 3; ++d) {
+        a[d] = p1[d] - p0[d];
+        b[d] = p2[d] - p0[d];
+        c[d] = p3[d] - p0[d];
+      }
+      double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
+      m->V[i] = std::fabs(det) / 6.0;
+      for (int d = 0; d < 3; ++d) m->xc[3 * i + d] = 0.25 * (p0[d] + p1[d] + p2[d] + p3[d]);
+    } else {
+      const CellShape* sh = cell_shape(kinds[i]);
+      double ctr[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < kinds[i]; ++a)
+        for (int d = 0; d < 3; ++d) ctr[d] += xyz[3 * cn[a] + d];
+      for (int d = 0; d < 3; ++d) ctr[d] /= kinds[i];
+      double vol = 0.0, mom[3] = {0.0, 0.0, 0.0};
+      bool bad = false;
+      for (int a = 0; a < sh->faces && !bad; ++a) {
+        const int n = sh->n[a];
+        const double* p[4];
+        double fm[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < n; ++q) {
+          p[q] = xyz + 3 * cn[sh->v[a][q]];
+          for (int d = 0; d < 3; ++d) fm[d] += p[q][d] / n;
+        }
+        double v6[4], cq[4][3], tot = 0.0;
+        const int nt = n == 3 ? 1 : 4;
+        for (int t = 0; t < nt; ++t) {
+          const double* x0 = n == 3 ? p[0] : p[t];
+          const double* x1 = n == 3 ? p[1] : p[(t + 1) % 4];
+          const double* x2 = n == 3 ? p[2] : fm;
+          double e1[3], e2[3], e3[3], cr[3];
+          for (int d = 0; d < 3; ++d) {
+            e1[d] = x1[d] - x0[d];
+            e2[d] = x2[d] - x0[d];
+            e3[d] = ctr[d] - x0[d];
+            cq[t][d] = 0.25 * (x0[d] + x1[d] + x2[d] + ctr[d]);
+          }
+          cross(e1, e2, cr);
+          v6[t] = cr[0] * e3[0] + cr[1] * e3[1] + cr[2] * e3[2];  // 6 x signed volume
+          tot += v6[t];
+        }
+        for (int t = 0; t < nt; ++t) {
+          const double v = (tot < 0.0 ? -v6[t] : v6[t]) / 6.0;
+          if (!(v > 0.0)) bad = true;
+          vol += v;
+          for (int d = 0; d < 3; ++d) mom[d] += v * cq[t][d];
+        }
+      }
+      if (bad) {
+        delete m;
+        return fail(CIS_E_MESH, "cell " + std::to_string(i) + " is folded");
+      }
+      m->V[i] = vol;
+      for (int d = 0; d < 3; ++d) m->xc[3 * i + d] = mom[d] / vol;
     }
-    double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
-    m->V[i] = std::fabs(det) / 6.0;
     if (!(m->V[i] > 0.0)) {
       delete m;
       return fail(CIS_E_MESH, "cell " + std::to_string(i) + " has zero volume");
     }
-    for (int d = 0; d < 3; ++d) m->xc[3 * i + d] = 0.25 * (p0[d] + p1[d] + p2[d] + p3[d]);
   }
   // Morton order of the centroids: kernels that read face neighbours walk the cells in this order, so that
   // neighbouring rows are read close together in time (the colour-major numbering puts every face neighbour
@@ -415,23 +567,26 @@ cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* te
     m->spatial.resize((size_t)n_cells);
     for (int64_t i = 0; i < n_cells; ++i) m->spatial[(size_t)i] = key[(size_t)i].second;
   }
-  // faces (face a of a tet is opposite its local vertex a)
-  std::unordered_map<TriKey, int64_t, TriHash> seen;
+  // faces: slot a of a cell is its a-th local face
+  std::unordered_map<FaceId, int64_t, FaceIdHash> seen;
   seen.reserve((size_t)(3 * n_cells));
-  std::vector<TriKey> fkey;
-  std::vector<int32_t> fslot;  // local slot of the first cell
+  std::vector<FaceId> fkey;
+  std::vector<std::array<int32_t, 4>> fcyc;  // the face's nodes in the first cell's cyclic order
   for (int64_t i = 0; i < n_cells; ++i) {
-    const int32_t* t = tet + 4 * i;
-    for (int a = 0; a < 4; ++a) {
-      TriKey key = make_key(t[(a + 1) % 4], t[(a + 2) % 4], t[(a + 3) % 4]);
+    const CellShape* sh = cell_shape(kinds[i]);
+    for (int a = 0; a < sh->faces; ++a) {
+      std::array<int32_t, 4> v = {-1, -1, -1, -1};
+      for (int q = 0; q < sh->n[a]; ++q) v[q] = cells[8 * i + sh->v[a][q]];
+      FaceId key = face_id(v.data(), sh->n[a]);
       auto it = seen.find(key);
       if (it == seen.end()) {
         int64_t f = (int64_t)fkey.size();
         seen.emplace(key, f);
         fkey.push_back(key);
+        fcyc.push_back(v);
         m->face_cell.push_back((int32_t)i);
         m->face_cell.push_back(-1);
-        m->cell_face[4 * i + a] = (int32_t)f;
+        m->cell_face[(size_t)mf * i + a] = (int32_t)f;
       } else {
         int64_t f = it->second;
         if (m->face_cell[2 * f + 1] != -1 || m->face_cell[2 * f] == (int32_t)i) {
@@ -439,14 +594,14 @@ cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* te
           return fail(CIS_E_MESH, "non-manifold face");
         }
         m->face_cell[2 * f + 1] = (int32_t)i;
-        m->cell_face[4 * i + a] = (int32_t)f;
+        m->cell_face[(size_t)mf * i + a] = (int32_t)f;
       }
     }
   }
   m->nf = (int64_t)fkey.size();
   m->face_tag.assign(m->nf, 0);
-  std::unordered_map<TriKey, int32_t, TriHash> tags;
-  for (int64_t b = 0; b < n_b; ++b) tags[make_key(btri[3 * b], btri[3 * b + 1], btri[3 * b + 2])] = btag[b];
+  std::unordered_map<FaceId, int32_t, FaceIdHash> tags;
+  for (int64_t b = 0; b < n_b; ++b) tags[face_id(bface + 4 * b, bface[4 * b + 3] < 0 ? 3 : 4)] = btag[b];
   m->n_int = 0;
   m->n_b = 0;
   for (int64_t f = 0; f < m->nf; ++f) {
@@ -467,20 +622,29 @@ cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* te
   m->fA.resize(m->nf);
   m->fn.resize(3 * m->nf);
   for (int64_t f = 0; f < m->nf; ++f) {
-    const double* a = xyz + 3 * fkey[f].a;
-    const double* b = xyz + 3 * fkey[f].b;
-    const double* c = xyz + 3 * fkey[f].c;
-    double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
-    double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-    double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    double n[3], len;
+    if (fkey[f].d < 0) {
+      // a triangle, from its sorted node ids
+      const double* a = xyz + 3 * fkey[f].a;
+      const double* b = xyz + 3 * fkey[f].b;
+      const double* c = xyz + 3 * fkey[f].c;
+      double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+      cross(e1, e2, n);
+      len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      for (int d = 0; d < 3; ++d) m->xf[3 * f + d] = (a[d] + b[d] + c[d]) / 3.0;
+    } else {
+      const double* p[4];
+      for (int q = 0; q < 4; ++q) p[q] = xyz + 3 * fcyc[f][q];
+      double S[3];
+      polygon_face(p, 4, S, &m->xf[3 * f]);
+      for (int d = 0; d < 3; ++d) n[d] = 2.0 * S[d];
+      len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    }
     if (!(len > 0.0)) {
       delete m;
       return fail(CIS_E_MESH, "degenerate face");
     }
-    for (int d = 0; d < 3; ++d) {
-      m->xf[3 * f + d] = (a[d] + b[d] + c[d]) / 3.0;
-      n[d] /= len;
-    }
+    for (int d = 0; d < 3; ++d) n[d] /= len;
     m->fA[f] = 0.5 * len;
     int32_t o = m->face_cell[2 * f];
     double dot = 0.0;
@@ -501,10 +665,11 @@ cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* te
   m->h.resize(n_cells);
   for (int64_t i = 0; i < n_cells; ++i) {
     double acc[3] = {0, 0, 0}, asum = 0.0;
-    for (int a = 0; a < 4; ++a) {
-      int64_t f = m->cell_face[4 * i + a];
+    for (int a = 0; a < mf; ++a) {
+      int64_t f = m->cell_face[(size_t)mf * i + a];
+      if (f < 0) continue;
       bool own = m->face_cell[2 * f] == (int32_t)i;
-      m->cell_nb[4 * i + a] = own ? m->face_cell[2 * f + 1] : m->face_cell[2 * f];
+      m->cell_nb[(size_t)mf * i + a] = own ? m->face_cell[2 * f + 1] : m->face_cell[2 * f];
       double sg = own ? 1.0 : -1.0;
       for (int d = 0; d < 3; ++d) acc[d] += sg * m->fA[f] * m->fn[3 * f + d];
       asum += m->fA[f];
@@ -536,6 +701,7 @@ cis_status cis_mesh_info(const cis_mesh* m, cis_mesh_info_t* out) {
   out->n_interior = m->n_int;
   out->n_boundary = m->n_b;
   out->n_colors = m->n_colors;
+  out->max_faces = m->mf;
   return CIS_OK;
 }
 
@@ -571,7 +737,7 @@ cis_status cis_state_required_bytes(const cis_mesh* m, const cis_dvs* d, int32_t
   out->phi_bytes = m->nc * d->n * es;
   out->face_bytes = m->nf * d->n * es;
   out->cell6_bytes = m->nc * 6 * 8;
-  out->code_bytes = m->nc * d->n;
+  out->code_bytes = m->nc * d->n * (m->mf == 4 ? 1 : 2);
   out->total_bytes = 6 * out->phi_bytes + 2 * out->face_bytes + 2 * out->cell6_bytes + out->code_bytes;
   return CIS_OK;
 }
@@ -585,7 +751,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   if (precision != CIS_FP64 && precision != CIS_MIXED) return fail(CIS_E_INVALID_ARG, "unknown precision");
   cis_status st = check_numerics(num);
   if (st != CIS_OK) return st;
-  if (num->limiter == 3) return fail(CIS_E_INVALID_ARG, "limiter 3 needs frozen values: cis_limiter_freeze first");
+  if (num->limiter >= 3) return fail(CIS_E_INVALID_ARG, "limiters 3 and 4 need stored values: cis_limiter_freeze first");
   if (!buf->G || !buf->R || !buf->dG || !buf->dR || !buf->resG || !buf->resR || !buf->faceG || !buf->faceR || !buf->W ||
       !buf->q || !buf->upwind)
     return fail(CIS_E_INVALID_ARG, "a device buffer is NULL");
@@ -643,17 +809,21 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
       g[5] = 2.0 * std::sqrt(d2);
     }
   }
-  std::vector<double> cgeo(CG * nc, 0.0);
+  const int mf = m->mf;
+  const int cgw = mf == 4 ? Lay<4>::CG : Lay<kMaxFaces>::CG;
+  const int cgfw = mf == 4 ? Lay<4>::CGF : Lay<kMaxFaces>::CGF;
+  std::vector<double> cgeo((size_t)cgw * nc, 0.0);
   for (int64_t i = 0; i < nc; ++i) {
-    double* g = &cgeo[CG * i];
+    double* g = &cgeo[(size_t)cgw * i];
     g[0] = m->V[i];
     g[1] = 1.0 / m->V[i];
     g[2] = m->h[i];
     for (int d = 0; d < 3; ++d) g[4 + d] = m->xc[3 * i + d];
-    double M[9] = {0}, dvec[4][3];
-    for (int a = 0; a < 4; ++a) {
-      int64_t f = m->cell_face[4 * i + a];
-      int32_t nb = m->cell_nb[4 * i + a];
+    double M[9] = {0}, dvec[kMaxFaces][3];
+    for (int a = 0; a < mf; ++a) {
+      int64_t f = m->cell_face[(size_t)mf * i + a];
+      int32_t nb = m->cell_nb[(size_t)mf * i + a];
+      if (f < 0) continue;  // unused slot: zero geometry
       double sg = m->face_cell[2 * f] == (int32_t)i ? 1.0 : -1.0;
       double* sl = g + CG_FACE + CG_SLOT * a;
       sl[0] = sg;
@@ -677,18 +847,18 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
     double I[9] = {c00, M[2] * M[7] - M[1] * M[8], M[1] * M[5] - M[2] * M[4],
                    c01, M[0] * M[8] - M[2] * M[6], M[2] * M[3] - M[0] * M[5],
                    c02, M[1] * M[6] - M[0] * M[7], M[0] * M[4] - M[1] * M[3]};
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < mf; ++a) {
       double* sl = g + CG_FACE + CG_SLOT * a;
-      bool interior = m->cell_nb[4 * i + a] >= 0;
+      bool interior = m->cell_nb[(size_t)mf * i + a] >= 0;
       for (int r = 0; r < 3; ++r)
         sl[9 + r] = interior ? (I[3 * r] * dvec[a][0] + I[3 * r + 1] * dvec[a][1] + I[3 * r + 2] * dvec[a][2]) / det : 0.0;
     }
   }
-  std::vector<float> cgeof(CGF * nc, 0.0f);
+  std::vector<float> cgeof((size_t)cgfw * nc, 0.0f);
   for (int64_t i = 0; i < nc; ++i)
-    for (int a = 0; a < 4; ++a) {
-      const double* sl = &cgeo[CG * i + CG_FACE + CG_SLOT * a];
-      float* o = &cgeof[CGF * i + 7 * a];
+    for (int a = 0; a < mf; ++a) {
+      const double* sl = &cgeo[(size_t)cgw * i + CG_FACE + CG_SLOT * a];
+      float* o = &cgeof[(size_t)cgfw * i + 7 * a];
       for (int q = 0; q < 3; ++q) {
         o[q] = (float)sl[5 + q];
         o[4 + q] = (float)sl[9 + q];
@@ -734,8 +904,8 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   Work& w = s->work;
   chk(own_alloc(s, &w.face_mac, 6 * nf));
   chk(own_alloc(s, &w.cell_prim, 8 * nc));
-  chk(own_alloc(s, &w.rcf, 4 * nc));
-  chk(own_alloc(s, &w.G0, 24 * nc));
+  chk(own_alloc(s, &w.rcf, (size_t)mf * nc));
+  chk(own_alloc(s, &w.G0, (size_t)6 * mf * nc));
   chk(own_alloc(s, &w.mres, 6 * nc));
   chk(own_alloc(s, &w.mD, 2 * nc));
   chk(own_alloc(s, &w.Fmac, 6 * nc));
@@ -761,6 +931,7 @@ cis_status cis_state_create(const cis_mesh* m, const cis_dvs* dv, const cis_gas*
   d.nc = nc;
   d.nf = nf;
   d.nv = nv;
+  d.mf = mf;
   d.cell_nb = s->d_cell_nb;
   d.spatial = s->d_spatial;
   d.cell_face = s->d_cell_face;
@@ -793,8 +964,8 @@ cis_status cis_state_set_numerics(cis_state* s, const cis_numerics* num) {
   cis_status st = check_numerics(num);
   if (st != CIS_OK) return st;
   if (num->cfl != s->num.cfl) return fail(CIS_E_UNSUPPORTED, "cfl (face step s_ij) is fixed at state creation");
-  if (num->limiter == 3 && !s->dev.lim_frozen)
-    return fail(CIS_E_INVALID_ARG, "limiter 3 needs frozen values: cis_limiter_freeze first");
+  if (num->limiter >= 3 && !s->dev.lim_frozen)
+    return fail(CIS_E_INVALID_ARG, "limiters 3 and 4 need stored values: cis_limiter_freeze first");
   const bool recode = num->snap != s->num.snap;
   s->num = *num;
   fill_dev_numerics(s);
@@ -812,11 +983,15 @@ void cis_state_destroy(cis_state* s) {
   delete s;
 }
 
-cis_status cis_limiter_freeze(cis_state* s, void* L) {
+cis_status cis_limiter_freeze(cis_state* s, void* L, int32_t compute) {
   if (!s) return fail(CIS_E_INVALID_ARG, "state is NULL");
   if (!L) {
-    if (s->num.limiter == 3) return fail(CIS_E_INVALID_ARG, "limiter 3 is in use: set another limiter first");
+    if (s->num.limiter >= 3) return fail(CIS_E_INVALID_ARG, "stored limiter values are in use: set limiter 0-2 first");
     s->dev.lim_frozen = nullptr;
+    return CIS_OK;
+  }
+  if (!compute) {
+    s->dev.lim_frozen = L;
     return CIS_OK;
   }
   cis_status st = dispatch(s, [&](auto* tp) {
@@ -1143,7 +1318,9 @@ cis_status cis_state_set_bc(cis_state* s, const cis_bc* bc, int32_t n_bc) {
 cis_status cis_steady_residual(cis_state* s, int32_t wall_tag, double* rG, double* rR, double* rW, double* rq,
                                double* J) {
   if (!s || !rG || !rR || !rW || !rq) return fail(CIS_E_INVALID_ARG, "NULL argument");
+  if (s->num.limiter == 4) return fail(CIS_E_UNSUPPORTED, "limiter 4 updates its values: use limiter 3 (stored values)");
   if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the steady residual is FP64 only");
+  if (s->mesh->mf != 4) return fail(CIS_E_UNSUPPORTED, "the steady residual runs on tetrahedral meshes");
   launch_recon<double>(s->dev, s->buf, s->stream);
   launch_face<double>(s->dev, s->buf, s->work, s->stream);
   launch_residual<double>(s->dev, s->buf, s->work, rG, rR, 1, s->stream);
@@ -1163,6 +1340,8 @@ cis_status cis_residual_vjp(cis_state* s, const double* vG, const double* vR, co
   if (anyv && !allv) return fail(CIS_E_INVALID_ARG, "vG, vR, vW, vq must be all set or all NULL");
   if (!std::isfinite(cJ)) return fail(CIS_E_INVALID_ARG, "non-finite cJ");
   if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the VJP is FP64 only");
+  if (s->mesh->mf != 4) return fail(CIS_E_UNSUPPORTED, "the VJP runs on tetrahedral meshes");
+  if (s->num.limiter == 4) return fail(CIS_E_UNSUPPORTED, "limiter 4 updates its values: use limiter 3 (stored values)");
   AdjSlots sl;
   cis_status st = adj_slots(s, wall_tag, ff_tag, cJ != 0.0, &sl);
   if (st != CIS_OK) return st;
@@ -1187,6 +1366,8 @@ cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int
                              int64_t work_bytes, double* lam, double* dJdp, double* J, cis_adjoint_info* info) {
   if (!s || !work || !lam || !dJdp) return fail(CIS_E_INVALID_ARG, "NULL argument");
   if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the adjoint is FP64 only");
+  if (s->num.limiter == 4) return fail(CIS_E_UNSUPPORTED, "limiter 4 updates its values: use limiter 3 (stored values)");
+  if (s->mesh->mf != 4) return fail(CIS_E_UNSUPPORTED, "the adjoint runs on tetrahedral meshes");
   if (restart < 1 || restart > 1000 || max_iter < 0 || !(rtol > 0.0) || precond_pairs < 0 || precond_pairs > 64 ||
       macro_pairs < 0 || macro_pairs > 200)
     return fail(CIS_E_INVALID_ARG, "restart, max_iter, rtol, precond_pairs or macro_pairs out of range");

@@ -4,21 +4,35 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <vector>
 
 namespace cis {
 
+// Face slots per cell: NF = 4 when every cell is a tetrahedron (slot a = the face opposite local vertex a),
+// else kMaxFaces = 6 (slot a = the a-th local face of the cell's kind; a cell with fewer faces leaves the last
+// slots unused: neighbour kNoFace, face -1, geometry zero).
+constexpr int kMaxFaces = 6;
+constexpr int32_t kNoFace = -2;
+
 // Per-cell geometry record, FP64, CG doubles per cell:
 //   [0] V  [1] 1/V  [2] h = 6V/sum A  [3] unused  [4..6] centroid  [7] unused
-//   face slot a (a = 0..3, face opposite local vertex a) at 8 + 12a:
+//   face slot a at 8 + 12a:
 //   [0] sign (+1: the face normal points out of this cell, -1: into it)  [1] A/V
 //   [2..4] outward unit normal  [5..7] x_f - x_i  [8] s_f (Eq. 45)  [9..11] least-squares weight M^-1 d
-constexpr int CG = 56;
-constexpr int CG_FACE = 8;
-constexpr int CG_SLOT = 12;
 // FP32 reconstruction geometry per cell: for face slot a, [7a, 7a + 3) = x_f - x_i, [7a + 3] = s_f,
 // [7a + 4, 7a + 7) = the least-squares weights of the neighbour difference
-constexpr int CGF = 32;
+// Upwind codes: 2 bits per slot, one byte per (cell, velocity) for NF = 4, two for NF = 6.
+template <int NF> struct Lay {
+  static constexpr int CG = 8 + 12 * NF;
+  static constexpr int CGF = NF == 4 ? 32 : 48;
+  using Code = typename std::conditional<NF == 4, uint8_t, uint16_t>::type;
+};
+// the tetrahedral layout (the adjoint kernels run on tetrahedral meshes only)
+constexpr int CG = Lay<4>::CG;
+constexpr int CG_FACE = 8;
+constexpr int CG_SLOT = 12;
+constexpr int CGF = Lay<4>::CGF;
 
 // Per-face record, FP64, FGW doubles: [0] A  [1..3] unit normal (out of face_cell[2f])  [4] s  [5] dl
 constexpr int FGW = 8;
@@ -43,12 +57,14 @@ struct GasC {
 
 struct Dev {
   int64_t nc, nf, nv;
-  const int32_t* cell_nb;    // [nc][4] neighbour cell or -1
+  int mf;                    // face slots per cell, 4 or kMaxFaces
+  const int32_t* cell_nb;    // [nc][mf] neighbour cell, -1 (boundary face) or kNoFace (unused slot)
   const int32_t* spatial;    // [nc] cells in Morton order of their centroids
-  const int32_t* cell_face;  // [nc][4]
-  const double* cell_geo;    // [nc][CG]
-  const float* cell_geo_f;   // [nc][CGF] FP32 copy of the reconstruction geometry, see CGF
-  uint8_t* upw;              // [nc][nv] upwind codes: bits 2a..2a+1 = 1 (u.n > 0), 2 (u.n < 0), 0 (tie) of slot a
+  const int32_t* cell_face;  // [nc][mf] (-1: unused slot)
+  const double* cell_geo;    // [nc][Lay<mf>::CG]
+  const float* cell_geo_f;   // [nc][Lay<mf>::CGF] FP32 copy of the reconstruction geometry
+  uint8_t* upw;              // [nc][nv] upwind codes (Lay<mf>::Code): bits 2a..2a+1 = 1 (u.n > 0), 2 (u.n < 0),
+                             // 0 (tie or unused slot) of slot a
   const int32_t* face_cell;  // [nf][2] (cell the normal points out of, other cell or -1)
   const int32_t* face_bc;    // [nf] slot in bc table, -1 interior
   const double* face_geo;    // [nf][FGW]
@@ -57,8 +73,9 @@ struct Dev {
   const double* bc;          // [nbc][BCW]
   GasC gas;
   double snap, lim_K, inv_dt, cfl_imp, umax;
-  int limiter;               // 0 off, 1 Venkatakrishnan, 2 the same (held fixed by the VJP), 3 frozen values
-  const void* lim_frozen;    // limiter 3: [2][nc][nv] stored limiter values of G then R (state precision)
+  int limiter;               // 0 off, 1 Venkatakrishnan, 2 the same (held fixed by the VJP), 3 stored values,
+                             // 4 the smaller of the computed and the stored value, stored back
+  const void* lim_frozen;    // limiter 3, 4: [2][nc][nv] stored limiter values of G then R (state precision)
 };
 
 // Step 7's residual is reduced in two stages over a fixed partition of the cells: kResidualParts partial sums of
@@ -68,8 +85,8 @@ constexpr int kResidualParts = 256;
 struct Work {
   double* face_mac;  // [nf][6]
   double* cell_prim; // [nc][8]: rho U T T_tr tau 0
-  double* rcf;       // [nc][4]
-  double* G0;        // [nc][4][6] Euler flux of the neighbour's W^n along the outward normal
+  double* rcf;       // [nc][mf] spectral radius r_ij of each face slot (Eq. 41)
+  double* G0;        // [nc][mf][6] Euler flux of the neighbour's W^n along the outward normal
   double* mres;      // [nc][6]
   double* mD;        // [nc][2]
   double* Fmac;      // [nc][6]

@@ -138,14 +138,14 @@ __device__ inline float lim_div(float a, float b) { return a * __builtin_amdgcn_
 
 // One distribution at one velocity: limited least-squares gradient of the cell and the upwind face values
 // (written at dst + frow[a] + k).  limiter 3 takes L from the frozen row Lin; Lcap (if set) receives L.
-template <class T>
+template <class T, int NF>
 __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const T* wx, const T* wy, const T* wz,
                                    const T* fx, const T* fy, const T* fz, const T* sf, T kh3, int limiter,
                                    const bool* up, T ux, T uy, T uz, T* dst, const int64_t* frow, int k,
                                    const T* Lin, T* Lcap) {
   T gx = 0, gy = 0, gz = 0, pmax = phi, pmin = phi;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     if (nb[a] < 0) continue;
     const T dphi = pn[a] - phi;
     gx += wx[a] * dphi;
@@ -157,13 +157,14 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
   T L = 1;
   if (limiter == 3) {
     L = Lin[k];
-  } else if (limiter) {
+  } else if (limiter) {  // 1, 2, and 4 (the smaller of this value and the stored one, stored back)
     const T scale = fabs(pmax) > fabs(pmin) ? fabs(pmax) : fabs(pmin);
     const T eps2 = kh3 * scale * scale;
     // Venkatakrishnan's function with the common factor d2 divided out of both parts:
-    // psi = (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2), and psi = 1 where d2 = 0
+    // psi = (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2), and psi = 1 where d2 = 0 (an unused
+    // slot has zero geometry, so d2 = 0)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       const T d2 = gx * fx[a] + gy * fy[a] + gz * fz[a];
       if (d2 != T(0)) {
         const T d1 = d2 > T(0) ? pmax - phi : pmin - phi;
@@ -172,13 +173,14 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
         L = psi < L ? psi : L;
       }
     }
+    if (limiter == 4) L = Lin[k] < L ? Lin[k] : L;
   }
   if (Lcap) Lcap[k] = L;
   gx *= L;
   gy *= L;
   gz *= L;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     if (!up[a]) continue;
     st_stream(dst + frow[a] + k, phi + (fx[a] - ux * sf[a]) * gx + (fy[a] - uy * sf[a]) * gy + (fz[a] - uz * sf[a]) * gz);
   }
@@ -186,31 +188,32 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
 
 // Every load of a thread's velocities is issued before its first store (the stores could alias later loads
 // as far as the compiler knows); per-cell geometry is converted once into registers.
-template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b, T* cap) {
+template <class T, int NF> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b, T* cap) {
+  using L = Lay<NF>;
   constexpr int U = kVptOne;
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
   const int64_t i = d.spatial[cc.cell];
   const int64_t nv = d.nv;
-  const double* geo = d.cell_geo + CG * i;
+  const double* geo = d.cell_geo + L::CG * i;
   const T* G = (const T*)b.G;
   const T* R = (const T*)b.R;
   T* FG = (T*)b.faceG;
   T* FR = (T*)b.faceR;
-  int32_t nb[4];
-  int64_t srow[4], frow[4];  // element offsets of the neighbour rows and the face rows (shared by G and R)
-  bool own[4];
-  T wx[4], wy[4], wz[4], fx[4], fy[4], fz[4], sf[4];
+  int32_t nb[NF];
+  int64_t srow[NF], frow[NF];  // element offsets of the neighbour rows and the face rows (shared by G and R)
+  bool own[NF];
+  T wx[NF], wy[NF], wz[NF], fx[NF], fy[NF], fz[NF], sf[NF];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    nb[a] = d.cell_nb[4 * i + a];
+  for (int a = 0; a < NF; ++a) {
+    nb[a] = d.cell_nb[NF * i + a];
     srow[a] = (int64_t)(nb[a] >= 0 ? nb[a] : i) * nv;
-    frow[a] = (int64_t)d.cell_face[4 * i + a] * nv;
+    frow[a] = (int64_t)d.cell_face[NF * i + a] * nv;  // unused slot: never written (its code is 0)
     const double* s = geo + CG_FACE + CG_SLOT * a;
     own[a] = s[0] > 0.0;
     if constexpr (std::is_same<T, float>::value) {
       // the FP32 copy: used straight from scalar registers, no conversions
-      const float* sg = d.cell_geo_f + CGF * i + 7 * a;
+      const float* sg = d.cell_geo_f + L::CGF * i + 7 * a;
       fx[a] = sg[0];
       fy[a] = sg[1];
       fz[a] = sg[2];
@@ -234,20 +237,23 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   const int limiter = cap ? 1 : d.limiter;
   const int64_t self = i * nv;
   const int64_t P = d.nc * nv;
-  const T* LinG = limiter == 3 ? (const T*)d.lim_frozen + self : nullptr;
-  const T* LinR = limiter == 3 ? LinG + P : nullptr;
-  T* capG = cap ? cap + self : nullptr;
-  T* capR = cap ? cap + P + self : nullptr;
+  const bool stored = limiter == 3 || limiter == 4;
+  const T* LinG = stored ? (const T*)d.lim_frozen + self : nullptr;
+  const T* LinR = stored ? LinG + P : nullptr;
+  // limiter 4 writes the smaller value back in place (each (cell, velocity) entry has one thread)
+  T* capG = cap ? cap + self : limiter == 4 ? (T*)d.lim_frozen + self : nullptr;
+  T* capR = cap ? cap + P + self : limiter == 4 ? (T*)d.lim_frozen + P + self : nullptr;
   const int nvi = (int)nv;
   const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
-  T pG[U], pR[U], nG[U][4], nR[U][4], tx[U], ty[U], tz[U];
+  T pG[U], pR[U], nG[U][NF], nR[U][NF], tx[U], ty[U], tz[U];
   unsigned code[U];
-  bool up[U][4];
+  bool up[U][NF];
+  const typename L::Code* upw = reinterpret_cast<const typename L::Code*>(d.upw);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = k0 + u * kBlock;
     if (k >= nvi) continue;
-    code[u] = d.upw[self + k];
+    code[u] = upw[self + k];
     if constexpr (std::is_same<T, float>::value) {
       tx[u] = d.dvs_f[k];
       ty[u] = d.dvs_f[nv + k];
@@ -260,7 +266,7 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
     pG[u] = G[self + k];
     pR[u] = R[self + k];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       nG[u][a] = G[srow[a] + k];
       nR[u][a] = R[srow[a] + k];
     }
@@ -271,7 +277,7 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   for (int u = 0; u < U; ++u) {
     if (k0 + u * kBlock >= nvi) continue;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       const unsigned c = (code[u] >> (2 * a)) & 3u;
       up[u][a] = nb[a] >= 0 ? (own[a] ? c == 1u : c != 2u) : c == 1u;
     }
@@ -280,15 +286,19 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs
   for (int u = 0; u < U; ++u) {
     const int k = k0 + u * kBlock;
     if (k >= nvi) continue;
-    recon_write<T>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FG, frow, k,
+    recon_write<T, NF>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FG, frow, k,
                    LinG, capG);
-    recon_write<T>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FR, frow, k,
+    recon_write<T, NF>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FR, frow, k,
                    LinR, capR);
   }
 }
 
 template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st, void* cap) {
-  hipLaunchKernelGGL(k_recon<T>, cell_chunk_grid_u<kVptOne>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, (T*)cap);
+  if (d.mf == 4)
+    hipLaunchKernelGGL((k_recon<T, 4>), cell_chunk_grid_u<kVptOne>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, (T*)cap);
+  else
+    hipLaunchKernelGGL((k_recon<T, kMaxFaces>), cell_chunk_grid_u<kVptOne>(d.nc, d.nv), dim3(kBlock), 0, st, d, b,
+                       (T*)cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,7 +403,7 @@ __device__ inline void face_state_coeffs(const double* m, const double* U0, doub
   ec[29] = s / (tau + s);
 }
 
-template <class T, bool UseLds>
+template <class T, bool UseLds, int NF>
 __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   extern __shared__ unsigned char smem_raw[];
   T* sG = reinterpret_cast<T*>(smem_raw);
@@ -475,9 +485,9 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     // (fewer cached DVS loads per velocity).
     const int64_t own = d.face_cell[2 * f];
     int slot = 0;
-    for (int a = 1; a < 4; ++a)
-      if (d.cell_face[4 * own + a] == (int32_t)f) slot = a;
-    const uint8_t* code = d.upw + own * nv;
+    for (int a = 1; a < NF; ++a)
+      if (d.cell_face[NF * own + a] == (int32_t)f) slot = a;
+    const typename Lay<NF>::Code* code = reinterpret_cast<const typename Lay<NF>::Code*>(d.upw) + own * nv;
     acc.zero();
     unsigned pc[P];
     k_loop_pf<P>(nv, [&](int k, int q) {
@@ -569,13 +579,20 @@ constexpr int64_t kLdsStageMax = 40 * 1024;
 
 template <class T> static bool face_lds_ok(int64_t nv) { return nv * 2 * (int64_t)sizeof(T) <= kLdsStageMax; }
 
-template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
+template <class T, int NF> void launch_face_nf(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
   if (face_lds_ok<T>(d.nv)) {
     size_t lds = (size_t)d.nv * 2 * sizeof(T);
-    hipLaunchKernelGGL((k_face<T, true>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
+    hipLaunchKernelGGL((k_face<T, true, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
   } else {
-    hipLaunchKernelGGL((k_face<T, false>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, w);
+    hipLaunchKernelGGL((k_face<T, false, NF>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, w);
   }
+}
+
+template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
+  if (d.mf == 4)
+    launch_face_nf<T, 4>(d, b, w, st);
+  else
+    launch_face_nf<T, kMaxFaces>(d, b, w, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -598,18 +615,22 @@ __global__ __launch_bounds__(kBlock) void k_cell_prim(Dev d, const double* W, Wo
 }
 
 // Macro flux per cell (Eq. 37), diagonal D_i and right-hand side Res_i of Eq. 43, spectral radii r_ij (Eq. 41)
-__global__ __launch_bounds__(kBlock) void k_macro_prep(Dev d, const double* W, Work w) {
+template <int NF> __global__ __launch_bounds__(kBlock) void k_macro_prep(Dev d, const double* W, Work w) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.nc) return;
-  const double* geo = d.cell_geo + CG * i;
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
   const double* pa = w.cell_prim + 8 * i;
   const GasC& g = d.gas;
   double F[6] = {0, 0, 0, 0, 0, 0};
   double acc = 0.0;
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     const double* s = geo + CG_FACE + CG_SLOT * a;
-    int32_t nb = d.cell_nb[4 * i + a];
-    int32_t f = d.cell_face[4 * i + a];
+    int32_t nb = d.cell_nb[NF * i + a];
+    int32_t f = d.cell_face[NF * i + a];
+    if (f < 0) {  // unused slot
+      w.rcf[NF * i + a] = 0.0;
+      continue;
+    }
     const double* pb = nb >= 0 ? w.cell_prim + 8 * (int64_t)nb : pa;
     // face state: arithmetic mean of the two cells
     double rho = 0.5 * (pa[0] + pb[0]);
@@ -617,10 +638,10 @@ __global__ __launch_bounds__(kBlock) void k_macro_prep(Dev d, const double* W, W
     double Ttr = 0.5 * (pa[5] + pb[5]);
     double Un = 0.5 * (pa[1] + pb[1]) * s[2] + 0.5 * (pa[2] + pb[2]) * s[3] + 0.5 * (pa[3] + pb[3]) * s[4];
     double r = fabs(Un) + sqrt(g.gamma * g.R * T) + 2.0 * visc(Ttr, g) / (rho * d.face_geo[FGW * (int64_t)f + 5]);
-    w.rcf[4 * i + a] = r;
+    w.rcf[NF * i + a] = r;
     acc += 0.5 * s[1] * r;
     // G_n(W_j^n) along the outward normal, constant during the sweeps
-    if (nb >= 0) euler_flux(W + 6 * (int64_t)nb, s[2], s[3], s[4], w.G0 + 24 * i + 6 * a);
+    if (nb >= 0) euler_flux(W + 6 * (int64_t)nb, s[2], s[3], s[4], w.G0 + 6 * NF * i + 6 * a);
     const double* fm = w.face_mac + 6 * (int64_t)f;
     for (int m = 0; m < 6; ++m) F[m] += s[0] * fm[m] * geo[1];
   }
@@ -642,10 +663,15 @@ __global__ __launch_bounds__(kBlock) void k_macro_prep(Dev d, const double* W, W
 // colour is ~N_c/5 cells, so small workgroups spread each launch over more CUs.
 constexpr int kMacroBlock = 64;
 
+// Lanes per cell: NF rounded up to a power of two (4 or 8); lanes past NF carry zero terms.
+template <int NF> struct MacroLanes { static constexpr int n = NF <= 4 ? 4 : 8, shift = NF <= 4 ? 2 : 3; };
+
+template <int NF>
 __global__ __launch_bounds__(kMacroBlock) void k_macro_sweep(Dev d, const double* W, Work w, int64_t c0, int64_t c1) {
+  constexpr int NL = MacroLanes<NF>::n;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = c0 + (t >> 2);
-  const int a = (int)(t & 3);
+  const int64_t i = c0 + (t >> MacroLanes<NF>::shift);
+  const int a = (int)(t & (NL - 1));
   const bool valid = i < c1;
   double term[6] = {0, 0, 0, 0, 0, 0};
   double acc[6], D = 1.0, D5 = 1.0;
@@ -654,33 +680,30 @@ __global__ __launch_bounds__(kMacroBlock) void k_macro_sweep(Dev d, const double
     for (int m = 0; m < 6; ++m) acc[m] = w.mres[6 * i + m];
     D = w.mD[2 * i];
     D5 = w.mD[2 * i + 1];
-    const int32_t nb = d.cell_nb[4 * i + a];
+    const int32_t nb = a < NF ? d.cell_nb[NF * i + a] : kNoFace;
     if (nb >= 0) {
-      const double* s = d.cell_geo + CG * i + CG_FACE + CG_SLOT * a;
+      const double* s = d.cell_geo + Lay<NF>::CG * i + CG_FACE + CG_SLOT * a;
       double Wp[6], dWj[6], G1[6];
       for (int m = 0; m < 6; ++m) {
         dWj[m] = w.dW[6 * (int64_t)nb + m];
         Wp[m] = W[6 * (int64_t)nb + m] + dWj[m];
       }
       euler_flux(Wp, s[2], s[3], s[4], G1);
-      const double* G0 = w.G0 + 24 * i + 6 * a;
-      const double r = w.rcf[4 * i + a];
+      const double* G0 = w.G0 + 6 * NF * i + 6 * a;
+      const double r = w.rcf[NF * i + a];
       for (int m = 0; m < 6; ++m) term[m] = 0.5 * s[1] * ((G1[m] - G0[m]) - r * dWj[m]);
     }
   }
-  double t1[6], t2[6], t3[6];
+  double tn[NL][6];
   const int lane = threadIdx.x & 63;
-  for (int m = 0; m < 6; ++m) {
-    t1[m] = __shfl(term[m], lane + 1, 64);
-    t2[m] = __shfl(term[m], lane + 2, 64);
-    t3[m] = __shfl(term[m], lane + 3, 64);
-  }
+#pragma unroll
+  for (int q = 1; q < NL; ++q)
+    for (int m = 0; m < 6; ++m) tn[q][m] = __shfl(term[m], lane + q, 64);
   if (!valid || a != 0) return;
   for (int m = 0; m < 6; ++m) {
     acc[m] -= term[m];
-    acc[m] -= t1[m];
-    acc[m] -= t2[m];
-    acc[m] -= t3[m];
+#pragma unroll
+    for (int q = 1; q < NF; ++q) acc[m] -= tn[q][m];
   }
   const double iD = 1.0 / D;  // one division on the cell's lane instead of five (measured: macro stage -2.6%)
   for (int m = 0; m < 5; ++m) w.dW[6 * i + m] = acc[m] * iD;
@@ -688,7 +711,7 @@ __global__ __launch_bounds__(kMacroBlock) void k_macro_sweep(Dev d, const double
 }
 
 // W~ = W^n + dW~; predicted equilibrium coefficients with q~ = q^n
-__global__ __launch_bounds__(kBlock) void k_cell_eq(Dev d, const double* W, const double* q, Work w) {
+template <int NF> __global__ __launch_bounds__(kBlock) void k_cell_eq(Dev d, const double* W, const double* q, Work w) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.nc) return;
   double Wt[6];
@@ -701,17 +724,19 @@ __global__ __launch_bounds__(kBlock) void k_cell_eq(Dev d, const double* W, cons
   double* e = w.eq + ER * i;
   eq_coeffs(p, q + 6 * i, d.gas, e);
   e[7] = visc(p.Ttr, d.gas) / (p.rho * d.gas.R * p.Ttr);
-  w.mbase[i] = inv_dt_cell(d, d.cell_geo[CG * i + 2]) + 1.0 / e[7];
+  w.mbase[i] = inv_dt_cell(d, d.cell_geo[Lay<NF>::CG * i + 2]) + 1.0 / e[7];
 }
 
-__global__ __launch_bounds__(kBlock) void k_macro_flux_cells(Dev d, Work w) {
+template <int NF> __global__ __launch_bounds__(kBlock) void k_macro_flux_cells(Dev d, Work w) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.nc) return;
-  const double* geo = d.cell_geo + CG * i;
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
   double F[6] = {0, 0, 0, 0, 0, 0};
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     const double* s = geo + CG_FACE + CG_SLOT * a;
-    const double* fm = w.face_mac + 6 * (int64_t)d.cell_face[4 * i + a];
+    const int32_t f = d.cell_face[NF * i + a];
+    if (f < 0) continue;
+    const double* fm = w.face_mac + 6 * (int64_t)f;
     for (int m = 0; m < 6; ++m) F[m] += s[0] * fm[m] * geo[1];
   }
   for (int m = 0; m < 6; ++m) w.Fmac[6 * i + m] = F[m];
@@ -719,7 +744,10 @@ __global__ __launch_bounds__(kBlock) void k_macro_flux_cells(Dev d, Work w) {
 
 void launch_macro_flux_cells(const Dev& d, const Work& w, hipStream_t st) {
   int nb = (int)((d.nc + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_macro_flux_cells, dim3(nb), dim3(kBlock), 0, st, d, w);
+  if (d.mf == 4)
+    hipLaunchKernelGGL(k_macro_flux_cells<4>, dim3(nb), dim3(kBlock), 0, st, d, w);
+  else
+    hipLaunchKernelGGL(k_macro_flux_cells<kMaxFaces>, dim3(nb), dim3(kBlock), 0, st, d, w);
 }
 
 // Colour order of n_pairs forward + backward Gauss-Seidel passes over the non-empty colours.  A colour that
@@ -739,17 +767,27 @@ std::vector<int64_t> sweep_sequence(const int64_t* color_off, int64_t n_colors, 
   return seq;
 }
 
-void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_macro,
-                  hipStream_t st) {
+template <int NF>
+void launch_macro_nf(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors,
+                     int n_macro, hipStream_t st) {
   int nb = (int)((d.nc + kBlock - 1) / kBlock);
+  constexpr int NL = MacroLanes<NF>::n;
   hipLaunchKernelGGL(k_cell_prim, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, w);
-  hipLaunchKernelGGL(k_macro_prep, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, w);
+  hipLaunchKernelGGL(k_macro_prep<NF>, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, w);
   for (const int64_t c : sweep_sequence(color_off, n_colors, n_macro)) {
     const int64_t n = color_off[c + 1] - color_off[c];
-    hipLaunchKernelGGL(k_macro_sweep, dim3((unsigned)((4 * n + kMacroBlock - 1) / kMacroBlock)), dim3(kMacroBlock), 0,
-                       st, d, (const double*)b.W, w, color_off[c], color_off[c + 1]);
+    hipLaunchKernelGGL(k_macro_sweep<NF>, dim3((unsigned)((NL * n + kMacroBlock - 1) / kMacroBlock)),
+                       dim3(kMacroBlock), 0, st, d, (const double*)b.W, w, color_off[c], color_off[c + 1]);
   }
-  hipLaunchKernelGGL(k_cell_eq, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, (const double*)b.q, w);
+  hipLaunchKernelGGL(k_cell_eq<NF>, dim3(nb), dim3(kBlock), 0, st, d, (const double*)b.W, (const double*)b.q, w);
+}
+
+void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_macro,
+                  hipStream_t st) {
+  if (d.mf == 4)
+    launch_macro_nf<4>(d, b, w, color_off, n_colors, n_macro, st);
+  else
+    launch_macro_nf<kMaxFaces>(d, b, w, color_off, n_colors, n_macro, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -757,19 +795,29 @@ void launch_macro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
 // flux_only = 1 writes F instead (explicit operator).  Workgroup (cell, velocity chunk).
 // ---------------------------------------------------------------------------
 
-template <class T>
+// Eq. 31 of one cell and velocity: the signed sum of the face fluxes, in slot order (left to right).
+template <class T, int NF> __device__ inline T face_sum(const T* sg, const T* x) {
+  T acc = sg[0] * x[0];
+#pragma unroll
+  for (int a = 1; a < NF; ++a) acc += sg[a] * x[a];
+  return acc;
+}
+
+template <class T, int NF>
 __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* outG, T* outR, int flux_only) {
   constexpr int U = Vpt<T>::v;
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
   const int64_t i = d.spatial[cc.cell];
   const int64_t nv = d.nv;
-  const double* geo = d.cell_geo + CG * i;
-  const T *fG[4], *fR[4];
-  T sg[4];
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
+  const T *fG[NF], *fR[NF];
+  T sg[NF];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t f = d.cell_face[4 * i + a];
+  for (int a = 0; a < NF; ++a) {
+    // an unused slot reads the first face's row with a zero sign (its geometry is zero)
+    const int32_t fa = d.cell_face[NF * i + a];
+    const int64_t f = fa >= 0 ? fa : d.cell_face[NF * i];
     fG[a] = (const T*)b.faceG + f * nv;
     fR[a] = (const T*)b.faceR + f * nv;
     sg[a] = (T)(geo[CG_FACE + CG_SLOT * a] * geo[1]);
@@ -778,14 +826,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
   const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
   T* oG = outG + i * nv;
   T* oR = outR + i * nv;
-  T xG[U][4], xR[U][4];
+  T xG[U][NF], xR[U][NF];
   if (flux_only) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u * kBlock;
       if (k >= nvi) continue;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
+      for (int a = 0; a < NF; ++a) {
         xG[u][a] = fG[a][k];
         xR[u][a] = fR[a][k];
       }
@@ -794,8 +842,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u * kBlock;
       if (k >= nvi) continue;
-      oG[k] = sg[0] * xG[u][0] + sg[1] * xG[u][1] + sg[2] * xG[u][2] + sg[3] * xG[u][3];
-      oR[k] = sg[0] * xR[u][0] + sg[1] * xR[u][1] + sg[2] * xR[u][2] + sg[3] * xR[u][3];
+      oG[k] = face_sum<T, NF>(sg, xG[u]);
+      oR[k] = face_sum<T, NF>(sg, xR[u]);
     }
     return;
   }
@@ -811,7 +859,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
     const int k = k0 + u * kBlock;
     if (k >= nvi) continue;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       xG[u][a] = fG[a][k];
       xR[u][a] = fR[a][k];
     }
@@ -823,8 +871,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
   for (int u = 0; u < U; ++u) {
     const int k = k0 + u * kBlock;
     if (k >= nvi) continue;
-    const T FG = sg[0] * xG[u][0] + sg[1] * xG[u][1] + sg[2] * xG[u][2] + sg[3] * xG[u][3];
-    const T FR = sg[0] * xR[u][0] + sg[1] * xR[u][1] + sg[2] * xR[u][2] + sg[3] * xR[u][3];
+    const T FG = face_sum<T, NF>(sg, xG[u]);
+    const T FR = face_sum<T, NF>(sg, xR[u]);
     T gs, rs;
     e.eval(ux[u], uy[u], uz[u], gs, rs);
     st_stream(oG + k, (gs - pG[u]) * itau - FG);
@@ -837,7 +885,7 @@ template <int V> struct alignas(4 * V) VecR { float v[V]; };
 // The mixed-mode micro residual with V adjacent velocities per thread moved as vectors (nv a multiple of V, so
 // that every row offset keeps them aligned), Res stored non-temporally; the arithmetic of k_residual<float>,
 // velocity by velocity.  Measured on the sphere (4140 velocities): 1.68 -> 1.50 ms with V = 4.
-template <int V>
+template <int V, int NF>
 __global__ __launch_bounds__(kBlock) void k_residual_vec(Dev d, Bufs b, Work w, float* outG, float* outR) {
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
@@ -846,12 +894,13 @@ __global__ __launch_bounds__(kBlock) void k_residual_vec(Dev d, Bufs b, Work w, 
   const int k = (int)cc.chunk * (V * kBlock) + V * (int)threadIdx.x;
   if (k >= (int)nv) return;
   using VF = VecR<V>;
-  const double* geo = d.cell_geo + CG * i;
-  VF xG[4], xR[4];
-  float sg[4];
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
+  VF xG[NF], xR[NF];
+  float sg[NF];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t f = d.cell_face[4 * i + a];
+  for (int a = 0; a < NF; ++a) {
+    const int32_t fa = d.cell_face[NF * i + a];
+    const int64_t f = fa >= 0 ? fa : d.cell_face[NF * i];
     xG[a] = *reinterpret_cast<const VF*>((const float*)b.faceG + f * nv + k);
     xR[a] = *reinterpret_cast<const VF*>((const float*)b.faceR + f * nv + k);
     sg[a] = (float)(geo[CG_FACE + CG_SLOT * a] * geo[1]);
@@ -868,8 +917,12 @@ __global__ __launch_bounds__(kBlock) void k_residual_vec(Dev d, Bufs b, Work w, 
   VF oG, oR;
 #pragma unroll
   for (int q = 0; q < V; ++q) {
-    const float FG = sg[0] * xG[0].v[q] + sg[1] * xG[1].v[q] + sg[2] * xG[2].v[q] + sg[3] * xG[3].v[q];
-    const float FR = sg[0] * xR[0].v[q] + sg[1] * xR[1].v[q] + sg[2] * xR[2].v[q] + sg[3] * xR[3].v[q];
+    float FG = sg[0] * xG[0].v[q], FR = sg[0] * xR[0].v[q];
+#pragma unroll
+    for (int a = 1; a < NF; ++a) {
+      FG += sg[a] * xG[a].v[q];
+      FR += sg[a] * xR[a].v[q];
+    }
     float gs, rs;
     e.eval(ux.v[q], uy.v[q], uz.v[q], gs, rs);
     oG.v[q] = (gs - pG.v[q]) * itau - FG;
@@ -886,20 +939,29 @@ __global__ __launch_bounds__(kBlock) void k_residual_vec(Dev d, Bufs b, Work w, 
   __builtin_nontemporal_store(sR, reinterpret_cast<ev*>(outR + i * nv + k));
 }
 
-template <class T>
-void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR, int flux_only, hipStream_t st) {
+template <class T, int NF>
+void launch_residual_nf(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR, int flux_only,
+                        hipStream_t st) {
   if (std::is_same<T, float>::value && !flux_only && d.nv % 4 == 0) {
-    hipLaunchKernelGGL(k_residual_vec<4>, cell_chunk_grid_u<4>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w,
+    hipLaunchKernelGGL((k_residual_vec<4, NF>), cell_chunk_grid_u<4>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w,
                        (float*)outG, (float*)outR);
     return;
   }
   if (std::is_same<T, float>::value && !flux_only && d.nv % 2 == 0) {
-    hipLaunchKernelGGL(k_residual_vec<2>, cell_chunk_grid_u<2>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w,
+    hipLaunchKernelGGL((k_residual_vec<2, NF>), cell_chunk_grid_u<2>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w,
                        (float*)outG, (float*)outR);
     return;
   }
-  hipLaunchKernelGGL(k_residual<T>, cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w, (T*)outG,
+  hipLaunchKernelGGL((k_residual<T, NF>), cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w, (T*)outG,
                      (T*)outR, flux_only);
+}
+
+template <class T>
+void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR, int flux_only, hipStream_t st) {
+  if (d.mf == 4)
+    launch_residual_nf<T, 4>(d, b, w, outG, outR, flux_only, st);
+  else
+    launch_residual_nf<T, kMaxFaces>(d, b, w, outG, outR, flux_only, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -912,22 +974,22 @@ void launch_residual(const Dev& d, const Bufs& b, const Work& w, void* outG, voi
 // every other kernel); the magnitudes u.n are computed in the precision of the distributions (FP32 in the
 // mixed mode; the increments of the sweep only steer the iteration, its fixed point is set by Res).  The
 // diagonal D = 1/dt + 1/tau~ + sum_f (A/V) max(u.n, 0) is summed and inverted in FP64 in both modes.
-template <class T> struct MicroCell {
-  const T *nG[4], *nR[4], *rG, *rR;
+template <class T, int NF> struct MicroCell {
+  const T *nG[NF], *nR[NF], *rG, *rR;
   T *oG, *oR;
-  T nx[4], ny[4], nz[4], av[4];
+  T nx[NF], ny[NF], nz[NF], av[NF];
   double dbase;  // 1/dt + 1/tau~
-  bool use[4];
+  bool use[NF];
 };
 
-template <class T>
+template <class T, int NF>
 __device__ inline void micro_setup(const Dev& d, const Bufs& b, const Work& w, int64_t i, int64_t cnext, int first,
-                                   MicroCell<T>& c) {
+                                   MicroCell<T, NF>& c) {
   const int64_t nv = d.nv;
-  const double* geo = d.cell_geo + CG * i;
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int32_t nb = d.cell_nb[4 * i + a];
+  for (int a = 0; a < NF; ++a) {
+    const int32_t nb = d.cell_nb[NF * i + a];
     c.use[a] = nb >= 0 && !(first && nb >= cnext);
     const int64_t row = (nb >= 0 ? nb : i) * nv;
     c.nG[a] = (const T*)b.dG + row;
@@ -947,21 +1009,21 @@ __device__ inline void micro_setup(const Dev& d, const Bufs& b, const Work& w, i
 
 // Values a relaxation reads: the outflow part max(u.n, 0) and inflow part min(u.n, 0) per face, the right-hand
 // sides and the upstream neighbours' increments
-template <class T, int U> struct MicroIn {
-  T pos[U][4], neg[U][4];
-  T xG[U], xR[U], yG[U][4], yR[U][4];
+template <class T, int U, int NF> struct MicroIn {
+  T pos[U][NF], neg[U][NF];
+  T xG[U], xR[U], yG[U][NF], yR[U][NF];
 };
 
-template <class T, int U>
-__device__ inline void micro_load(const MicroCell<T>& c, const T (*uv)[3], const unsigned* code, const int* k,
-                                  int nvi, MicroIn<T, U>& in) {
+template <class T, int U, int NF>
+__device__ inline void micro_load(const MicroCell<T, NF>& c, const T (*uv)[3], const unsigned* code, const int* k,
+                                  int nvi, MicroIn<T, U, NF>& in) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (k[u] >= nvi) continue;
     in.xG[u] = __builtin_nontemporal_load(c.rG + k[u]);
     in.xR[u] = __builtin_nontemporal_load(c.rR + k[u]);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       const unsigned cd = (code[u] >> (2 * a)) & 3u;
       const T t = uv[u][0] * c.nx[a] + uv[u][1] * c.ny[a] + uv[u][2] * c.nz[a];
       in.pos[u][a] = cd == 1u ? fmax(t, T(0)) : T(0);
@@ -974,8 +1036,8 @@ __device__ inline void micro_load(const MicroCell<T>& c, const T (*uv)[3], const
   }
 }
 
-template <class T, int U>
-__device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& in, const unsigned* code,
+template <class T, int U, int NF>
+__device__ inline void micro_store(const MicroCell<T, NF>& c, const MicroIn<T, U, NF>& in, const unsigned* code,
                                    const int* k, int nvi) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -983,7 +1045,7 @@ __device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& i
     double D = c.dbase;
     T aG = in.xG[u], aR = in.xR[u];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       D += (double)(c.av[a] * in.pos[u][a]);
       if (c.use[a] && ((code[u] >> (2 * a)) & 3u) == 2u) {
         aG -= c.av[a] * in.neg[u][a] * in.yG[u][a];
@@ -998,7 +1060,7 @@ __device__ inline void micro_store(const MicroCell<T>& c, const MicroIn<T, U>& i
 
 // Workgroup (cell, velocity chunk): velocities first, then every load of the relaxation, then the stores.
 // (Relaxing several cells per workgroup with the next cell's loads issued ahead was measured slower.)
-template <class T>
+template <class T, int NF>
 __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, int64_t c0, int64_t cnext, int first) {
   constexpr int U = kVptOne;
   const CellChunk cc = cell_chunk(cnext - c0);
@@ -1013,7 +1075,7 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, i
   for (int u = 0; u < U; ++u) {
     k[u] = (int)cc.chunk * (kBlock * U) + u * kBlock + (int)threadIdx.x;
     if (k[u] >= nvi) continue;
-    code[u] = d.upw[i * nv + k[u]];
+    code[u] = reinterpret_cast<const typename Lay<NF>::Code*>(d.upw)[i * nv + k[u]];
     if constexpr (std::is_same<T, float>::value) {
       uv[u][0] = d.dvs_f[k[u]];
       uv[u][1] = d.dvs_f[nv + k[u]];
@@ -1024,11 +1086,11 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, i
       uv[u][2] = d.dvs[2 * nv + k[u]];
     }
   }
-  MicroCell<T> c;
-  MicroIn<T, U> in;
-  micro_setup<T>(d, b, w, i, cnext, first, c);
-  micro_load<T, U>(c, uv, code, k, nvi, in);
-  micro_store<T, U>(c, in, code, k, nvi);
+  MicroCell<T, NF> c;
+  MicroIn<T, U, NF> in;
+  micro_setup<T, NF>(d, b, w, i, cnext, first, c);
+  micro_load<T, U, NF>(c, uv, code, k, nvi, in);
+  micro_store<T, U, NF>(c, in, code, k, nvi);
 }
 
 // The mixed-mode sweep moves V adjacent velocities per thread as one vector per row (one load or store of
@@ -1056,13 +1118,18 @@ template <int V> __device__ inline void st_nt(float* p, const VecF<V>& v) {
   for (int q = 0; q < V; ++q) x[q] = v.v[q];
   __builtin_nontemporal_store(x, reinterpret_cast<typename ExtV<V>::type*>(p));
 }
-template <int V> struct CodeT;
-template <> struct CodeT<2> { using type = uint16_t; };
-template <> struct CodeT<4> { using type = uint32_t; };
+// The codes of V adjacent velocities as one word: V bytes (4 face slots) or V 16-bit codes (6 slots)
+template <int V, int NF> struct CodeT;
+template <> struct CodeT<2, 4> { using type = uint16_t; };
+template <> struct CodeT<4, 4> { using type = uint32_t; };
+template <> struct CodeT<2, kMaxFaces> { using type = uint32_t; };
+template <> struct CodeT<4, kMaxFaces> { using type = uint64_t; };
 
-template <int V>
+template <int V, int NF>
 __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work w, int64_t c0, int64_t cnext,
                                                             int first) {
+  using Code = typename Lay<NF>::Code;
+  constexpr int bits = 8 * (int)sizeof(Code);
   const CellChunk cc = cell_chunk(cnext - c0);
   if (cc.cell >= cnext - c0) return;
   const int64_t nv = d.nv;
@@ -1070,21 +1137,22 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work 
   const int k = (int)cc.chunk * (V * kBlock) + V * (int)threadIdx.x;
   if (k >= (int)nv) return;
   using VF = VecF<V>;
-  const unsigned cw = *reinterpret_cast<const typename CodeT<V>::type*>(d.upw + i * nv + k);
+  const uint64_t cw = *reinterpret_cast<const typename CodeT<V, NF>::type*>(reinterpret_cast<const Code*>(d.upw) +
+                                                                             i * nv + k);
   const VF vx = *reinterpret_cast<const VF*>(d.dvs_f + k);
   const VF vy = *reinterpret_cast<const VF*>(d.dvs_f + nv + k);
   const VF vz = *reinterpret_cast<const VF*>(d.dvs_f + 2 * nv + k);
-  MicroCell<float> c;
-  micro_setup<float>(d, b, w, i, cnext, first, c);
+  MicroCell<float, NF> c;
+  micro_setup<float, NF>(d, b, w, i, cnext, first, c);
   const VF xG = ld_nt<V>(c.rG + k);
   const VF xR = ld_nt<V>(c.rR + k);
   unsigned code[V];
 #pragma unroll
-  for (int q = 0; q < V; ++q) code[q] = (cw >> (8 * q)) & 0xffu;
-  float pos[V][4], neg[V][4];
-  VF yG[4], yR[4];
+  for (int q = 0; q < V; ++q) code[q] = (unsigned)((cw >> (bits * q)) & ((1ull << bits) - 1));
+  float pos[V][NF], neg[V][NF];
+  VF yG[NF], yR[NF];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     bool need = false;
 #pragma unroll
     for (int q = 0; q < V; ++q) {
@@ -1107,7 +1175,7 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work 
     double D = c.dbase;
     float aG = xG.v[q], aR = xR.v[q];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       D += (double)(c.av[a] * pos[q][a]);
       if (c.use[a] && ((code[q] >> (2 * a)) & 3u) == 2u) {
         aG -= c.av[a] * neg[q][a] * yG[a].v[q];
@@ -1198,28 +1266,31 @@ void launch_adj_sweeps(const Dev& d, const Bufs& b, const double* in, double* ou
 
 // Upwind codes of every (cell, velocity): the sign of u.n out of the cell through each of its four faces, with
 // the tie rule |u.n| <= snap |u| -> 0 (Eq. 46), in FP64.  Computed once per state (and when snap changes).
-__global__ __launch_bounds__(kBlock) void k_upwind_codes(Dev d) {
+template <int NF> __global__ __launch_bounds__(kBlock) void k_upwind_codes(Dev d) {
   const int64_t nv = d.nv;
   const int64_t n = d.nc * nv;
   for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n; x += (int64_t)gridDim.x * kBlock) {
     const int64_t i = x / nv, k = x - i * nv;
     const double ux = d.dvs[k], uy = d.dvs[nv + k], uz = d.dvs[2 * nv + k], um = d.dvs[4 * nv + k];
-    const double* geo = d.cell_geo + CG * i;
+    const double* geo = d.cell_geo + Lay<NF>::CG * i;
     unsigned code = 0;
-    for (int a = 0; a < 4; ++a) {
-      const double* s = geo + CG_FACE + CG_SLOT * a;
+    for (int a = 0; a < NF; ++a) {
+      const double* s = geo + CG_FACE + CG_SLOT * a;  // an unused slot has a zero normal: code 0
       double un = ux * s[2] + uy * s[3] + uz * s[4];
       un = fabs(un) <= d.snap * um ? 0.0 : un;
       code |= (un > 0.0 ? 1u : (un < 0.0 ? 2u : 0u)) << (2 * a);
     }
-    d.upw[x] = (uint8_t)code;
+    reinterpret_cast<typename Lay<NF>::Code*>(d.upw)[x] = (typename Lay<NF>::Code)code;
   }
 }
 
 void launch_upwind_codes(const Dev& d, hipStream_t st) {
   const int64_t n = d.nc * d.nv;
   const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 65536));
-  hipLaunchKernelGGL(k_upwind_codes, dim3(nb), dim3(kBlock), 0, st, d);
+  if (d.mf == 4)
+    hipLaunchKernelGGL(k_upwind_codes<4>, dim3(nb), dim3(kBlock), 0, st, d);
+  else
+    hipLaunchKernelGGL(k_upwind_codes<kMaxFaces>, dim3(nb), dim3(kBlock), 0, st, d);
 }
 
 template <class T> __global__ __launch_bounds__(kBlock) void k_zero(T* a, T* b, int64_t n) {
@@ -1229,9 +1300,9 @@ template <class T> __global__ __launch_bounds__(kBlock) void k_zero(T* a, T* b, 
   }
 }
 
-template <class T>
-void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_micro,
-                  hipStream_t st) {
+template <class T, int NF>
+void launch_micro_nf(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors,
+                     int n_micro, hipStream_t st) {
   const std::vector<int64_t> seq = sweep_sequence(color_off, n_colors, n_micro);
   if (seq.empty()) {
     // no sweep: the increments of Eq. 33 stay zero
@@ -1246,15 +1317,24 @@ void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
     const int64_t c = seq[p];
     const int64_t n = color_off[c + 1] - color_off[c];
     if (std::is_same<T, float>::value && d.nv % 4 == 0)
-      hipLaunchKernelGGL(k_micro_sweep_vec<4>, cell_chunk_grid_u<4>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
+      hipLaunchKernelGGL((k_micro_sweep_vec<4, NF>), cell_chunk_grid_u<4>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
                          color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
     else if (std::is_same<T, float>::value && d.nv % 2 == 0)
-      hipLaunchKernelGGL(k_micro_sweep_vec<2>, cell_chunk_grid_u<2>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
+      hipLaunchKernelGGL((k_micro_sweep_vec<2, NF>), cell_chunk_grid_u<2>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
                          color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
     else
-      hipLaunchKernelGGL(k_micro_sweep<T>, cell_chunk_grid_u<kVptOne>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
+      hipLaunchKernelGGL((k_micro_sweep<T, NF>), cell_chunk_grid_u<kVptOne>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
                          color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
   }
+}
+
+template <class T>
+void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* color_off, int64_t n_colors, int n_micro,
+                  hipStream_t st) {
+  if (d.mf == 4)
+    launch_micro_nf<T, 4>(d, b, w, color_off, n_colors, n_micro, st);
+  else
+    launch_micro_nf<T, kMaxFaces>(d, b, w, color_off, n_colors, n_micro, st);
 }
 
 // ---------------------------------------------------------------------------
