@@ -150,8 +150,7 @@ cis_status cis_mesh_create(const double* xyz, int64_t n_nodes, const int32_t* te
    triangles.  Face slot a of a cell is its a-th local face: for a tetrahedron the face opposite local vertex a;
    a pyramid: base, then (0,1,4), (1,2,4), (2,3,4), (3,0,4); a prism: (0,1,2), (3,4,5), (0,1,4,3), (1,2,5,4),
    (2,0,3,5); a hexahedron: (0,1,2,3), (4,5,6,7), (0,1,5,4), (1,2,6,5), (2,3,7,6), (3,0,4,7).  Colours and errors as
-   for cis_mesh_create (plus CIS_E_INVALID_ARG for an unknown kind, CIS_E_MESH for a folded cell).  The steady
-   residual, VJP and adjoint run on tetrahedral meshes only (CIS_E_UNSUPPORTED otherwise). */
+   for cis_mesh_create (plus CIS_E_INVALID_ARG for an unknown kind, CIS_E_MESH for a folded cell). */
 cis_status cis_mesh_create_cells(const double* xyz, int64_t n_nodes, const int32_t* cells, const int32_t* kinds,
                                  int64_t n_cells, const int32_t* bface, const int32_t* btag, int64_t n_b,
                                  const int64_t* color_offsets, int64_t n_colors, cis_mesh** out);

@@ -18,6 +18,7 @@ from . import dvs as _dvs
 from . import mesh as _mesh
 
 __all__ = ["gas_n2", "numerics_default", "mu_ref_from_kn", "cavity_case", "sphere_case", "sphere_hex_case",
+           "small_sphere_hex_case",
            "capsule_case",
            "freestream_box_case", "open_box_case", "small_sphere_case", "rest_state"]
 
@@ -150,6 +151,14 @@ def small_sphere_case(seed: int = 0, n_ang: int = 3, n_rad: int = 3, h_outer: fl
     return _external_case(f"sphere_small_{n_ang}x{n_rad}_seed{seed}", _mesh.sphere_body(0.5), n_ang, n_rad,
                           3.0, 0.1, 5.0, 0.1, 3.0, 3.0, None, seed, n_iter, h_outer=h_outer,
                           refine_scale=refine_scale)
+
+
+def small_sphere_hex_case(seed: int = 0, n_ang: int = 4, n_rad: int = 4, h_outer: float = 2.2,
+                          refine_scale: float = 2.0, n_iter: int = 20):
+    """A few hundred hexahedra with the small sphere's DVS and physics (parity-test size)."""
+    return _external_case(f"sphere_hex_small_{n_ang}x{n_rad}_seed{seed}", _mesh.sphere_body(0.5), n_ang, n_rad,
+                          3.0, 0.1, 5.0, 0.1, 3.0, 3.0, None, seed, n_iter, h_outer=h_outer,
+                          refine_scale=refine_scale, cells="hex")
 
 
 def capsule_case(seed: int = 0, n_ang: int = 18, n_rad: int = 13, nv_target: int = 10000, n_iter: int = 50,

@@ -10,7 +10,7 @@ namespace cis {
 
 // Per-cell scratch of the block preconditioner, 24 doubles per cell: gW [nc][6], gq [nc][6], u [nc][6],
 // r [nc][4] (face spectral radii of Eq. 41), D [nc][2] (macro diagonals).
-constexpr int kBlockPrecondCellDoubles = 24;
+constexpr int kBlockPrecondCellDoubles = 26;  // gW, gq, u (6 each), r_f (up to 6 slots), 2 diagonals
 
 // out = P in over the full adjoint vector [G | R | W | q]: the W and q rows are eliminated exactly (their
 // diagonal block is taken as the identity) and the phi Schur complement is approximated by the transpose of

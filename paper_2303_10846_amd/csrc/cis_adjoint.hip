@@ -191,14 +191,14 @@ __global__ __launch_bounds__(kBlock) void k_cell_vjp(Dev d, Bufs b, AdjArgs a) {
 // The seed of the face flux A (u.n) phi_f is -A (u.n)(v_o/V_o - v_n/V_n), plus the objective's.
 // ---------------------------------------------------------------------------
 
-template <bool HasV> __global__ __launch_bounds__(kBlock) void k_face_vjp(Dev d, Bufs b, AdjArgs a) {
+template <bool HasV, int NF> __global__ __launch_bounds__(kBlock) void k_face_vjp(Dev d, Bufs b, AdjArgs a) {
   __shared__ double red[(kBlock / 64) * 2 * 14];
   __shared__ double sh_th[NTH + 1], sh_jac[14 * 12], sh_bar[12];
   const int64_t f = blockIdx.x, nv = d.nv;
   const double* fg = d.face_geo + FGW * f;
   const double A = fg[0], nx = fg[1], ny = fg[2], nz = fg[3], s = fg[4];
   const int64_t o = d.face_cell[2 * f], nb = d.face_cell[2 * f + 1];
-  const double iVo = d.cell_geo[CG * o + 1], iVn = nb >= 0 ? d.cell_geo[CG * nb + 1] : 0.0;
+  const double iVo = d.cell_geo[Lay<NF>::CG * o + 1], iVn = nb >= 0 ? d.cell_geo[Lay<NF>::CG * nb + 1] : 0.0;
   double* rowG = (double*)b.faceG + f * nv;
   double* rowR = (double*)b.faceR + f * nv;
   const int32_t bcs = d.face_bc[f];
@@ -461,6 +461,7 @@ template <bool HasV> __global__ __launch_bounds__(kBlock) void k_face_vjp(Dev d,
 // Workgroup (cell, 256 velocities); contributions are added with FP64 atomics.
 // ---------------------------------------------------------------------------
 
+template <int NF>
 __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ src, const double* __restrict__ fadj,
                                      double* gout, int64_t i, int64_t k, const int32_t* nb, const int32_t* fc,
                                      const double* geo, double kh3, const Vel& v, const double* un,
@@ -470,7 +471,7 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
   double pself = 0.0, gbx = 0.0, gby = 0.0, gbz = 0.0;
   bool any = false;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     const double* s = geo + CG_FACE + CG_SLOT * a;
     bool up = nb[a] >= 0 ? (s[0] > 0.0 ? un[a] > 0.0 : un[a] >= 0.0) : un[a] > 0.0;
     if (!up) continue;
@@ -484,13 +485,13 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
   if (!any) return;
   // forward: least-squares gradient, extrema of the stencil and the limiter (same branches as Step 2(a))
   const double phi = src[i * nv + k];
-  double pn[4];
+  double pn[NF];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) pn[a] = nb[a] >= 0 ? src[(int64_t)nb[a] * nv + k] : phi;
+  for (int a = 0; a < NF; ++a) pn[a] = nb[a] >= 0 ? src[(int64_t)nb[a] * nv + k] : phi;
   double gx = 0, gy = 0, gz = 0, pmax = phi, pmin = phi;
   int imax = -1, imin = -1;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     if (nb[a] < 0) continue;
     const double* s = geo + CG_FACE + CG_SLOT * a;
     const double dphi = pn[a] - phi;
@@ -517,7 +518,7 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
     isel = use_max ? imax : imin;
     eps2 = kh3 * psel * psel;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       const double* s = geo + CG_FACE + CG_SLOT * a;
       const double d2 = gx * s[5] + gy * s[6] + gz * s[7];
       if (d2 != 0.0) {
@@ -533,13 +534,15 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
     }
   }
   // reverse: grad_out = L g
-  double pnb[4] = {0.0, 0.0, 0.0, 0.0};
+  double pnb[NF];
+#pragma unroll
+  for (int a = 0; a < NF; ++a) pnb[a] = 0.0;
   auto add_to = [&](int idx, double x) {
     if (idx < 0) {
       pself += x;
     } else {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < NF; ++a)
         if (a == idx) pnb[a] += x;
     }
   };
@@ -564,7 +567,7 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
     add_to(isel, Lb * p_e * 2.0 * kh3 * psel);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     if (nb[a] < 0) continue;
     const double* s = geo + CG_FACE + CG_SLOT * a;
     const double t = s[9] * grx + s[10] * gry + s[11] * grz;
@@ -573,48 +576,55 @@ __device__ inline void recon_vjp_one(const Dev& d, const double* __restrict__ sr
   }
   unsafeAtomicAdd(gout + i * nv + k, pself);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NF; ++a)
     if (nb[a] >= 0 && pnb[a] != 0.0) unsafeAtomicAdd(gout + (int64_t)nb[a] * nv + k, pnb[a]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_recon_vjp(Dev d, Bufs b, AdjArgs a) {
+template <int NF> __global__ __launch_bounds__(kBlock) void k_recon_vjp(Dev d, Bufs b, AdjArgs a) {
   const int64_t i = blockIdx.x, nv = d.nv;
   const int64_t k = (int64_t)blockIdx.y * kBlock + threadIdx.x;
   if (k >= nv) return;
-  int32_t nb[4], fc[4];
+  int32_t nb[NF], fc[NF];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    nb[q] = d.cell_nb[4 * i + q];
-    fc[q] = d.cell_face[4 * i + q];
+  for (int q = 0; q < NF; ++q) {
+    nb[q] = d.cell_nb[NF * i + q];
+    fc[q] = d.cell_face[NF * i + q];
   }
-  const double* geo = d.cell_geo + CG * i;
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
   double kh3 = d.lim_K * geo[2];
   kh3 = kh3 * kh3 * kh3;
   const Vel v = vel(d, k);
-  double un[4];
+  double un[NF];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NF; ++q) {
     const double* s = geo + CG_FACE + CG_SLOT * q;
     un[q] = udotn(v, s[2], s[3], s[4], d.snap);
   }
   const double* LG = (const double*)d.lim_frozen;
   const double* LR = LG ? LG + d.nc * nv : nullptr;
-  recon_vjp_one(d, (const double*)b.G, (const double*)b.faceG, a.gG, i, k, nb, fc, geo, kh3, v, un, LG);
-  recon_vjp_one(d, (const double*)b.R, (const double*)b.faceR, a.gR, i, k, nb, fc, geo, kh3, v, un, LR);
+  recon_vjp_one<NF>(d, (const double*)b.G, (const double*)b.faceG, a.gG, i, k, nb, fc, geo, kh3, v, un, LG);
+  recon_vjp_one<NF>(d, (const double*)b.R, (const double*)b.faceR, a.gR, i, k, nb, fc, geo, kh3, v, un, LR);
 }
 
-void launch_vjp(const Dev& d, const Bufs& b, const AdjArgs& a, hipStream_t st) {
+template <int NF> void launch_vjp_nf(const Dev& d, const Bufs& b, const AdjArgs& a, hipStream_t st) {
   const bool hv = a.vG != nullptr;
   launch_recon<double>(d, b, st);
   if (hv) {
-    hipLaunchKernelGGL(k_face_vjp<true>, dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, a);
+    hipLaunchKernelGGL((k_face_vjp<true, NF>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, a);
     hipLaunchKernelGGL(k_cell_vjp<true>, dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, b, a);
   } else {
-    hipLaunchKernelGGL(k_face_vjp<false>, dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, a);
+    hipLaunchKernelGGL((k_face_vjp<false, NF>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, a);
     hipLaunchKernelGGL(k_cell_vjp<false>, dim3((unsigned)d.nc), dim3(kBlock), 0, st, d, b, a);
   }
   const unsigned nch = (unsigned)((d.nv + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_recon_vjp, dim3((unsigned)d.nc, nch), dim3(kBlock), 0, st, d, b, a);
+  hipLaunchKernelGGL(k_recon_vjp<NF>, dim3((unsigned)d.nc, nch), dim3(kBlock), 0, st, d, b, a);
+}
+
+void launch_vjp(const Dev& d, const Bufs& b, const AdjArgs& a, hipStream_t st) {
+  if (d.mf == 4)
+    launch_vjp_nf<4>(d, b, a, st);
+  else
+    launch_vjp_nf<kMaxFaces>(d, b, a, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -623,17 +633,17 @@ void launch_vjp(const Dev& d, const Bufs& b, const AdjArgs& a, hipStream_t st) {
 
 // out = M^-1 in: the phi rows are divided by -(1/tau_i + sum_f (A_f/V_i) max(u.n_out, 0)), the diagonal of
 // dR_phi/dphi with first-order upwind faces; the W and q rows are copied (their blocks are near identity).
-__global__ __launch_bounds__(kBlock) void k_precond(Dev d, Bufs b, const double* in, double* out) {
+template <int NF> __global__ __launch_bounds__(kBlock) void k_precond(Dev d, Bufs b, const double* in, double* out) {
   const int64_t i = blockIdx.x, nv = d.nv;
   const int64_t P = d.nc * nv;
-  const double* geo = d.cell_geo + CG * i;
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
   Prim p = prim_of(b.W + 6 * i, d.gas.R);
   const double itau = (p.rho * d.gas.R * p.Ttr) / visc(p.Ttr, d.gas);
   for (int64_t k = (int64_t)blockIdx.y * kBlock + threadIdx.x; k < nv; k += (int64_t)gridDim.y * kBlock) {
     const Vel v = vel(d, k);
     double D = itau;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < NF; ++a) {
       const double* s = geo + CG_FACE + CG_SLOT * a;
       const double un = udotn(v, s[2], s[3], s[4], d.snap);
       if (un > 0.0) D += s[1] * un;
@@ -649,7 +659,10 @@ __global__ __launch_bounds__(kBlock) void k_precond(Dev d, Bufs b, const double*
 
 void launch_precond(const Dev& d, const Bufs& b, const double* in, double* out, hipStream_t st) {
   const unsigned nch = (unsigned)std::min<int64_t>((d.nv + kBlock - 1) / kBlock, 64);
-  hipLaunchKernelGGL(k_precond, dim3((unsigned)d.nc, nch), dim3(kBlock), 0, st, d, b, in, out);
+  if (d.mf == 4)
+    hipLaunchKernelGGL(k_precond<4>, dim3((unsigned)d.nc, nch), dim3(kBlock), 0, st, d, b, in, out);
+  else
+    hipLaunchKernelGGL(k_precond<kMaxFaces>, dim3((unsigned)d.nc, nch), dim3(kBlock), 0, st, d, b, in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -707,22 +720,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_lift(Dev d, const double* u, dou
 }
 
 // Face spectral radii r_f (Eq. 41, from the cells' own W) and the diagonals of the steady macro system.
-__global__ __launch_bounds__(kBlock) void k_adj_macro_prep(Dev d, Bufs b, double* rc, double* mD) {
+template <int NF> __global__ __launch_bounds__(kBlock) void k_adj_macro_prep(Dev d, Bufs b, double* rc, double* mD) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.nc) return;
   const GasC& g = d.gas;
-  const double* geo = d.cell_geo + CG * i;
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
   const Prim pa = prim_of(b.W + 6 * i, g.R);
   double acc = 0.0;
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     const double* s = geo + CG_FACE + CG_SLOT * a;
-    const int32_t nb = d.cell_nb[4 * i + a];
+    const int32_t nb = d.cell_nb[NF * i + a];
+    const int32_t fc = d.cell_face[NF * i + a];
+    if (fc < 0) {  // unused slot
+      rc[NF * i + a] = 0.0;
+      continue;
+    }
     const Prim pb = nb >= 0 ? prim_of(b.W + 6 * (int64_t)nb, g.R) : pa;
     const double rho = 0.5 * (pa.rho + pb.rho), T = 0.5 * (pa.T + pb.T), Ttr = 0.5 * (pa.Ttr + pb.Ttr);
     const double Un = 0.5 * ((pa.U[0] + pb.U[0]) * s[2] + (pa.U[1] + pb.U[1]) * s[3] + (pa.U[2] + pb.U[2]) * s[4]);
     const double r = fabs(Un) + sqrt(g.gamma * g.R * T) +
-                     2.0 * visc(Ttr, g) / (rho * d.face_geo[FGW * (int64_t)d.cell_face[4 * i + a] + 5]);
-    rc[4 * i + a] = r;
+                     2.0 * visc(Ttr, g) / (rho * d.face_geo[FGW * (int64_t)fc + 5]);
+    rc[NF * i + a] = r;
     acc += 0.5 * s[1] * r;
   }
   const double tau = visc(pa.Ttr, g) / (pa.rho * g.R * pa.Ttr);
@@ -733,37 +751,39 @@ __global__ __launch_bounds__(kBlock) void k_adj_macro_prep(Dev d, Bufs b, double
 // One point relaxation over one colour of Mac^T u = t.  Row i of Mac^T couples the neighbours j through
 // Mac_ji^T = -(A_f/V_j)(dG_n/dW (W_i)^T + r_f I)/2 with n out of cell i (the flux Jacobian is odd in n and r_f
 // is the same from both sides).  Four lanes per cell, one per face, as in the forward macro sweep.
+template <int NF>
 __global__ __launch_bounds__(64) void k_adj_macro_sweep(Dev d, Bufs b, const double* rc, const double* mD,
                                                         const double* t, double* u, int64_t c0, int64_t c1) {
+  constexpr int NL = NF <= 4 ? 4 : 8, SH = NF <= 4 ? 2 : 3;  // lanes per cell; lanes past NF carry zero
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = c0 + (tid >> 2);
-  const int a = (int)(tid & 3);
+  const int64_t i = c0 + (tid >> SH);
+  const int a = (int)(tid & (NL - 1));
   const bool valid = i < c1;
   double term[6] = {0, 0, 0, 0, 0, 0};
   if (valid) {
-    const int32_t nb = d.cell_nb[4 * i + a];
+    const int32_t nb = a < NF ? d.cell_nb[NF * i + a] : kNoFace;
     if (nb >= 0) {
-      const double* geo = d.cell_geo + CG * i;
+      const double* geo = d.cell_geo + Lay<NF>::CG * i;
       const double* s = geo + CG_FACE + CG_SLOT * a;
-      const double half_av = 0.5 * s[1] * geo[0] * d.cell_geo[CG * (int64_t)nb + 1];
+      const double half_av = 0.5 * s[1] * geo[0] * d.cell_geo[Lay<NF>::CG * (int64_t)nb + 1];
       double uj[6], gj[6];
       for (int m = 0; m < 6; ++m) uj[m] = u[6 * (int64_t)nb + m];
       euler_flux_vjp(b.W + 6 * i, s[2], s[3], s[4], uj, gj);
-      const double r = rc[4 * i + a];
+      const double r = rc[NF * i + a];
       for (int m = 0; m < 6; ++m) term[m] = half_av * (gj[m] + r * uj[m]);
     }
   }
-  double t1[6], t2[6], t3[6];
+  double tn[NL][6];
   const int lane = threadIdx.x & 63;
-  for (int m = 0; m < 6; ++m) {
-    t1[m] = __shfl(term[m], lane + 1, 64);
-    t2[m] = __shfl(term[m], lane + 2, 64);
-    t3[m] = __shfl(term[m], lane + 3, 64);
-  }
+#pragma unroll
+  for (int q = 1; q < NL; ++q)
+    for (int m = 0; m < 6; ++m) tn[q][m] = __shfl(term[m], lane + q, 64);
   if (!valid || a != 0) return;
   const double D = mD[2 * i], D5 = mD[2 * i + 1];
   for (int m = 0; m < 6; ++m) {
-    const double acc = t[6 * i + m] + term[m] + t1[m] + t2[m] + t3[m];
+    double acc = t[6 * i + m] + term[m];
+#pragma unroll
+    for (int q = 1; q < NF; ++q) acc += tn[q][m];
     u[6 * i + m] = acc / (m == 5 ? D5 : D);
   }
 }
@@ -785,7 +805,7 @@ void launch_adj_block_precond(const Dev& d, const Bufs& b, const double* in, dou
   double* gq = gW + 6 * nc;
   double* u = gq + 6 * nc;
   double* rc = u + 6 * nc;
-  double* mD = rc + 4 * nc;
+  double* mD = rc + (int64_t)d.mf * nc;
   const unsigned nch = (unsigned)std::min<int64_t>((d.nv + kBlock - 1) / kBlock, 64);
   const unsigned ncb = (unsigned)((nc + kBlock - 1) / kBlock);
   // z = -(D + N)^-T (s_phi + M^T s_Y)
@@ -798,12 +818,19 @@ void launch_adj_block_precond(const Dev& d, const Bufs& b, const double* in, dou
   if (macro_pairs > 0) {
     // t = B^T z (W part), then Mac^T u = t and x_phi = z + M_c^T u
     hipLaunchKernelGGL((k_cell_vjp<true, true>), dim3((unsigned)nc), dim3(kBlock), 0, st, d, b, a);
-    hipLaunchKernelGGL(k_adj_macro_prep, dim3(ncb), dim3(kBlock), 0, st, d, b, rc, mD);
+    if (d.mf == 4)
+      hipLaunchKernelGGL(k_adj_macro_prep<4>, dim3(ncb), dim3(kBlock), 0, st, d, b, rc, mD);
+    else
+      hipLaunchKernelGGL(k_adj_macro_prep<kMaxFaces>, dim3(ncb), dim3(kBlock), 0, st, d, b, rc, mD);
     launch_axpby(6 * nc, 0.0, gW, 0.0, u, st);
     for (const int64_t c : sweep_sequence(color_off, n_colors, macro_pairs)) {
       const int64_t n = color_off[c + 1] - color_off[c];
-      hipLaunchKernelGGL(k_adj_macro_sweep, dim3((unsigned)((4 * n + 63) / 64)), dim3(64), 0, st, d, b,
-                         (const double*)rc, (const double*)mD, (const double*)gW, u, color_off[c], color_off[c + 1]);
+      if (d.mf == 4)
+        hipLaunchKernelGGL(k_adj_macro_sweep<4>, dim3((unsigned)((4 * n + 63) / 64)), dim3(64), 0, st, d, b,
+                           (const double*)rc, (const double*)mD, (const double*)gW, u, color_off[c], color_off[c + 1]);
+      else
+        hipLaunchKernelGGL(k_adj_macro_sweep<kMaxFaces>, dim3((unsigned)((8 * n + 63) / 64)), dim3(64), 0, st, d, b,
+                           (const double*)rc, (const double*)mD, (const double*)gW, u, color_off[c], color_off[c + 1]);
     }
     hipLaunchKernelGGL(k_adj_lift, dim3((unsigned)nc, nch), dim3(kBlock), 0, st, d, (const double*)u, out);
   }

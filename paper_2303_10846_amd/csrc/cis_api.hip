@@ -1320,7 +1320,6 @@ cis_status cis_steady_residual(cis_state* s, int32_t wall_tag, double* rG, doubl
   if (!s || !rG || !rR || !rW || !rq) return fail(CIS_E_INVALID_ARG, "NULL argument");
   if (s->num.limiter == 4) return fail(CIS_E_UNSUPPORTED, "limiter 4 updates its values: use limiter 3 (stored values)");
   if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the steady residual is FP64 only");
-  if (s->mesh->mf != 4) return fail(CIS_E_UNSUPPORTED, "the steady residual runs on tetrahedral meshes");
   launch_recon<double>(s->dev, s->buf, s->stream);
   launch_face<double>(s->dev, s->buf, s->work, s->stream);
   launch_residual<double>(s->dev, s->buf, s->work, rG, rR, 1, s->stream);
@@ -1340,7 +1339,6 @@ cis_status cis_residual_vjp(cis_state* s, const double* vG, const double* vR, co
   if (anyv && !allv) return fail(CIS_E_INVALID_ARG, "vG, vR, vW, vq must be all set or all NULL");
   if (!std::isfinite(cJ)) return fail(CIS_E_INVALID_ARG, "non-finite cJ");
   if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the VJP is FP64 only");
-  if (s->mesh->mf != 4) return fail(CIS_E_UNSUPPORTED, "the VJP runs on tetrahedral meshes");
   if (s->num.limiter == 4) return fail(CIS_E_UNSUPPORTED, "limiter 4 updates its values: use limiter 3 (stored values)");
   AdjSlots sl;
   cis_status st = adj_slots(s, wall_tag, ff_tag, cJ != 0.0, &sl);
@@ -1367,7 +1365,6 @@ cis_status cis_adjoint_solve(cis_state* s, int32_t wall_tag, int32_t ff_tag, int
   if (!s || !work || !lam || !dJdp) return fail(CIS_E_INVALID_ARG, "NULL argument");
   if (s->precision != CIS_FP64) return fail(CIS_E_UNSUPPORTED, "the adjoint is FP64 only");
   if (s->num.limiter == 4) return fail(CIS_E_UNSUPPORTED, "limiter 4 updates its values: use limiter 3 (stored values)");
-  if (s->mesh->mf != 4) return fail(CIS_E_UNSUPPORTED, "the adjoint runs on tetrahedral meshes");
   if (restart < 1 || restart > 1000 || max_iter < 0 || !(rtol > 0.0) || precond_pairs < 0 || precond_pairs > 64 ||
       macro_pairs < 0 || macro_pairs > 200)
     return fail(CIS_E_INVALID_ARG, "restart, max_iter, rtol, precond_pairs or macro_pairs out of range");

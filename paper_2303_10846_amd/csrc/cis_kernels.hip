@@ -1195,33 +1195,34 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work 
 // the collision term frozen: D_i = 1/tau_i + sum_f (A_f/V_i) max(u.n_i, 0) and N_ij = (A_f/V_i) min(u.n_i, 0).
 // Transposed, cell i couples to the neighbours it feeds (u.n_i > 0) with (N^T)_ij = -(A_f/V_j) u.n_i.  The W and
 // q rows are copied.  With a zero start the first forward pass reads no later colour.
+template <int NF>
 __global__ __launch_bounds__(kBlock) void k_adj_sweep(Dev d, Bufs b, const double* in, double* x, int64_t c0,
                                                       int64_t cnext, int first) {
   const CellChunk cc = cell_chunk(cnext - c0);
   if (cc.cell >= cnext - c0) return;
   const int64_t i = c0 + cc.cell, nv = d.nv, P = d.nc * nv;
   const int64_t k = cc.chunk * kBlock + threadIdx.x;
-  const double* geo = d.cell_geo + CG * i;
+  const double* geo = d.cell_geo + Lay<NF>::CG * i;
   const Prim p = prim_of(b.W + 6 * i, d.gas.R);
   const double itau = (p.rho * d.gas.R * p.Ttr) / visc(p.Ttr, d.gas);
-  int64_t nrow[4];
-  double cT[4];
-  bool use[4];
+  int64_t nrow[NF];
+  double cT[NF];
+  bool use[NF];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int32_t nb = d.cell_nb[4 * i + a];
+  for (int a = 0; a < NF; ++a) {
+    const int32_t nb = d.cell_nb[NF * i + a];
     use[a] = nb >= 0 && !(first && nb >= cnext);
     nrow[a] = (nb >= 0 ? nb : i) * nv;
     // A_f / V_j = (A_f / V_i) V_i (1 / V_j)
-    cT[a] = nb >= 0 ? geo[CG_FACE + CG_SLOT * a + 1] * geo[0] * d.cell_geo[CG * (int64_t)nb + 1] : 0.0;
+    cT[a] = nb >= 0 ? geo[CG_FACE + CG_SLOT * a + 1] * geo[0] * d.cell_geo[Lay<NF>::CG * (int64_t)nb + 1] : 0.0;
   }
   if (k >= nv) return;
-  const unsigned code = d.upw[i * nv + k];
+  const unsigned code = reinterpret_cast<const typename Lay<NF>::Code*>(d.upw)[i * nv + k];
   const double ux = d.dvs[k], uy = d.dvs[nv + k], uz = d.dvs[2 * nv + k];
-  double un[4], yG[4], yR[4];
+  double un[NF], yG[NF], yR[NF];
   double D = itau;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     const double* s = geo + CG_FACE + CG_SLOT * a;
     un[a] = ux * s[2] + uy * s[3] + uz * s[4];
     const bool out = ((code >> (2 * a)) & 3u) == 1u;
@@ -1235,7 +1236,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(Dev d, Bufs b, const doubl
   const double rG = in[i * nv + k], rR = in[P + i * nv + k];
   double aG = -rG, aR = -rR;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < NF; ++a) {
     aG += cT[a] * un[a] * yG[a];
     aR += cT[a] * un[a] * yR[a];
   }
@@ -1256,8 +1257,12 @@ void launch_adj_sweeps(const Dev& d, const Bufs& b, const double* in, double* ou
   for (size_t q = 0; q < seq.size(); ++q) {
     const int64_t c = seq[q];
     const int64_t n = color_off[c + 1] - color_off[c];
-    hipLaunchKernelGGL(k_adj_sweep, cell_chunk_grid<double>(n, d.nv), dim3(kBlock), 0, st, d, b, in, out,
-                       color_off[c], color_off[c + 1], (int64_t)q < nonempty ? 1 : 0);
+    if (d.mf == 4)
+      hipLaunchKernelGGL(k_adj_sweep<4>, cell_chunk_grid<double>(n, d.nv), dim3(kBlock), 0, st, d, b, in, out,
+                         color_off[c], color_off[c + 1], (int64_t)q < nonempty ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_adj_sweep<kMaxFaces>, cell_chunk_grid<double>(n, d.nv), dim3(kBlock), 0, st, d, b, in,
+                         out, color_off[c], color_off[c + 1], (int64_t)q < nonempty ? 1 : 0);
   }
   const int64_t tail = 12 * d.nc;
   hipLaunchKernelGGL(k_copy_tail, dim3((unsigned)std::min<int64_t>((tail + kBlock - 1) / kBlock, 4096)), dim3(kBlock),

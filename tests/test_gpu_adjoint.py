@@ -47,7 +47,15 @@ CASES = {
     "open_box_sutherland": (lambda: _sutherland(_open_box(1), 0.8), 1, 2),   # Eq. 14 viscosity, limiter on
     "open_box_frozen": (lambda: _open_box(2), 1, 2),                          # limiter held fixed in the VJP
     "open_box_stored": (lambda: dict(_open_box(1), freeze=True), 1, 2),       # stored values (limiter 3)
+    "open_box_hex": (lambda: _kind_box("hex"), 1, 2),                          # hexahedra, 6 face slots
+    "open_box_mixed": (lambda: _kind_box("mixed"), 1, 2),                      # hexahedra, pyramids, tetrahedra
 }
+
+
+def _kind_box(kind):
+    c = configs.open_box_case(n=3 if kind == "hex" else 4, nv_side=5, kind=kind)
+    c["num"] = dict(c["num"], limiter=1)
+    return c
 
 
 def _sutherland(case, C_s):

@@ -86,6 +86,7 @@ CASES = {
     "small_sphere_sutherland": lambda: _sutherland(configs.small_sphere_case(), 0.5),   # Eq. 14 viscosity
     "hex_cavity_n3_dvs6": lambda: configs.cavity_case(n=3, nv_side=6, kind="hex"),        # warped hexahedra
     "mixed_box_n4_dvs5": lambda: configs.open_box_case(n=4, nv_side=5, kind="mixed"),     # hex + pyramid + tet
+    "small_sphere_hex": lambda: configs.small_sphere_hex_case(),                          # graded hex O-grid
 }
 
 
