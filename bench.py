@@ -349,6 +349,119 @@ def adjoint_check(gmres_iters=300, fd_rel=1e-3, fd_iters=400):
             "rel_diff_frozen_vs_fd": [(x - y) / abs(y) for x, y in zip(adj, fd)]}
 
 
+def _converge(s, tol, max_iter, chunk=100):
+    """Iterate until the residual (largest component) is below tol or stops falling (a rounding floor)."""
+    hist = []
+    done = 0
+    while done < max_iter:
+        h = s.iterate(chunk)
+        hist.append(h)
+        done += chunk
+        r = h.max(axis=1)
+        if r[-1] < tol or (len(hist) > 2 and r.min() >= 0.5 * hist[-2].max(axis=1).min()):
+            break
+    return np.concatenate(hist)
+
+
+def hex_sphere_converged(max_iter=1500):
+    """The sphere on its hexahedral O-grid, FP64 and mixed precision, each from rest to the paper's criterion
+    (FP64 below 1e-10, Sec. 4.1) or to its rounding floor (mixed), and the mixed fields against the FP64 ones."""
+    import torch
+
+    from paper_2303_10846_amd.binding import Solver
+    from paper_2303_10846_amd.cases import configs
+    case = configs.sphere_hex_case(seed=0)
+    out = {"workload": "sphere Ma 5 Kn 0.1 Tw/Tinf 3 on a hexahedral O-grid (48 384 hexahedra) x 4 140 velocities"}
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver(case, precision=prec, device="cuda:0")
+        s.init_equilibrium(case["W0"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = _converge(s, 1e-12 if prec == "fp64" else 1e-10, max_iter)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        r = h.max(axis=1)
+        W, _ = s.moments()
+        co = s.wall_coefficients(1, 1.0, case["U_inf"], 1.0, A_ref=math.pi * 0.25)
+        res[prec] = dict(W=W, Qw=s.wall_heat_flux(1))
+        out[prec] = {"iterations": len(r), "residual_last": float(r[-1]), "seconds": t,
+                     "ms_per_iteration": 1e3 * t / len(r),
+                     "iterations_to_1e-10": int(np.argmax(r < 1e-10)) + 1 if np.any(r < 1e-10) else None,
+                     "Qw": res[prec]["Qw"], "Cd": co["Cd"], "CQ": co["CQ"]}
+        print(f"bench: hex sphere {prec} {len(r)} iterations, residual {r[-1]:.2e}", file=sys.stderr, flush=True)
+        del s
+        torch.cuda.empty_cache()
+
+    def rho_T(W):
+        rho = W[:, 0]
+        ke = 0.5 * np.sum(W[:, 1:4] ** 2, axis=1) / rho
+        return rho, 0.4 * (W[:, 4] - ke) / (rho * 0.5)
+
+    rm, Tm = rho_T(res["mixed"]["W"])
+    rd, Td = rho_T(res["fp64"]["W"])
+    err = {"rho": float(np.max(np.abs(rm - rd)) / np.max(np.abs(rd))),
+           "T": float(np.max(np.abs(Tm - Td)) / np.max(np.abs(Td))),
+           "Qw": abs(res["mixed"]["Qw"] - res["fp64"]["Qw"]) / abs(res["fp64"]["Qw"])}
+    out["mixed_vs_fp64_converged"] = dict(err, matched_error=bool(max(err.values()) <= 1e-5))
+    return out
+
+
+def adjoint_check_hex(fd_rel=1e-6, gmres_iters=600):
+    """Discrete adjoint of the converged hexahedral sphere (FP64, residual below 1e-12) against central
+    differences of the converged heat load with step 1e-6 of each parameter, with the limiter differentiated on
+    its branch (limiter 1) and with its values stored at the converged state (limiter 3)."""
+    import torch
+
+    from paper_2303_10846_amd.binding import Solver
+    from paper_2303_10846_amd.cases import configs
+    case = configs.sphere_hex_case(seed=0)
+    s = Solver(case, precision="fp64", device="cuda:0")
+    s.init_equilibrium(case["W0"])
+    hist = _converge(s, 1e-13, 1500)
+    print(f"bench: hex adjoint check primal residual {hist[-1].max():.3e} after {len(hist)}", file=sys.stderr,
+          flush=True)
+    base = s.get_state()
+    p0 = s.params(1, 2)
+    out = {"check": "dQ_w/dp of the converged hexahedral sphere (Ma 5, Kn 0.1), p = (T_w, rho_inf, |U_inf|)",
+           "n_cells": s.nc, "n_vel": s.nv, "primal_iterations": len(hist), "primal_residual": float(hist[-1].max())}
+    for mode, lim in (("active_limiter", 1), ("stored_limiter", 3)):
+        s.set_state(*base)
+        s.set_params(p0, 1, 2)
+        if lim == 3:
+            s.freeze_limiter()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a = s.adjoint(1, 2, restart=60, max_iter=gmres_iters, rtol=1e-10, precond_pairs=2, macro_pairs=20)
+        t_adj = time.perf_counter() - t0
+        print(f"bench: hex adjoint {mode} {a['iterations']} iterations, relative residual {a['rel_residual']:.2e}",
+              file=sys.stderr, flush=True)
+        del a["lam"]
+        torch.cuda.empty_cache()
+        fd = []
+        for k in range(3):
+            h = fd_rel * abs(p0[k])
+            J = []
+            for sgn in (1, -1):
+                p = p0.copy()
+                p[k] += sgn * h
+                s.set_params(p, 1, 2)
+                s.set_state(*base)
+                hk = _converge(s, 1e-13, 800)
+                J.append(s.wall_heat_flux(1))
+                print(f"bench: hex adjoint check {mode} p[{k}] {sgn:+d}h residual {hk[-1].max():.2e}",
+                      file=sys.stderr, flush=True)
+            fd.append((J[0] - J[1]) / (2 * h))
+        s.set_params(p0, 1, 2)
+        if lim == 3:
+            s.unfreeze_limiter()
+        adj = [float(x) for x in a["dJdp"]]
+        out[mode] = {"dJdp_adjoint": adj, "gmres_iterations": a["iterations"], "rel_residual": a["rel_residual"],
+                     "adjoint_seconds": t_adj, "dJdp_central_differences": [float(x) for x in fd],
+                     "h_over_p": fd_rel, "rel_diff": [(x - y) / abs(y) for x, y in zip(adj, fd)], "J": a["J"]}
+    return out
+
+
 # Implicit-step schedule of a capsule run that starts from a converged macroscopic field (another DVS's)
 CAPSULE_WARM_RAMP = ((0, 10.0), (100, 30.0), (300, 100.0))
 
@@ -465,9 +578,12 @@ def main():
                     help="iterations (from rest) after which the two precisions' fields are compared")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["sphere", "capsule"], default="sphere",
-                    help="sphere (the headline workload) or the Ma 10 capsule (303k tets x 10.6k velocities, "
-                         "mixed precision only: its FP64 state does not fit one GPU)")
+    ap.add_argument("--workload", choices=["sphere", "capsule", "sphere_hex"], default="sphere",
+                    help="sphere (the headline workload), the Ma 10 capsule (303k tets x 10.6k velocities, "
+                         "mixed precision only: its FP64 state does not fit one GPU) or, for --adjoint-check, the "
+                         "sphere on its hexahedral O-grid")
+    ap.add_argument("--no-hex", action="store_true",
+                    help="leave out the converged hexahedral-sphere block of the default line")
     ap.add_argument("--dvs-study", type=int, default=0, metavar="ITERS",
                     help="instead of timing, run the sphere with six DVS sets for ITERS iterations each and print "
                          "the wall coefficients against the DVS")
@@ -496,7 +612,7 @@ def main():
         print(json.dumps(capsule_converge(args.capsule_converge)))
         return
     if args.adjoint_check:
-        print(json.dumps(adjoint_check()))
+        print(json.dumps(adjoint_check_hex() if args.workload == "sphere_hex" else adjoint_check()))
         return
     if args.dvs_study:
         print(json.dumps(dvs_study(args.dvs_study, args.workload)))
@@ -556,11 +672,17 @@ def main():
         err = {"rho": float(np.max(np.abs(rm - rd)) / np.max(np.abs(rd))),
                "T": float(np.max(np.abs(Tm - Td)) / np.max(np.abs(Td))),
                "Qw": abs(r["Qw"] - f["Qw"]) / abs(f["Qw"])}
-        line["mixed_vs_fp64"] = dict(err, iterations=r["iterations"], residual_mixed=r["residual_last"],
+        line["mixed_vs_fp64"] = dict(err, basis="fields after the same number of iterations from rest, both at the "
+                                     "limiter plateau of the tetrahedral mesh (residuals beside), mixed against the "
+                                     "FP64 GPU run; converged fields: converged_hex_sphere",
+                                     iterations=r["iterations"], residual_mixed=r["residual_last"],
                                      residual_fp64=f["residual_last"], Qw_fp64=f["Qw"],
                                      matched_error=bool(max(err.values()) <= 1e-5),
                                      iterations_to_residual_mixed=r["iterations_to"],
                                      iterations_to_residual_fp64=f["iterations_to"])
+    if args.workload == "sphere" and args.converge_iters and not args.no_hex:
+        print("bench: hexahedral sphere to convergence", file=sys.stderr, flush=True)
+        line["converged_hex_sphere"] = hex_sphere_converged()
     if not args.no_cpu and args.workload == "sphere":
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(case)
