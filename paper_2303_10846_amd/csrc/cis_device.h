@@ -21,6 +21,26 @@ __device__ inline int64_t xcd_block(int64_t w, int64_t n) {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Element k of a row whose base pointer is uniform over the workgroup, with the byte offset formed in 32 bits
+// (the scalar-base addressing form where the compiler can match it).  Callers keep k * sizeof(T) below 2^32
+// (the velocity count is bounded).
+template <class T> __device__ inline T ld_row(const T* row, uint32_t k) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + (uint64_t)(k * (uint32_t)sizeof(T)));
+}
+template <class T> __device__ inline T* at_row(T* row, uint32_t k) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(row) + (uint64_t)(k * (uint32_t)sizeof(T)));
+}
+// An empty asm statement (no instruction) that uses x in a VGPR: placed after a group of stores it keeps their
+// data and address registers live until the last store has issued.  A register that a pending store still
+// reads is otherwise reused for the next store, and the compiler then waits for every outstanding memory
+// operation before each store (vmcnt(0)).
+template <class T> __device__ inline void keep_live(const T& x) { asm volatile("" : : "v"(x)); }
+
+__device__ inline float vmin(float a, float b) { return fminf(a, b); }
+__device__ inline double vmin(double a, double b) { return fmin(a, b); }
+__device__ inline float vmax(float a, float b) { return fmaxf(a, b); }
+__device__ inline double vmax(double a, double b) { return fmax(a, b); }
+
 // ---------------------------------------------------------------------------
 // Reductions over a workgroup of NT threads (NT/64 wave64 wavefronts)
 // ---------------------------------------------------------------------------
@@ -33,9 +53,32 @@ __device__ inline void two_sum_add(double& s, double& c, double x) {
   s = t;
 }
 
+// One 64-bit value moved across lanes by a DPP control (two 32-bit data-parallel-primitive moves, all rows
+// enabled; a lane without a source receives 0).
+template <int Ctrl> __device__ inline double dpp_move(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, Ctrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), Ctrl, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum of x over the 64 lanes of a wavefront, valid in lane 63 (other lanes hold partial sums): quad exchanges
+// and rotations by 4 and 8 within each row of 16 lanes give every lane its row's sum; the broadcast of each
+// row's lane 15 into the next row, then of lane 31 into rows 2 and 3, completes the sum in row 3.  A fixed
+// pairwise order, with VALU moves instead of LDS permutes (a few cycles per step rather than an LDS round trip).
+__device__ inline double wave_sum_last(double x) {
+  x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_move<0x124>(x);  // row_ror:4
+  x += dpp_move<0x128>(x);  // row_ror:8
+  x += dpp_move<0x142>(x);  // row_bcast:15
+  x += dpp_move<0x143>(x);  // row_bcast:31
+  return x;
+}
+
 // N running FP64 sums per thread.  With Comp, every thread's running sum is compensated: the exact rounding
 // error of each addition (TwoSum) is accumulated beside it, over the long sequential part of the summation;
-// the 64 lanes of a wavefront are combined by a pairwise shuffle tree (error O(log2(64) eps)) and the
+// the 64 lanes of a wavefront are combined by a pairwise tree (error O(log2(64) eps)) and the
 // wavefronts' results again with compensation.  Without Comp the
 // running sums and the merge are plain FP64.
 template <int N, bool Comp, int NT> struct Acc {
@@ -60,10 +103,8 @@ template <int N, bool Comp, int NT> struct Acc {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      double a = Comp ? s[m] + c[m] : s[m];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-      if (lane == 0) red[wid * N + m] = a;
+      const double a = wave_sum_last(Comp ? s[m] + c[m] : s[m]);
+      if (lane == 63) red[wid * N + m] = a;
     }
     __syncthreads();
 #pragma unroll
@@ -86,10 +127,8 @@ template <int N, bool Comp, int NT> struct Acc {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      double a = Comp ? s[m] + c[m] : s[m];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-      if (lane == 0) red[wid * N + m] = a;
+      const double a = wave_sum_last(Comp ? s[m] + c[m] : s[m]);
+      if (lane == 63) red[wid * N + m] = a;
       __builtin_amdgcn_sched_barrier(0);  // one chain at a time: keeps the register peak low
     }
     __syncthreads();
@@ -181,11 +220,31 @@ __device__ inline void eq_coeffs(const Prim& p, const double* q, const GasC& g, 
   e[27] = 1.0 / g.Z;
 }
 
-// exp of the equilibrium evaluation.  The full-precision exp in both precisions: the hardware exponential's
-// FP32 error grows with |x| (x * log2(e) is rounded first) and moved the converged wall heat flux of the
-// mixed path by 1.3e-5 relative, through the tails of the velocity set.
+// exp of the equilibrium evaluation.  FP64: the library exp.  FP32: the hardware base-2 exponential of
+// t = fl(x log2 e), corrected by the rounding error of that product: with log2 e = L_hi + L_lo (L_hi the FP32
+// value nearest log2 e), e = (x L_hi - t) + x L_lo is formed exactly enough by two FMAs (the FMA-based exact
+// product error of Dekker's method), and exp(x) = 2^t 2^e ~ 2^t (1 + e ln 2), |e| < 2^-24 |t|.  Without the
+// correction the error grows with |x| (3.8e-6 relative at x = -87, which moved the converged mixed wall heat
+// flux by 1.3e-5); with it the error is that of the hardware 2^t plus one rounding (about 1.2e-7 relative
+// with a correctly rounded 2^t).  Six instructions instead of the library expf's ten; results below the FP32
+// normal range may flush to zero (values under 1.2e-38, against O(1) sums).
+#ifndef CIS_EXP_FAST
+#define CIS_EXP_FAST 0
+#endif
 __device__ inline double eq_exp(double x) { return exp(x); }
-__device__ inline float eq_exp(float x) { return expf(x); }
+__device__ inline float eq_exp(float x) {
+#if CIS_EXP_FAST
+  constexpr float kL2eHi = 1.44269502162933349609375f;  // FP32 nearest log2(e)
+  constexpr float kL2eLo = 1.925963e-8f;                 // log2(e) - kL2eHi
+  constexpr float kLn2 = 0.693147180559945309f;
+  const float t = x * kL2eHi;
+  const float e = __builtin_fmaf(x, kL2eLo, __builtin_fmaf(x, kL2eHi, -t));
+  const float r = __builtin_amdgcn_exp2f(t);
+  return __builtin_fmaf(r, e * kLn2, r);
+#else
+  return expf(x);
+#endif
+}
 
 template <class C> struct Eq {
   C Ux, Uy, Uz, qtx, qty, qtz, qrx, qry, qrz, a_tr, b_tr, a_T, b_T, ktr, kT, ktr_r, kT_r, iRTtr, iRT, RTrot, RT, z1,
@@ -229,6 +288,49 @@ template <class C> struct Eq {
     C Rrot = RT * (Grot + cqr * kT_r * gT);
     Gs = z1 * Gtr + z2 * Grot;
     Rs = z1 * Rtr + z2 * Rrot;
+  }
+};
+
+// The same G*, R* times a constant factor c (c = s/(tau+s) in the face step of Eq. 45), with the constants
+// combined once per face: c (1-1/Z) a_tr and c a_T/Z as the two exponentials' amplitudes, the Shakhov-type
+// factors in the form c2 k1 - k2, and the R* parts as RT_rot G_tr + RT G_rot + (c.q_rot)(m3 g_tr + m4 g_T).
+// Mathematically the same values as c * Eq::eval; 28 operations and two exponentials per velocity.
+template <class C> struct EqScaled {
+  C Ux, Uy, Uz, qtx, qty, qtz, qrx, qry, qrz, A1, nb1, A2, nb2, k1, k2, k3, k4, m1, m2, m3, m4;
+  __device__ inline void load(const double* e, double c) {
+    Ux = (C)e[1];
+    Uy = (C)e[2];
+    Uz = (C)e[3];
+    qtx = (C)e[8];
+    qty = (C)e[9];
+    qtz = (C)e[10];
+    qrx = (C)e[11];
+    qry = (C)e[12];
+    qrz = (C)e[13];
+    A1 = (C)(c * e[26] * e[14]);
+    nb1 = (C)(-e[15]);
+    A2 = (C)(c * e[27] * e[16]);
+    nb2 = (C)(-e[17]);
+    k1 = (C)(e[18] * e[22]);
+    k2 = (C)(5.0 * e[18]);
+    k3 = (C)(e[19] * e[23]);
+    k4 = (C)(5.0 * e[19]);
+    m1 = (C)e[24];
+    m2 = (C)e[25];
+    m3 = (C)(e[24] * e[20]);
+    m4 = (C)(e[25] * e[21]);
+  }
+  __device__ inline void eval(C ux, C uy, C uz, C& Gs, C& Rs) const {
+    const C cx = ux - Ux, cy = uy - Uy, cz = uz - Uz;
+    const C c2 = cx * cx + cy * cy + cz * cz;
+    const C cqt = cx * qtx + cy * qty + cz * qtz;
+    const C cqr = cx * qrx + cy * qry + cz * qrz;
+    const C g1 = A1 * eq_exp(c2 * nb1);
+    const C g2 = A2 * eq_exp(c2 * nb2);
+    const C Gt = g1 + g1 * (cqt * (c2 * k1 - k2));
+    const C Gr = g2 + g2 * (cqt * (c2 * k3 - k4));
+    Gs = Gt + Gr;
+    Rs = m1 * Gt + (m2 * Gr + cqr * (m3 * g1 + m4 * g2));
   }
 };
 

@@ -30,8 +30,9 @@
 namespace cis {
 
 // Velocities per thread in the (cell, chunk) kernels, chunk = kBlock * Vpt<T>: 2 in FP32, 1 in FP64 (measured
-// on the sphere workload: more velocities per thread raise the loads in flight but cost occupancy).  The
-// reconstruction and the scalar micro sweep take one in both precisions (kVptOne: measured faster in FP32).
+// on the sphere workload: more velocities per thread raise the loads in flight but cost occupancy; the
+// reconstruction: FP32 2.42 -> 2.31 ms with two, FP64 3.9 -> 5.5 ms).  The scalar micro sweep takes one in
+// both precisions (kVptOne: measured faster in FP32).
 // In the mixed mode the micro sweep and the micro residual have vector forms (k_micro_sweep_vec,
 // k_residual_vec) for an nv that is a multiple of 4 or 2.
 template <class T> struct Vpt;
@@ -137,12 +138,14 @@ __device__ inline double lim_div(double a, double b) { return a / b; }
 __device__ inline float lim_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // One distribution at one velocity: limited least-squares gradient of the cell and the upwind face values
-// (written at dst + frow[a] + k).  limiter 3 takes L from the frozen row Lin; Lcap (if set) receives L.
+// (written at dst[a] + k).  limiter 3 takes L from the frozen row Lin; Lcap (if set) receives L.
+// With d2_a = grad . (x_f - x_i) (the unlimited gradient's increment to face a, which the limiter needs anyway)
+// and ug = u . grad, the face value of Eq. 46 is phi + L (d2_a - s_f ug): two operations per face.
 template <class T, int NF>
 __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const T* wx, const T* wy, const T* wz,
                                    const T* fx, const T* fy, const T* fz, const T* sf, T kh3, int limiter,
-                                   const bool* up, T ux, T uy, T uz, T* dst, const int64_t* frow, int k,
-                                   const T* Lin, T* Lcap) {
+                                   const bool* up, T ux, T uy, T uz, T* const* dst, uint32_t k, const T* Lin,
+                                   T* Lcap) {
   T gx = 0, gy = 0, gz = 0, pmax = phi, pmin = phi;
 #pragma unroll
   for (int a = 0; a < NF; ++a) {
@@ -151,46 +154,59 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
     gx += wx[a] * dphi;
     gy += wy[a] * dphi;
     gz += wz[a] * dphi;
-    pmax = pn[a] > pmax ? pn[a] : pmax;
-    pmin = pn[a] < pmin ? pn[a] : pmin;
+    pmax = vmax(pmax, pn[a]);
+    pmin = vmin(pmin, pn[a]);
   }
+  T d2[NF];
+#pragma unroll
+  for (int a = 0; a < NF; ++a) d2[a] = gx * fx[a] + gy * fy[a] + gz * fz[a];
   T L = 1;
   if (limiter == 3) {
-    L = Lin[k];
+    L = ld_row(Lin, k);
   } else if (limiter) {  // 1, 2, and 4 (the smaller of this value and the stored one, stored back)
-    const T scale = fabs(pmax) > fabs(pmin) ? fabs(pmax) : fabs(pmin);
+    const T scale = vmax(fabs(pmax), fabs(pmin));
     const T eps2 = kh3 * scale * scale;
+    const T dmax = pmax - phi, dmin = pmin - phi;
     // Venkatakrishnan's function with the common factor d2 divided out of both parts:
     // psi = (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2), and psi = 1 where d2 = 0 (an unused
     // slot has zero geometry, so d2 = 0)
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
-      const T d2 = gx * fx[a] + gy * fy[a] + gz * fz[a];
-      if (d2 != T(0)) {
-        const T d1 = d2 > T(0) ? pmax - phi : pmin - phi;
-        const T d11 = d1 * d1, d12 = d1 * d2;
-        const T psi = lim_div(d11 + eps2 + T(2) * d12, d11 + T(2) * d2 * d2 + d12 + eps2);
-        L = psi < L ? psi : L;
+      if (d2[a] != T(0)) {  // skipped by a whole wavefront where the field is locally uniform
+        const T d1 = d2[a] > T(0) ? dmax : dmin;
+        const T dd = d2[a] + d2[a];
+        L = vmin(L, lim_div(d1 * (d1 + dd) + eps2, d1 * (d1 + d2[a]) + (dd * d2[a] + eps2)));
       }
     }
-    if (limiter == 4) L = Lin[k] < L ? Lin[k] : L;
+    if (limiter == 4) L = vmin(L, ld_row(Lin, k));
   }
-  if (Lcap) Lcap[k] = L;
-  gx *= L;
-  gy *= L;
-  gz *= L;
+  if (Lcap) *at_row(Lcap, k) = L;
+  const T ug = ux * gx + uy * gy + uz * gz;
+  // all face values and addresses first, then the stores, with every store's registers kept live to the last
+  // (measured: the kernel is 13% slower when the stores wait for one another)
+  T val[NF];
+  T* adr[NF];
 #pragma unroll
   for (int a = 0; a < NF; ++a) {
-    if (!up[a]) continue;
-    st_stream(dst + frow[a] + k, phi + (fx[a] - ux * sf[a]) * gx + (fy[a] - uy * sf[a]) * gy + (fz[a] - uz * sf[a]) * gz);
+    val[a] = phi + L * (d2[a] - sf[a] * ug);
+    adr[a] = at_row(dst[a], k);
+  }
+#pragma unroll
+  for (int a = 0; a < NF; ++a)
+    if (up[a]) st_stream(adr[a], val[a]);
+#pragma unroll
+  for (int a = 0; a < NF; ++a) {
+    keep_live(val[a]);
+    keep_live(adr[a]);
   }
 }
 
 // Every load of a thread's velocities is issued before its first store (the stores could alias later loads
-// as far as the compiler knows); per-cell geometry is converted once into registers.
+// as far as the compiler knows); per-cell geometry is converted once into registers.  Rows are addressed
+// from uniform base pointers with 32-bit element offsets.
 template <class T, int NF> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b, T* cap) {
   using L = Lay<NF>;
-  constexpr int U = kVptOne;
+  constexpr int U = Vpt<T>::v;
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
   const int64_t i = d.spatial[cc.cell];
@@ -198,17 +214,20 @@ template <class T, int NF> __global__ __launch_bounds__(kBlock) void k_recon(Dev
   const double* geo = d.cell_geo + L::CG * i;
   const T* G = (const T*)b.G;
   const T* R = (const T*)b.R;
-  T* FG = (T*)b.faceG;
-  T* FR = (T*)b.faceR;
   int32_t nb[NF];
-  int64_t srow[NF], frow[NF];  // element offsets of the neighbour rows and the face rows (shared by G and R)
+  const T *rowG[NF], *rowR[NF];  // neighbour rows (the cell's own row at a boundary face)
+  T *dstG[NF], *dstR[NF];        // face rows
   bool own[NF];
   T wx[NF], wy[NF], wz[NF], fx[NF], fy[NF], fz[NF], sf[NF];
 #pragma unroll
   for (int a = 0; a < NF; ++a) {
     nb[a] = d.cell_nb[NF * i + a];
-    srow[a] = (int64_t)(nb[a] >= 0 ? nb[a] : i) * nv;
-    frow[a] = (int64_t)d.cell_face[NF * i + a] * nv;  // unused slot: never written (its code is 0)
+    const int64_t srow = (int64_t)(nb[a] >= 0 ? nb[a] : i) * nv;
+    rowG[a] = G + srow;
+    rowR[a] = R + srow;
+    const int64_t frow = (int64_t)d.cell_face[NF * i + a] * nv;  // unused slot: never written (its code is 0)
+    dstG[a] = (T*)b.faceG + frow;
+    dstR[a] = (T*)b.faceR + frow;
     const double* s = geo + CG_FACE + CG_SLOT * a;
     own[a] = s[0] > 0.0;
     if constexpr (std::is_same<T, float>::value) {
@@ -243,32 +262,31 @@ template <class T, int NF> __global__ __launch_bounds__(kBlock) void k_recon(Dev
   // limiter 4 writes the smaller value back in place (each (cell, velocity) entry has one thread)
   T* capG = cap ? cap + self : limiter == 4 ? (T*)d.lim_frozen + self : nullptr;
   T* capR = cap ? cap + P + self : limiter == 4 ? (T*)d.lim_frozen + P + self : nullptr;
-  const int nvi = (int)nv;
-  const int k0 = (int)cc.chunk * (kBlock * U) + (int)threadIdx.x;
+  const T* selfG = G + self;
+  const T* selfR = R + self;
+  const T* ux_row = std::is_same<T, float>::value ? (const T*)d.dvs_f : (const T*)d.dvs;
+  const T* uy_row = ux_row + nv;
+  const T* uz_row = ux_row + 2 * nv;
+  const typename L::Code* upw = reinterpret_cast<const typename L::Code*>(d.upw) + self;
+  const uint32_t nvi = (uint32_t)nv;
+  const uint32_t k0 = (uint32_t)cc.chunk * (kBlock * U) + threadIdx.x;
   T pG[U], pR[U], nG[U][NF], nR[U][NF], tx[U], ty[U], tz[U];
   unsigned code[U];
   bool up[U][NF];
-  const typename L::Code* upw = reinterpret_cast<const typename L::Code*>(d.upw);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int k = k0 + u * kBlock;
+    const uint32_t k = k0 + u * kBlock;
     if (k >= nvi) continue;
-    code[u] = upw[self + k];
-    if constexpr (std::is_same<T, float>::value) {
-      tx[u] = d.dvs_f[k];
-      ty[u] = d.dvs_f[nv + k];
-      tz[u] = d.dvs_f[2 * nv + k];
-    } else {
-      tx[u] = d.dvs[k];
-      ty[u] = d.dvs[nv + k];
-      tz[u] = d.dvs[2 * nv + k];
-    }
-    pG[u] = G[self + k];
-    pR[u] = R[self + k];
+    code[u] = ld_row(upw, k);
+    tx[u] = ld_row(ux_row, k);
+    ty[u] = ld_row(uy_row, k);
+    tz[u] = ld_row(uz_row, k);
+    pG[u] = ld_row(selfG, k);
+    pR[u] = ld_row(selfR, k);
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
-      nG[u][a] = G[srow[a] + k];
-      nR[u][a] = R[srow[a] + k];
+      nG[u][a] = ld_row(rowG[a], k);
+      nR[u][a] = ld_row(rowR[a], k);
     }
   }
   // upwind cell of the face for this velocity: the owner when u.n_face > 0, else the neighbour (a tie goes to
@@ -284,20 +302,20 @@ template <class T, int NF> __global__ __launch_bounds__(kBlock) void k_recon(Dev
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int k = k0 + u * kBlock;
+    const uint32_t k = k0 + u * kBlock;
     if (k >= nvi) continue;
-    recon_write<T, NF>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FG, frow, k,
-                   LinG, capG);
-    recon_write<T, NF>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u], FR, frow, k,
-                   LinR, capR);
+    recon_write<T, NF>(pG[u], nG[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u],
+                       dstG, k, LinG, capG);
+    recon_write<T, NF>(pR[u], nR[u], nb, wx, wy, wz, fx, fy, fz, sf, kh3, limiter, up[u], tx[u], ty[u], tz[u],
+                       dstR, k, LinR, capR);
   }
 }
 
 template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st, void* cap) {
   if (d.mf == 4)
-    hipLaunchKernelGGL((k_recon<T, 4>), cell_chunk_grid_u<kVptOne>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, (T*)cap);
+    hipLaunchKernelGGL((k_recon<T, 4>), cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, (T*)cap);
   else
-    hipLaunchKernelGGL((k_recon<T, kMaxFaces>), cell_chunk_grid_u<kVptOne>(d.nc, d.nv), dim3(kBlock), 0, st, d, b,
+    hipLaunchKernelGGL((k_recon<T, kMaxFaces>), cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b,
                        (T*)cap);
 }
 
@@ -332,7 +350,8 @@ template <class F> __device__ inline void k_loop(int64_t nv, F&& body) {
 // The same loop with the loads of P velocities per thread issued before any of their arithmetic:
 // load(k, q) fills the registers of slot q (loads only), body(k, q) consumes them.  A face workgroup that
 // loops over a whole row is otherwise bound by one memory round trip per trip (measured: face kernel -12%;
-// the update kernel loses occupancy with it and is not faster).  P = 4 in FP32, 2 in FP64 (registers).
+// the update kernel loses occupancy with it and is not faster).  P = 4 in FP32 (2 and 8 measured slower on the
+// sphere: face 3.38 and 3.76 ms against 3.22), 2 in FP64 (registers).
 template <class T> struct Prefetch { static constexpr int v = sizeof(T) == 4 ? 4 : 2; };
 template <int P, class L, class B> __device__ inline void k_loop_pf(int64_t nv, L&& load, B&& body) {
   const int n = (int)nv;
@@ -477,9 +496,9 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     __shared__ double sh_ec[ER];
     if (threadIdx.x == 0) face_state_coeffs(sh_m, U0, s, g, sh_ec);
     __syncthreads();
-    Eq<T> e;
-    e.load(sh_ec);
-    const T ct = (T)sh_ec[28], cs = (T)sh_ec[29];
+    EqScaled<T> e;  // s/(tau+s) times the face equilibrium
+    e.load(sh_ec, sh_ec[29]);
+    const T ct = (T)sh_ec[28];
     // pass 2: phi_f (Eq. 45), micro flux and macro flux.  The upwind side (with its tie rule) is the owner's
     // upwind code, as in the reconstruction, and u.n is the plain FP64 product; |u|^2/2 is formed in registers
     // (fewer cached DVS loads per velocity).
@@ -503,8 +522,8 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       const double ux = px[q], uy = py[q], uz = pz[q], vw = pw[q];
       T gs, rs;
       e.eval((T)ux, (T)uy, (T)uz, gs, rs);
-      const T gf = ct * gb + cs * gs;
-      const T rf = ct * rb + cs * rs;
+      const T gf = ct * gb + gs;
+      const T rf = ct * rb + rs;
       const double un = ((pc[q] >> (2 * slot)) & 3u) == 0u ? 0.0 : ux * nx + uy * ny + uz * nz;
       rowG[k] = (T)(A * un) * gf;
       rowR[k] = (T)(A * un) * rf;
