@@ -228,12 +228,8 @@ __device__ inline void eq_coeffs(const Prim& p, const double* q, const GasC& g, 
 // flux by 1.3e-5); with it the error is that of the hardware 2^t plus one rounding (about 1.2e-7 relative
 // with a correctly rounded 2^t).  Six instructions instead of the library expf's ten; results below the FP32
 // normal range may flush to zero (values under 1.2e-38, against O(1) sums).
-#ifndef CIS_EXP_FAST
-#define CIS_EXP_FAST 0
-#endif
 __device__ inline double eq_exp(double x) { return exp(x); }
 __device__ inline float eq_exp(float x) {
-#if CIS_EXP_FAST
   constexpr float kL2eHi = 1.44269502162933349609375f;  // FP32 nearest log2(e)
   constexpr float kL2eLo = 1.925963e-8f;                 // log2(e) - kL2eHi
   constexpr float kLn2 = 0.693147180559945309f;
@@ -241,63 +237,15 @@ __device__ inline float eq_exp(float x) {
   const float e = __builtin_fmaf(x, kL2eLo, __builtin_fmaf(x, kL2eHi, -t));
   const float r = __builtin_amdgcn_exp2f(t);
   return __builtin_fmaf(r, e * kLn2, r);
-#else
-  return expf(x);
-#endif
 }
 
+// G*, R* of Eqs. 17-23 times a constant factor c (c = 1, or c = s/(tau+s) in the face step of Eq. 45), with
+// the constants combined once per cell or face: c (1-1/Z) a_tr and c a_T/Z as the two exponentials'
+// amplitudes, the Shakhov-type factors in the form c^2 k1 - k2 of the peculiar speed, and the R* parts as
+// RT_rot G_tr + RT G_rot + (c.q_rot)(m3 g_tr + m4 g_T).  28 operations and two exponentials per velocity.
 template <class C> struct Eq {
-  C Ux, Uy, Uz, qtx, qty, qtz, qrx, qry, qrz, a_tr, b_tr, a_T, b_T, ktr, kT, ktr_r, kT_r, iRTtr, iRT, RTrot, RT, z1,
-      z2;
-  __device__ inline void load(const double* e) {
-    Ux = (C)e[1];
-    Uy = (C)e[2];
-    Uz = (C)e[3];
-    qtx = (C)e[8];
-    qty = (C)e[9];
-    qtz = (C)e[10];
-    qrx = (C)e[11];
-    qry = (C)e[12];
-    qrz = (C)e[13];
-    a_tr = (C)e[14];
-    b_tr = (C)e[15];
-    a_T = (C)e[16];
-    b_T = (C)e[17];
-    ktr = (C)e[18];
-    kT = (C)e[19];
-    ktr_r = (C)e[20];
-    kT_r = (C)e[21];
-    iRTtr = (C)e[22];
-    iRT = (C)e[23];
-    RTrot = (C)e[24];
-    RT = (C)e[25];
-    z1 = (C)e[26];
-    z2 = (C)e[27];
-  }
-  // G*, R* at velocity u (Eqs. 17-23)
-  __device__ inline void eval(C ux, C uy, C uz, C& Gs, C& Rs) const {
-    C cx = ux - Ux, cy = uy - Uy, cz = uz - Uz;
-    C c2 = cx * cx + cy * cy + cz * cz;
-    C cqt = cx * qtx + cy * qty + cz * qtz;
-    C cqr = cx * qrx + cy * qry + cz * qrz;
-    C gtr = a_tr * eq_exp(-c2 * b_tr);
-    C gT = a_T * eq_exp(-c2 * b_T);
-    C Gtr = gtr * (C(1) + cqt * ktr * (c2 * iRTtr - C(5)));
-    C Grot = gT * (C(1) + cqt * kT * (c2 * iRT - C(5)));
-    C Rtr = RTrot * (Gtr + cqr * ktr_r * gtr);
-    C Rrot = RT * (Grot + cqr * kT_r * gT);
-    Gs = z1 * Gtr + z2 * Grot;
-    Rs = z1 * Rtr + z2 * Rrot;
-  }
-};
-
-// The same G*, R* times a constant factor c (c = s/(tau+s) in the face step of Eq. 45), with the constants
-// combined once per face: c (1-1/Z) a_tr and c a_T/Z as the two exponentials' amplitudes, the Shakhov-type
-// factors in the form c2 k1 - k2, and the R* parts as RT_rot G_tr + RT G_rot + (c.q_rot)(m3 g_tr + m4 g_T).
-// Mathematically the same values as c * Eq::eval; 28 operations and two exponentials per velocity.
-template <class C> struct EqScaled {
   C Ux, Uy, Uz, qtx, qty, qtz, qrx, qry, qrz, A1, nb1, A2, nb2, k1, k2, k3, k4, m1, m2, m3, m4;
-  __device__ inline void load(const double* e, double c) {
+  __device__ inline void load(const double* e, double c = 1.0) {
     Ux = (C)e[1];
     Uy = (C)e[2];
     Uz = (C)e[3];

@@ -496,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     __shared__ double sh_ec[ER];
     if (threadIdx.x == 0) face_state_coeffs(sh_m, U0, s, g, sh_ec);
     __syncthreads();
-    EqScaled<T> e;  // s/(tau+s) times the face equilibrium
+    Eq<T> e;  // s/(tau+s) times the face equilibrium
     e.load(sh_ec, sh_ec[29]);
     const T ct = (T)sh_ec[28];
     // pass 2: phi_f (Eq. 45), micro flux and macro flux.  The upwind side (with its tie rule) is the owner's
