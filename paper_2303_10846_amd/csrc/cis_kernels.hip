@@ -324,7 +324,8 @@ template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st
 // collision-coupled face distribution (Eq. 45), micro flux A (u.n) phi_f (written in place over phi_bar)
 // and the face's macro flux A sum_k w (u.n) Phi phi_f (Eq. 37).  Boundary faces: diffuse wall with rho_w
 // from zero net mass flux, or far-field Maxwellian, for incoming velocities.  phi_bar is staged in LDS
-// (UseLds) or re-read from global memory in pass 2; the interior passes issue the loads of Prefetch<T>
+// (Stage = 2: G and R, 1: G only, 0: neither) or re-read from global memory in pass 2; the interior passes issue
+// the loads of Prefetch<T>
 // velocities per thread before their arithmetic, the other velocity loops kUnroll per trip.  The face sums are plain FP64 (each face flux is computed once and applied with opposite signs to its two
 // cells, so conservation does not depend on their rounding; compensating them was measured at +40% face time).
 // ---------------------------------------------------------------------------
@@ -422,11 +423,11 @@ __device__ inline void face_state_coeffs(const double* m, const double* U0, doub
   ec[29] = s / (tau + s);
 }
 
-template <class T, bool UseLds, int NF>
+template <class T, int Stage, int NF>
 __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   extern __shared__ unsigned char smem_raw[];
   T* sG = reinterpret_cast<T*>(smem_raw);
-  T* sR = sG + d.nv;
+  T* sR = sG + d.nv;  // Stage 2 only
   __shared__ double red[(kBlock / 64) * 6];
   __shared__ double red17[(kBlock / 64) * 17];
   const int64_t f = blockIdx.x;
@@ -465,10 +466,8 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       pw[q] = V.w[k];
     }, [&](int k, int q) {
       const T gb = pg[q], rb = pr[q];
-      if (UseLds) {
-        sG[k] = gb;
-        sR[k] = rb;
-      }
+      if (Stage >= 1) sG[k] = gb;
+      if (Stage == 2) sR[k] = rb;
       const double vx = px[q] - U0[0], vy = py[q] - U0[1], vz = pz[q] - U0[2], w = pw[q];
       const double wg = w * (double)gb, wr = w * (double)rb;
       const double gx = wg * vx, gy = wg * vy, gz = wg * vz, v2 = vx * vx + vy * vy + vz * vz;
@@ -510,8 +509,8 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     acc.zero();
     unsigned pc[P];
     k_loop_pf<P>(nv, [&](int k, int q) {
-      pg[q] = UseLds ? sG[k] : rowG[k];
-      pr[q] = UseLds ? sR[k] : rowR[k];
+      pg[q] = Stage >= 1 ? sG[k] : rowG[k];
+      pr[q] = Stage == 2 ? sR[k] : rowR[k];
       px[q] = V.ux[k];
       py[q] = V.uy[k];
       pz[q] = V.uz[k];
@@ -591,20 +590,26 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   if (threadIdx.x < 6) w.face_mac[6 * f + threadIdx.x] = A * tot[threadIdx.x];
 }
 
-// phi_bar of one face is staged in LDS when the row takes at most 40 KB, so that four face workgroups still
-// share a CU (160 KB of LDS); a longer row is re-read from global memory (the caches) in pass 2.  Measured on
-// the sphere (4140 velocities): FP32 rows (33 KB) are faster staged, FP64 rows (66 KB) faster re-read.
+// phi_bar of one face is staged in LDS as far as it fits in 40 KB, so that four face workgroups still share a
+// CU (160 KB of LDS): G and R (FP32 rows of the sphere, 33 KB), else G alone (FP64 rows of the sphere: pass 2
+// re-reads only R from global memory), else neither.  Measured on the sphere (4140 velocities): FP32 rows are
+// faster staged; staging both FP64 rows (66 KB, two workgroups per CU) was slower than re-reading both.
 constexpr int64_t kLdsStageMax = 40 * 1024;
 
-template <class T> static bool face_lds_ok(int64_t nv) { return nv * 2 * (int64_t)sizeof(T) <= kLdsStageMax; }
+template <class T> static int face_stage(int64_t nv) {
+  const int64_t row = nv * (int64_t)sizeof(T);
+  return 2 * row <= kLdsStageMax ? 2 : row <= kLdsStageMax ? 1 : 0;
+}
 
 template <class T, int NF> void launch_face_nf(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
-  if (face_lds_ok<T>(d.nv)) {
-    size_t lds = (size_t)d.nv * 2 * sizeof(T);
-    hipLaunchKernelGGL((k_face<T, true, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
-  } else {
-    hipLaunchKernelGGL((k_face<T, false, NF>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, w);
-  }
+  const int stage = face_stage<T>(d.nv);
+  const size_t lds = (size_t)d.nv * stage * sizeof(T);
+  if (stage == 2)
+    hipLaunchKernelGGL((k_face<T, 2, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
+  else if (stage == 1)
+    hipLaunchKernelGGL((k_face<T, 1, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
+  else
+    hipLaunchKernelGGL((k_face<T, 0, NF>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, w);
 }
 
 template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
