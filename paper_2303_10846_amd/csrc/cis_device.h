@@ -62,23 +62,62 @@ template <int Ctrl> __device__ inline double dpp_move(double x) {
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Sum of x over the 64 lanes of a wavefront, valid in lane 63 (other lanes hold partial sums): quad exchanges
-// and rotations by 4 and 8 within each row of 16 lanes give every lane its row's sum; the broadcast of each
-// row's lane 15 into the next row, then of lane 31 into rows 2 and 3, completes the sum in row 3.  A fixed
-// pairwise order, with VALU moves instead of LDS permutes (a few cycles per step rather than an LDS round trip).
-__device__ inline double wave_sum_last(double x) {
-  x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
-  x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
-  x += dpp_move<0x124>(x);  // row_ror:4
-  x += dpp_move<0x128>(x);  // row_ror:8
-  x += dpp_move<0x142>(x);  // row_bcast:15
-  x += dpp_move<0x143>(x);  // row_bcast:31
-  return x;
+// The wavefront sums of N values per lane, written to dst[0..N) (LDS) by one lane each.  Recursive halving:
+// the gfx950 lane swaps exchange half of two registers at a time (permlane32_swap: lanes 32-63 of the first
+// with lanes 0-31 of the second; permlane16_swap: the odd 16-lane rows of the first with the even rows of the
+// second), so one swap and one add fold two values over 32 lanes, then pairs of those over 16 lanes; DPP
+// rotations and quad permutations finish each 16-lane row.  For N = 17 that is 102 VALU instructions per
+// wavefront instead of 306 with a DPP tree per value.  A fixed pairwise order (deterministic).
+typedef unsigned int cis_u32x2 __attribute__((ext_vector_type(2)));
+template <bool Half32> __device__ inline void lane_swap(double& x, double& y) {
+  const uint64_t ux = __builtin_bit_cast(uint64_t, x), uy = __builtin_bit_cast(uint64_t, y);
+  cis_u32x2 lo, hi;
+  if (Half32) {
+    lo = __builtin_amdgcn_permlane32_swap((uint32_t)ux, (uint32_t)uy, false, false);
+    hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ux >> 32), (uint32_t)(uy >> 32), false, false);
+  } else {
+    lo = __builtin_amdgcn_permlane16_swap((uint32_t)ux, (uint32_t)uy, false, false);
+    hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ux >> 32), (uint32_t)(uy >> 32), false, false);
+  }
+  x = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+  y = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
+template <int N> __device__ inline void wave_sums(const double* v, double* dst) {
+  constexpr int M1 = (N + 1) / 2, M2 = (M1 + 1) / 2;
+  // p[j]: lanes 0-31 hold value 2j, lanes 32-63 value 2j+1 (each summed over lanes l and l+32); an odd last
+  // value is paired with itself (its copy has index N and is not written)
+  double p[M1];
+#pragma unroll
+  for (int j = 0; j < M1; ++j) {
+    double x = v[2 * j], y = 2 * j + 1 < N ? v[2 * j + 1] : v[2 * j];
+    lane_swap<true>(x, y);
+    p[j] = x + y;
+  }
+  // q[i]: rows 0, 1, 2, 3 hold values 4i, 4i+2, 4i+1, 4i+3 (each summed over four lanes)
+  double q[M2];
+#pragma unroll
+  for (int i = 0; i < M2; ++i) {
+    double x = p[2 * i], y = 2 * i + 1 < M1 ? p[2 * i + 1] : p[2 * i];
+    lane_swap<false>(x, y);
+    q[i] = x + y;
+  }
+  const int lane = threadIdx.x & 63, r = lane >> 4;
+  const int slot = r == 1 ? 2 : r == 2 ? 1 : r;
+#pragma unroll
+  for (int i = 0; i < M2; ++i) {
+    double x = q[i];
+    x += dpp_move<0x128>(x);  // row_ror:8
+    x += dpp_move<0x124>(x);  // row_ror:4
+    x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+    x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    const int m = 4 * i + slot;
+    if ((lane & 15) == 0 && m < N) dst[m] = x;
+  }
 }
 
 // N running FP64 sums per thread.  With Comp, every thread's running sum is compensated: the exact rounding
 // error of each addition (TwoSum) is accumulated beside it, over the long sequential part of the summation;
-// the 64 lanes of a wavefront are combined by a pairwise tree (error O(log2(64) eps)) and the
+// the 64 lanes of a wavefront are combined by a pairwise tree (wave_sums; error O(log2(64) eps)) and the
 // wavefronts' results again with compensation.  Without Comp the
 // running sums and the merge are plain FP64.
 template <int N, bool Comp, int NT> struct Acc {
@@ -100,12 +139,11 @@ template <int N, bool Comp, int NT> struct Acc {
   }
   // Block-wide totals, identical in every thread.  red: NW * N doubles of LDS.
   __device__ inline void reduce(double* out, double* red) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wid = threadIdx.x >> 6;
+    double v[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      const double a = wave_sum_last(Comp ? s[m] + c[m] : s[m]);
-      if (lane == 63) red[wid * N + m] = a;
-    }
+    for (int m = 0; m < N; ++m) v[m] = Comp ? s[m] + c[m] : s[m];
+    wave_sums<N>(v, red + wid * N);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < N; ++m) {
@@ -124,13 +162,11 @@ template <int N, bool Comp, int NT> struct Acc {
   // The same totals written to LDS by thread 0 only (sh_out: N doubles), for a block that hands them to one
   // thread: the totals are then not live in every thread's registers.
   __device__ inline void reduce_to_lds(double* sh_out, double* red) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wid = threadIdx.x >> 6;
+    double v[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      const double a = wave_sum_last(Comp ? s[m] + c[m] : s[m]);
-      if (lane == 63) red[wid * N + m] = a;
-      __builtin_amdgcn_sched_barrier(0);  // one chain at a time: keeps the register peak low
-    }
+    for (int m = 0; m < N; ++m) v[m] = Comp ? s[m] + c[m] : s[m];
+    wave_sums<N>(v, red + wid * N);
     __syncthreads();
     if (threadIdx.x < N) {
       const int m = threadIdx.x;
