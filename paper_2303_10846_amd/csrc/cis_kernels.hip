@@ -423,11 +423,39 @@ __device__ inline void face_state_coeffs(const double* m, const double* U0, doub
   ec[29] = s / (tau + s);
 }
 
+// Stage 3: G, R and the owner's upwind codes are copied into LDS by LDS-DMA loads (global_load_lds), all
+// issued before any arithmetic, so the row costs one memory round trip instead of one per loop trip.
+typedef __attribute__((address_space(1))) const void* GlobalPtr;
+typedef __attribute__((address_space(3))) void* LdsPtr;
+
+// Copy n bytes (n a multiple of 4 * Dw, src and dst aligned to 4 * Dw bytes) from global memory into LDS with
+// LDS-DMA loads of Dw dwords per lane: wavefront w of the block copies 64-lane blocks w, w + 4, ...; a lane
+// past the end is inactive and writes nothing.
+template <int Dw> __device__ inline void lds_dma_copy(const void* src, void* dst, int64_t n) {
+  static_assert(Dw == 1 || Dw == 4, "LDS-DMA loads of 4 or 16 bytes per lane");
+  constexpr int kLane = 4 * Dw, kWave = 64 * kLane;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t nblk = (n + kWave - 1) / kWave;
+  for (int64_t blk = wid; blk < nblk; blk += kBlock / 64) {
+    const int64_t off = blk * kWave + (int64_t)lane * kLane;
+    if (off < n) {
+      const GlobalPtr g = (GlobalPtr)((const char*)src + off);
+      const LdsPtr l = (LdsPtr)((char*)dst + blk * kWave);
+      if constexpr (Dw == 4)
+        __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+      else
+        __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+    }
+  }
+}
+
 template <class T, int Stage, int NF>
 __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
-  extern __shared__ unsigned char smem_raw[];
+  using Code = typename Lay<NF>::Code;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sG = reinterpret_cast<T*>(smem_raw);
-  T* sR = sG + d.nv;  // Stage 2 only
+  T* sR = sG + d.nv;                                // Stage >= 2
+  Code* sC = reinterpret_cast<Code*>(sR + d.nv);  // Stage 3
   __shared__ double red[(kBlock / 64) * 6];
   __shared__ double red17[(kBlock / 64) * 17];
   const int64_t f = blockIdx.x;
@@ -452,21 +480,30 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     const double* Wn = b.W + 6 * (int64_t)d.face_cell[2 * f + 1];
     const double U0[3] = {0.5 * (Wo[1] / Wo[0] + Wn[1] / Wn[0]), 0.5 * (Wo[2] / Wo[0] + Wn[2] / Wn[0]),
                           0.5 * (Wo[3] / Wo[0] + Wn[3] / Wn[0])};
+    const int64_t own = d.face_cell[2 * f];
+    const Code* code = reinterpret_cast<const Code*>(d.upw) + own * nv;
+    if constexpr (Stage == 3) {
+      lds_dma_copy<4>(rowG, sG, nv * (int64_t)sizeof(T));
+      lds_dma_copy<4>(rowR, sR, nv * (int64_t)sizeof(T));
+      lds_dma_copy<1>(code, sC, nv * (int64_t)sizeof(Code));
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
     Acc<17, false, kBlock> a17;
     a17.zero();
     constexpr int P = Prefetch<T>::v;
     T pg[P], pr[P];
     double px[P], py[P], pz[P], pw[P];
     k_loop_pf<P>(nv, [&](int k, int q) {
-      pg[q] = rowG[k];
-      pr[q] = rowR[k];
+      pg[q] = Stage == 3 ? sG[k] : rowG[k];
+      pr[q] = Stage == 3 ? sR[k] : rowR[k];
       px[q] = V.ux[k];
       py[q] = V.uy[k];
       pz[q] = V.uz[k];
       pw[q] = V.w[k];
     }, [&](int k, int q) {
       const T gb = pg[q], rb = pr[q];
-      if (Stage >= 1) sG[k] = gb;
+      if (Stage == 1 || Stage == 2) sG[k] = gb;
       if (Stage == 2) sR[k] = rb;
       const double vx = px[q] - U0[0], vy = py[q] - U0[1], vz = pz[q] - U0[2], w = pw[q];
       const double wg = w * (double)gb, wr = w * (double)rb;
@@ -501,21 +538,19 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     // pass 2: phi_f (Eq. 45), micro flux and macro flux.  The upwind side (with its tie rule) is the owner's
     // upwind code, as in the reconstruction, and u.n is the plain FP64 product; |u|^2/2 is formed in registers
     // (fewer cached DVS loads per velocity).
-    const int64_t own = d.face_cell[2 * f];
     int slot = 0;
     for (int a = 1; a < NF; ++a)
       if (d.cell_face[NF * own + a] == (int32_t)f) slot = a;
-    const typename Lay<NF>::Code* code = reinterpret_cast<const typename Lay<NF>::Code*>(d.upw) + own * nv;
     acc.zero();
     unsigned pc[P];
     k_loop_pf<P>(nv, [&](int k, int q) {
       pg[q] = Stage >= 1 ? sG[k] : rowG[k];
-      pr[q] = Stage == 2 ? sR[k] : rowR[k];
+      pr[q] = Stage >= 2 ? sR[k] : rowR[k];
       px[q] = V.ux[k];
       py[q] = V.uy[k];
       pz[q] = V.uz[k];
       pw[q] = V.w[k];
-      pc[q] = code[k];
+      pc[q] = Stage == 3 ? sC[k] : code[k];
     }, [&](int k, int q) {
       const T gb = pg[q], rb = pr[q];
       const double ux = px[q], uy = py[q], uz = pz[q], vw = pw[q];
@@ -596,15 +631,24 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
 // faster staged; staging both FP64 rows (66 KB, two workgroups per CU) was slower than re-reading both.
 constexpr int64_t kLdsStageMax = 40 * 1024;
 
-template <class T> static int face_stage(int64_t nv) {
+template <class T, int NF> static int face_stage(const Dev& d, const Bufs& b) {
+  const int64_t nv = d.nv;
   const int64_t row = nv * (int64_t)sizeof(T);
+  // LDS-DMA staging needs 16-byte aligned rows (aligned arrays, nv a multiple of 4), 4-byte aligned code rows
+  // and room for the code row
+  const int64_t code_row = nv * (int64_t)sizeof(typename Lay<NF>::Code);
+  const bool aligned = (uintptr_t)b.faceG % 16 == 0 && (uintptr_t)b.faceR % 16 == 0 && (uintptr_t)d.upw % 4 == 0;
+  if (aligned && nv % 4 == 0 && 2 * row + code_row <= kLdsStageMax) return 3;
   return 2 * row <= kLdsStageMax ? 2 : row <= kLdsStageMax ? 1 : 0;
 }
 
 template <class T, int NF> void launch_face_nf(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
-  const int stage = face_stage<T>(d.nv);
-  const size_t lds = (size_t)d.nv * stage * sizeof(T);
-  if (stage == 2)
+  const int stage = face_stage<T, NF>(d, b);
+  const size_t lds = (size_t)d.nv * std::min(stage, 2) * sizeof(T) +
+                     (stage == 3 ? (size_t)d.nv * sizeof(typename Lay<NF>::Code) : 0);
+  if (stage == 3)
+    hipLaunchKernelGGL((k_face<T, 3, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
+  else if (stage == 2)
     hipLaunchKernelGGL((k_face<T, 2, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
   else if (stage == 1)
     hipLaunchKernelGGL((k_face<T, 1, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
