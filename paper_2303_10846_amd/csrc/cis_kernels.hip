@@ -146,7 +146,10 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
                                    const T* fx, const T* fy, const T* fz, const T* sf, T kh3, int limiter,
                                    const bool* up, T ux, T uy, T uz, T* const* dst, uint32_t k, const T* Lin,
                                    T* Lcap) {
-  T gx = 0, gy = 0, gz = 0, pmax = phi, pmin = phi;
+  // dmax, dmin: the largest and smallest neighbour difference, or 0 (max_a phi_a - phi and min_a phi_a - phi
+  // over the cell and its neighbours; taken over the differences, which need no NaN canonicalisation as the
+  // loaded values would)
+  T gx = 0, gy = 0, gz = 0, dmax = 0, dmin = 0;
 #pragma unroll
   for (int a = 0; a < NF; ++a) {
     if (nb[a] < 0) continue;
@@ -154,8 +157,8 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
     gx += wx[a] * dphi;
     gy += wy[a] * dphi;
     gz += wz[a] * dphi;
-    pmax = vmax(pmax, pn[a]);
-    pmin = vmin(pmin, pn[a]);
+    dmax = vmax(dmax, dphi);
+    dmin = vmin(dmin, dphi);
   }
   T d2[NF];
 #pragma unroll
@@ -164,9 +167,8 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
   if (limiter == 3) {
     L = ld_row(Lin, k);
   } else if (limiter) {  // 1, 2, and 4 (the smaller of this value and the stored one, stored back)
-    const T scale = vmax(fabs(pmax), fabs(pmin));
+    const T scale = vmax(fabs(phi + dmax), fabs(phi + dmin));  // max(|phi_max|, |phi_min|)
     const T eps2 = kh3 * scale * scale;
-    const T dmax = pmax - phi, dmin = pmin - phi;
     // Venkatakrishnan's function with the common factor d2 divided out of both parts:
     // psi = (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2), and psi = 1 where d2 = 0 (an unused
     // slot has zero geometry, so d2 = 0)

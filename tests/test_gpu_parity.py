@@ -258,7 +258,9 @@ def test_small_sphere_from_rest_ten_iterations_fp64():
 
 
 def test_large_dvs_takes_the_global_memory_face_path():
-    """nv = 17^3 = 4913 > 4096: the face kernel re-reads phi_bar from global memory instead of LDS (FP64)."""
+    """nv = 17^3 = 4913: an FP64 row pair (79 KB) exceeds the face kernel's 40 KB of LDS staging, so it stages G
+    alone (39 KB) and re-reads R from global memory (FP64).  nv = 16 384 (test_maximum_velocity_count) stages
+    neither, nv = 343 both without LDS-DMA (not a multiple of 4), and the other cases both with LDS-DMA."""
     c = configs.cavity_case(n=2, nv_side=17)
     o, s = _pair(c, warm=2)
     o.iterate(1)
@@ -266,6 +268,53 @@ def test_large_dvs_takes_the_global_memory_face_path():
     G, R, W, q = s.get_state()
     Go, Ro, Wo, qo = o.get_state()
     assert nrel(G, Go) < TOL and colrel(W, Wo) < TOL
+
+
+@pytest.mark.parametrize("nv_side", [7, 18, 22])
+def test_face_staging_paths_mixed(nv_side):
+    """The mixed face kernel's staging paths against the FP64 oracle: nv = 343 stages G and R in LDS by ordinary
+    loads (nv not a multiple of 4, so no LDS-DMA), nv = 5 832 stages G alone (the FP32 pair with its codes is
+    52 KB), nv = 10 648 stages neither (one FP32 row is 42 KB); the LDS-DMA path is that of every other mixed
+    case.  Both sides start from the same FP32-rounded state three iterations from rest.  The cavity's cell fluxes
+    are sums of face fluxes that nearly cancel, and each face's macro flux a velocity sum that nearly cancels,
+    so the error is measured against the sums of the absolute terms: sum_f |A (u.n) phi_f| / V per (cell,
+    velocity), and sum_f sum_k w |Psi_k| |A (u.n) phi_f,k| / V per cell and macro-flux column (Psi = 1, |u_x|,
+    |u_y|, |u_z|, |u|^2/2 for G with 1 for R, 1 for R): FP32 rounding of those terms, some units of 6e-8
+    (bar 1e-6); a wrong staged value gives errors of order one."""
+    say("case cavity n2 mixed face staging nv_side", nv_side)
+    c = configs.cavity_case(n=2, nv_side=nv_side)
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(3)
+    G, R, W, q = o.get_state()
+    G32, R32 = G.astype(np.float32), R.astype(np.float32)
+    o.set_state(G32.astype(np.float64), R32.astype(np.float64), W, q)
+    s = solver(c, precision="mixed")
+    s.set_state(G32, R32, W, q)
+    FG, FR, Fm = s.residual()
+    o.explicit()
+    g = o.geometry()
+    cf, V = g["cf"], g["V"]
+
+    def terms(ff):
+        """sum over each cell's faces of |ff[face]| / V"""
+        t = np.zeros((o.nc,) + ff.shape[1:])
+        for a in range(cf.shape[1]):
+            ok = cf[:, a] >= 0
+            t[ok] += np.abs(ff[cf[ok, a]])
+        return t / V.reshape((-1,) + (1,) * (ff.ndim - 1))
+
+    eF = max(float(np.max(np.abs(FG.cpu().numpy() - o.stage("FG")))) / float(np.max(terms(o.stage("ffG")))),
+             float(np.max(np.abs(FR.cpu().numpy() - o.stage("FR")))) / float(np.max(terms(o.stage("ffR")))))
+    aG, aR = np.abs(o.stage("ffG")), np.abs(o.stage("ffR"))
+    u, wq = np.asarray(c["u"]), np.asarray(c["w"])
+    fmac_terms = np.stack([aG @ wq, aG @ (wq * np.abs(u[:, 0])), aG @ (wq * np.abs(u[:, 1])),
+                           aG @ (wq * np.abs(u[:, 2])), aG @ (0.5 * wq * np.sum(u * u, axis=1)) + aR @ wq,
+                           aR @ wq], axis=1)
+    tm = np.max(terms(fmac_terms), axis=0)
+    eFm = float(np.max(np.max(np.abs(np.asarray(Fm) - o.stage("Fmac")), axis=0) / tm))
+    say(f"nv {len(c['u'])}: F {eF:.2e} Fmac {eFm:.2e} (against the face terms)")
+    assert eF < 1e-6 and eFm < 1e-6
 
 
 def _grid_dvs(nx, ny, nz, half=4.0):
