@@ -57,10 +57,17 @@ def stats(trace_dir: str, out: str, command: str, top: int = 16, bench_log: str 
         # the bench line printed by the same run: its hipEvent figure for the dominant kernel
         import json
         line = [x for x in open(bench_log) if x.startswith("{")][-1]
-        roof = json.loads(line)["roofline"]
+        bl = json.loads(line)
+        roof = bl["roofline"]
         lines += ["", f"bench.py (hipEvents, same run): {roof['kernel']} average launch {roof['avg_launch_us']:.2f} us, "
                       f"{roof['launches_per_iter']:g} launches per iteration, achieved {roof['achieved']:.0f} GB/s "
-                      f"algorithmic"]
+                      f"algorithmic",
+                  f"bench.py (same run, under the profiler): {bl['ms_per_step']:.2f} ms per iteration, "
+                  f"{bl['value']:.3e} {bl['unit']} ({bl['config'].get('workload', '')}, "
+                  f"{bl['config'].get('pairs', 0):.3e} pairs, {bl['dtype']})"]
+        if "stages" in bl:
+            lines.append("bench.py stages (ms per iteration): " + ", ".join(
+                f"{k} {v['ms_per_iter']:.2f}" for k, v in bl["stages"].items()))
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
