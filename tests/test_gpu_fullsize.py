@@ -62,6 +62,35 @@ def test_sphere_full_size_one_iteration_fp64():
     assert np.max(np.abs(hs - ho) / np.abs(ho)) < 1e-9
 
 
+def test_sphere_full_size_one_iteration_mixed():
+    """The headline path itself: the mixed precision on the full sphere workload (LDS-DMA face staging, vector
+    micro kernels, 4 140 velocities), one iteration from rest against the FP64 oracle.  The GPU starts from its
+    FP32 equilibrium, so both the initial state and the arithmetic differ by FP32 rounding (6e-8 of the largest
+    terms): bars 2e-6 on W (normwise per quantity: rho, the momentum vector, rho E, rho E_rot) and 1e-4 on the
+    wall heat load, a sum over incoming and outgoing velocities that cancels to a few per cent of its terms.  A
+    wrong staged value, upwind bit or coefficient gives errors of order one."""
+    from paper_2303_10846_amd.binding import Solver
+    c = configs.sphere_case(seed=0)
+    say("case", c["name"], "mixed", len(c["mesh"]["tets"]), "x", len(c["u"]))
+    s = Solver(c, precision="mixed")
+    s.init_equilibrium(c["W0"])
+    s.iterate(1)
+    W, _ = s.moments()
+    Qw = s.wall_heat_flux(1)
+    del s
+    o = oracle.Oracle(c)
+    o.init_equilibrium(c["W0"])
+    o.iterate(1)
+    _, _, Wo, _ = o.get_state()
+    Qo = o.wall_heat_flux(1)
+    mom = float(np.max(np.abs(Wo[:, 1:4])))
+    scale = np.array([np.max(np.abs(Wo[:, 0])), mom, mom, mom, np.max(np.abs(Wo[:, 4])), np.max(np.abs(Wo[:, 5]))])
+    eW = float(np.max(np.max(np.abs(W - Wo), axis=0) / scale))
+    eQ = abs(Qw - Qo) / abs(Qo)
+    say(f"mixed full sphere vs oracle: W {eW:.2e} Q_w {eQ:.2e}")
+    assert eW < 2e-6 and eQ < 1e-4
+
+
 def test_capsule_mesh_full_size_coarse_dvs_mixed_vs_oracle():
     from paper_2303_10846_amd.binding import Solver
     c = configs.capsule_case(seed=0, nv_target=700)
