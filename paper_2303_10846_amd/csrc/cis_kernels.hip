@@ -356,9 +356,11 @@ template <class F> __device__ inline void k_loop(int64_t nv, F&& body) {
 // the update kernel loses occupancy with it and is not faster).  P = 4 in FP32 (2 and 8 measured slower on the
 // sphere: face 3.38 and 3.76 ms against 3.22), 2 in FP64 (registers).
 template <class T> struct Prefetch { static constexpr int v = sizeof(T) == 4 ? 4 : 2; };
-template <int P, class L, class B> __device__ inline void k_loop_pf(int64_t nv, L&& load, B&& body) {
-  const int n = (int)nv;
-  for (int k0 = threadIdx.x; k0 < n; k0 += P * kBlock) {
+// The same over the velocities [begin, end), begin a multiple of kBlock.
+template <int P, class L, class B>
+__device__ inline void k_loop_pf_range(int64_t begin, int64_t end, L&& load, B&& body) {
+  const int n = (int)end;
+  for (int k0 = (int)begin + threadIdx.x; k0 < n; k0 += P * kBlock) {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const int k = k0 + q * kBlock;
@@ -370,6 +372,9 @@ template <int P, class L, class B> __device__ inline void k_loop_pf(int64_t nv, 
       if (k < n) body(k, q);
     }
   }
+}
+template <int P, class L, class B> __device__ inline void k_loop_pf(int64_t nv, L&& load, B&& body) {
+  k_loop_pf_range<P>(0, nv, load, body);
 }
 
 // The DVS arrays as uniform row pointers (32-bit velocity offsets)
@@ -425,6 +430,12 @@ __device__ inline void face_state_coeffs(const double* m, const double* U0, doub
   ec[29] = s / (tau + s);
 }
 
+// LDS staging of one face row: at most 38 KB per workgroup (with the kernel's 1.2 KB of static LDS, four face
+// workgroups still share a CU's 160 KB).  Stage 0 stages the first kStagePrefix<T> velocities of G and R (a
+// multiple of the workgroup size) when not even one whole row fits.
+constexpr int64_t kLdsStageMax = 38 * 1024;
+template <class T> constexpr int64_t kStagePrefix = kLdsStageMax / (2 * (int64_t)sizeof(T)) / kBlock * kBlock;
+
 // Stage 3: G, R and the owner's upwind codes are copied into LDS by LDS-DMA loads (global_load_lds), all
 // issued before any arithmetic, so the row costs one memory round trip instead of one per loop trip.
 typedef __attribute__((address_space(1))) const void* GlobalPtr;
@@ -458,6 +469,9 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   T* sG = reinterpret_cast<T*>(smem_raw);
   T* sR = sG + d.nv;                                // Stage >= 2
   Code* sC = reinterpret_cast<Code*>(sR + d.nv);  // Stage 3
+  // Stage 0: velocities [0, M) of G and R staged at sG and sG + M
+  const int64_t M = Stage == 0 ? (d.nv < kStagePrefix<T> ? d.nv : kStagePrefix<T>) : 0;
+  T* sR0 = sG + M;
   __shared__ double red[(kBlock / 64) * 6];
   __shared__ double red17[(kBlock / 64) * 17];
   const int64_t f = blockIdx.x;
@@ -496,17 +510,22 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     constexpr int P = Prefetch<T>::v;
     T pg[P], pr[P];
     double px[P], py[P], pz[P], pw[P];
-    k_loop_pf<P>(nv, [&](int k, int q) {
+    auto load1 = [&](int k, int q) {
       pg[q] = Stage == 3 ? sG[k] : rowG[k];
       pr[q] = Stage == 3 ? sR[k] : rowR[k];
       px[q] = V.ux[k];
       py[q] = V.uy[k];
       pz[q] = V.uz[k];
       pw[q] = V.w[k];
-    }, [&](int k, int q) {
+    };
+    auto body1 = [&](auto prefix, int k, int q) {
       const T gb = pg[q], rb = pr[q];
       if (Stage == 1 || Stage == 2) sG[k] = gb;
       if (Stage == 2) sR[k] = rb;
+      if constexpr (decltype(prefix)::value) {
+        sG[k] = gb;
+        sR0[k] = rb;
+      }
       const double vx = px[q] - U0[0], vy = py[q] - U0[1], vz = pz[q] - U0[2], w = pw[q];
       const double wg = w * (double)gb, wr = w * (double)rb;
       const double gx = wg * vx, gy = wg * vy, gz = wg * vz, v2 = vx * vx + vy * vy + vz * vz;
@@ -527,7 +546,13 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       a17.add(14, wr * vx);
       a17.add(15, wr * vy);
       a17.add(16, wr * vz);
-    });
+    };
+    if constexpr (Stage == 0) {
+      k_loop_pf_range<P>(0, M, load1, [&](int k, int q) { body1(std::true_type{}, k, q); });
+      k_loop_pf_range<P>(M, nv, load1, [&](int k, int q) { body1(std::false_type{}, k, q); });
+    } else {
+      k_loop_pf<P>(nv, load1, [&](int k, int q) { body1(std::false_type{}, k, q); });
+    }
     __shared__ double sh_m[17];
     a17.reduce_to_lds(sh_m, red17);
     // the face state (Eqs. 47-52) and its equilibrium coefficients, computed by one thread, shared through LDS
@@ -545,15 +570,21 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       if (d.cell_face[NF * own + a] == (int32_t)f) slot = a;
     acc.zero();
     unsigned pc[P];
-    k_loop_pf<P>(nv, [&](int k, int q) {
-      pg[q] = Stage >= 1 ? sG[k] : rowG[k];
-      pr[q] = Stage >= 2 ? sR[k] : rowR[k];
+    auto load2 = [&](auto prefix, int k, int q) {
+      if constexpr (decltype(prefix)::value) {
+        pg[q] = sG[k];
+        pr[q] = sR0[k];
+      } else {
+        pg[q] = Stage >= 1 ? sG[k] : rowG[k];
+        pr[q] = Stage >= 2 ? sR[k] : rowR[k];
+      }
       px[q] = V.ux[k];
       py[q] = V.uy[k];
       pz[q] = V.uz[k];
       pw[q] = V.w[k];
       pc[q] = Stage == 3 ? sC[k] : code[k];
-    }, [&](int k, int q) {
+    };
+    auto body2 = [&](int k, int q) {
       const T gb = pg[q], rb = pr[q];
       const double ux = px[q], uy = py[q], uz = pz[q], vw = pw[q];
       T gs, rs;
@@ -570,7 +601,13 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       acc.add(3, uz * wg);
       acc.add(4, 0.5 * (ux * ux + uy * uy + uz * uz) * wg + wr);
       acc.add(5, wr);
-    });
+    };
+    if constexpr (Stage == 0) {
+      k_loop_pf_range<P>(0, M, [&](int k, int q) { load2(std::true_type{}, k, q); }, body2);
+      k_loop_pf_range<P>(M, nv, [&](int k, int q) { load2(std::false_type{}, k, q); }, body2);
+    } else {
+      k_loop_pf<P>(nv, [&](int k, int q) { load2(std::false_type{}, k, q); }, body2);
+    }
     acc.reduce_to_lds(tot, red);
   } else {
     const double* bc = d.bc + BCW * bcs;
@@ -627,12 +664,12 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   if (threadIdx.x < 6) w.face_mac[6 * f + threadIdx.x] = A * tot[threadIdx.x];
 }
 
-// phi_bar of one face is staged in LDS as far as it fits in 40 KB, so that four face workgroups still share a
-// CU (160 KB of LDS): G and R (FP32 rows of the sphere, 33 KB), else G alone (FP64 rows of the sphere: pass 2
-// re-reads only R from global memory), else neither.  Measured on the sphere (4140 velocities): FP32 rows are
-// faster staged; staging both FP64 rows (66 KB, two workgroups per CU) was slower than re-reading both.
-constexpr int64_t kLdsStageMax = 40 * 1024;
-
+// phi_bar of one face is staged in LDS as far as it fits in 38 KB, so that four face workgroups still share a
+// CU (160 KB of LDS): G, R and the codes by LDS-DMA (FP32 rows of the sphere, 37 KB), G and R by ordinary
+// stores, G alone (FP64 rows of the sphere: pass 2 re-reads only R from global memory), else the first
+// kStagePrefix<T> velocities of G and R (the capsule's FP32 rows, 42 KB each).  Measured on the sphere (4140
+// velocities): FP32 rows are faster staged; staging both FP64 rows (66 KB, two workgroups per CU) was slower
+// than re-reading both.
 template <class T, int NF> static int face_stage(const Dev& d, const Bufs& b) {
   const int64_t nv = d.nv;
   const int64_t row = nv * (int64_t)sizeof(T);
@@ -646,8 +683,9 @@ template <class T, int NF> static int face_stage(const Dev& d, const Bufs& b) {
 
 template <class T, int NF> void launch_face_nf(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
   const int stage = face_stage<T, NF>(d, b);
-  const size_t lds = (size_t)d.nv * std::min(stage, 2) * sizeof(T) +
-                     (stage == 3 ? (size_t)d.nv * sizeof(typename Lay<NF>::Code) : 0);
+  const size_t lds = stage == 0 ? (size_t)std::min<int64_t>(d.nv, kStagePrefix<T>) * 2 * sizeof(T)
+                                 : (size_t)d.nv * std::min(stage, 2) * sizeof(T) +
+                                       (stage == 3 ? (size_t)d.nv * sizeof(typename Lay<NF>::Code) : 0);
   if (stage == 3)
     hipLaunchKernelGGL((k_face<T, 3, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
   else if (stage == 2)
@@ -655,7 +693,7 @@ template <class T, int NF> void launch_face_nf(const Dev& d, const Bufs& b, cons
   else if (stage == 1)
     hipLaunchKernelGGL((k_face<T, 1, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
   else
-    hipLaunchKernelGGL((k_face<T, 0, NF>), dim3((unsigned)d.nf), dim3(kBlock), 0, st, d, b, w);
+    hipLaunchKernelGGL((k_face<T, 0, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
 }
 
 template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {

@@ -258,9 +258,10 @@ def test_small_sphere_from_rest_ten_iterations_fp64():
 
 
 def test_large_dvs_takes_the_global_memory_face_path():
-    """nv = 17^3 = 4913: an FP64 row pair (79 KB) exceeds the face kernel's 40 KB of LDS staging, so it stages G
-    alone (39 KB) and re-reads R from global memory (FP64).  nv = 16 384 (test_maximum_velocity_count) stages
-    neither, nv = 343 both without LDS-DMA (not a multiple of 4), and the other cases both with LDS-DMA."""
+    """nv = 17^3 = 4913: one FP64 row (39 KB) exceeds the face kernel's 38 KB of LDS staging, so it stages the first
+    2 304 velocities of G and R and re-reads the rest from global memory (FP64), as nv = 16 384 does
+    (test_maximum_velocity_count); the full sphere's FP64 rows (33 KB) stage G alone, nv = 343 stages both without
+    LDS-DMA (not a multiple of 4), and the other cases stage both with LDS-DMA."""
     c = configs.cavity_case(n=2, nv_side=17)
     o, s = _pair(c, warm=2)
     o.iterate(1)
@@ -274,8 +275,8 @@ def test_large_dvs_takes_the_global_memory_face_path():
 def test_face_staging_paths_mixed(nv_side):
     """The mixed face kernel's staging paths against the FP64 oracle: nv = 343 stages G and R in LDS by ordinary
     loads (nv not a multiple of 4, so no LDS-DMA), nv = 5 832 stages G alone (the FP32 pair with its codes is
-    52 KB), nv = 10 648 stages neither (one FP32 row is 42 KB); the LDS-DMA path is that of every other mixed
-    case.  Both sides start from the same FP32-rounded state three iterations from rest.  The cavity's cell fluxes
+    52 KB), nv = 10 648 stages the first 4 864 velocities of G and R (one FP32 row is 42 KB, over the 38 KB
+    budget); the LDS-DMA path is that of every other mixed case.  Both sides start from the same FP32-rounded state three iterations from rest.  The cavity's cell fluxes
     are sums of face fluxes that nearly cancel, and each face's macro flux a velocity sum that nearly cancels,
     so the error is measured against the sums of the absolute terms: sum_f |A (u.n) phi_f| / V per (cell,
     velocity), and sum_f sum_k w |Psi_k| |A (u.n) phi_f,k| / V per cell and macro-flux column (Psi = 1, |u_x|,
