@@ -1455,6 +1455,57 @@ void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
 // Step 7: per-cell |W^{n+1} - W^n|, reduced by k_reduce_res.  One workgroup per cell.
 // ---------------------------------------------------------------------------
 
+// The 12 moment sums of Eqs. 62-67 of one velocity: phi^{n+1} - phi~* weighted by Phi (conserved moments) and
+// by c |c|^2 / 2, c (heat fluxes), c = u - U~.
+template <class T, class A>
+__device__ inline void update_moments(A& acc, T g, T r, T gs, T rs, double vx, double vy, double vz, double vw,
+                                      double Ux, double Uy, double Uz) {
+  double gd = (double)g - (double)gs, rd = (double)r - (double)rs;
+  double cx = vx - Ux, cy = vy - Uy, cz = vz - Uz;
+  double c2 = cx * cx + cy * cy + cz * cz;
+  double wg = vw * gd, wr = vw * rd;
+  acc.add(0, wg);
+  acc.add(1, vx * wg);
+  acc.add(2, vy * wg);
+  acc.add(3, vz * wg);
+  acc.add(4, 0.5 * (vx * vx + vy * vy + vz * vz) * wg + wr);
+  acc.add(5, wr);
+  double hc = 0.5 * c2 * wg;
+  acc.add(6, cx * hc);
+  acc.add(7, cy * hc);
+  acc.add(8, cz * hc);
+  acc.add(9, cx * wr);
+  acc.add(10, cy * wr);
+  acc.add(11, cz * wr);
+}
+
+// W^{n+1} and q^{n+1} of cell i from its 12 sums (Eqs. 62-67), and |W^{n+1} - W^n| for the residual.
+__device__ inline void update_cell(const Dev& d, const Bufs& b, const Work& w, int64_t i, const double* s) {
+  const GasC& gg = d.gas;
+  const double* ec = w.eq + ER * i;
+  const double* Wt = w.Wt + 6 * i;
+  double* W = b.W + 6 * i;
+  double* q = b.q + 6 * i;
+  double Wn[6], qn[6];
+  Wn[0] = s[0] + Wt[0];                                                      // Eq. 62
+  Wn[1] = s[1] + Wt[1];                                                      // Eq. 63
+  Wn[2] = s[2] + Wt[2];
+  Wn[3] = s[3] + Wt[3];
+  Wn[4] = s[4] + Wt[4];                                                      // Eq. 64
+  Wn[5] = s[5] + ec[0] * gg.R * ((1.0 - 1.0 / gg.Z) * ec[6] + ec[4] / gg.Z);  // Eq. 65
+  const double ctr = (1.0 / 3.0) * (1.0 - (1.0 - gg.omega0) / gg.Z);
+  const double crot = (1.0 - gg.delta) * (1.0 - (1.0 - gg.omega1) / gg.Z);
+  for (int m = 0; m < 3; ++m) {
+    qn[m] = s[6 + m] + q[m] * ctr;          // Eq. 66
+    qn[3 + m] = s[9 + m] + q[3 + m] * crot;  // Eq. 67
+  }
+  for (int m = 0; m < 6; ++m) {
+    w.cellres[6 * i + m] = fabs(Wn[m] - W[m]);
+    W[m] = Wn[m];
+    q[m] = qn[m];
+  }
+}
+
 template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update(Dev d, Bufs b, Work w) {
   __shared__ double red[(kBlock / 64) * 2 * 12];
   const int64_t i = blockIdx.x;
@@ -1478,50 +1529,11 @@ template <class T, bool Comp> __global__ __launch_bounds__(kBlock) void k_update
     const double vx = V.ux[k], vy = V.uy[k], vz = V.uz[k], vw = V.w[k];
     T gs, rs;
     e.eval((T)vx, (T)vy, (T)vz, gs, rs);
-    double gd = (double)g - (double)gs, rd = (double)r - (double)rs;
-    double cx = vx - Ux, cy = vy - Uy, cz = vz - Uz;
-    double c2 = cx * cx + cy * cy + cz * cz;
-    double wg = vw * gd, wr = vw * rd;
-    acc.add(0, wg);
-    acc.add(1, vx * wg);
-    acc.add(2, vy * wg);
-    acc.add(3, vz * wg);
-    acc.add(4, 0.5 * (vx * vx + vy * vy + vz * vz) * wg + wr);
-    acc.add(5, wr);
-    double hc = 0.5 * c2 * wg;
-    acc.add(6, cx * hc);
-    acc.add(7, cy * hc);
-    acc.add(8, cz * hc);
-    acc.add(9, cx * wr);
-    acc.add(10, cy * wr);
-    acc.add(11, cz * wr);
+    update_moments(acc, g, r, gs, rs, vx, vy, vz, vw, Ux, Uy, Uz);
   });
   __shared__ double s[12];
   acc.reduce_to_lds(s, red);
-  if (threadIdx.x == 0) {
-    const GasC& gg = d.gas;
-    const double* Wt = w.Wt + 6 * i;
-    double* W = b.W + 6 * i;
-    double* q = b.q + 6 * i;
-    double Wn[6], qn[6];
-    Wn[0] = s[0] + Wt[0];                                                      // Eq. 62
-    Wn[1] = s[1] + Wt[1];                                                      // Eq. 63
-    Wn[2] = s[2] + Wt[2];
-    Wn[3] = s[3] + Wt[3];
-    Wn[4] = s[4] + Wt[4];                                                      // Eq. 64
-    Wn[5] = s[5] + ec[0] * gg.R * ((1.0 - 1.0 / gg.Z) * ec[6] + ec[4] / gg.Z);  // Eq. 65
-    const double ctr = (1.0 / 3.0) * (1.0 - (1.0 - gg.omega0) / gg.Z);
-    const double crot = (1.0 - gg.delta) * (1.0 - (1.0 - gg.omega1) / gg.Z);
-    for (int m = 0; m < 3; ++m) {
-      qn[m] = s[6 + m] + q[m] * ctr;          // Eq. 66
-      qn[3 + m] = s[9 + m] + q[3 + m] * crot;  // Eq. 67
-    }
-    for (int m = 0; m < 6; ++m) {
-      w.cellres[6 * i + m] = fabs(Wn[m] - W[m]);
-      W[m] = Wn[m];
-      q[m] = qn[m];
-    }
-  }
+  if (threadIdx.x == 0) update_cell(d, b, w, i, s);
 }
 
 constexpr int kResParts = kResidualParts;
