@@ -109,7 +109,10 @@ typedef struct {
   int64_t total_bytes; /* sum over all cis_device_buffers members */
 } cis_buffer_sizes;
 
-/* Caller-owned device memory of a state (sizes from cis_state_required_bytes). */
+/* Caller-owned device memory of a state (sizes from cis_state_required_bytes).  Alignment: element alignment is
+   required; faceG and faceR aligned to 16 bytes and upwind to 4 bytes (torch and hipMalloc give 256) let the face
+   pass copy each face row into LDS with LDS-DMA loads when n_vel is a multiple of 4 (a faster path with the same
+   results). */
 typedef struct {
   void* G;      /* phi^n, [n_cells][n_vel] */
   void* R;
