@@ -30,15 +30,17 @@
 namespace cis {
 
 // Velocities per thread in the (cell, chunk) kernels, chunk = kBlock * Vpt<T>: 2 in FP32, 1 in FP64 (measured
-// on the sphere workload: more velocities per thread raise the loads in flight but cost occupancy; the
-// reconstruction: FP32 2.42 -> 2.31 ms with two, FP64 3.9 -> 5.5 ms).  The scalar micro sweep takes one in
-// both precisions (kVptOne: measured faster in FP32).
+// on the sphere workload: more velocities per thread raise the loads in flight but cost occupancy).  The
+// reconstruction takes VptRecon<T>: 3 strided velocities per thread in FP32, 1 in FP64 (measured: FP32 2.42 ms
+// with one, 2.31 with two, 2.25 with three, 2.34 with four; FP64 3.9 ms with one, 5.5 with two).  The scalar
+// micro sweep takes one in both precisions (kVptOne: measured faster in FP32).
 // In the mixed mode the micro sweep and the micro residual have vector forms (k_micro_sweep_vec,
 // k_residual_vec) for an nv that is a multiple of 4 or 2.
 template <class T> struct Vpt;
 template <> struct Vpt<double> { static constexpr int v = 1; };
 template <> struct Vpt<float> { static constexpr int v = 2; };
 constexpr int kVptOne = 1;
+template <class T> struct VptRecon { static constexpr int v = sizeof(T) == 4 ? 3 : 1; };
 
 template <int U> static inline unsigned n_chunks_u(int64_t nv) {
   constexpr int c = kBlock * U;
@@ -208,7 +210,7 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
 // from uniform base pointers with 32-bit element offsets.
 template <class T, int NF> __global__ __launch_bounds__(kBlock) void k_recon(Dev d, Bufs b, T* cap) {
   using L = Lay<NF>;
-  constexpr int U = Vpt<T>::v;
+  constexpr int U = VptRecon<T>::v;
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
   const int64_t i = d.spatial[cc.cell];
@@ -315,9 +317,9 @@ template <class T, int NF> __global__ __launch_bounds__(kBlock) void k_recon(Dev
 
 template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st, void* cap) {
   if (d.mf == 4)
-    hipLaunchKernelGGL((k_recon<T, 4>), cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, (T*)cap);
+    hipLaunchKernelGGL((k_recon<T, 4>), cell_chunk_grid_u<VptRecon<T>::v>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, (T*)cap);
   else
-    hipLaunchKernelGGL((k_recon<T, kMaxFaces>), cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b,
+    hipLaunchKernelGGL((k_recon<T, kMaxFaces>), cell_chunk_grid_u<VptRecon<T>::v>(d.nc, d.nv), dim3(kBlock), 0, st, d, b,
                        (T*)cap);
 }
 
