@@ -354,36 +354,61 @@ def adjoint_check(gmres_iters=300, fd_rel=1e-3, fd_iters=400):
             "rel_diff_frozen_vs_fd": [(x - y) / abs(y) for x, y in zip(adj, fd)]}
 
 
-def _converge(s, tol, max_iter, chunk=100):
-    """Iterate until the residual (largest component) is below tol or stops falling (a rounding floor)."""
+def _converge(s, tol, max_iter, chunk=100, schedule=None, floor_below=1e-5):
+    """Iterate until the residual (largest component) is below tol or, once it is below floor_below, stops
+    falling (a rounding floor).  schedule: (iteration, cfl_imp) pairs at multiples of chunk."""
+    ramp = dict(schedule or ())
     hist = []
     done = 0
     while done < max_iter:
+        if done in ramp:
+            s.set_numerics(cfl_imp=ramp[done])
         h = s.iterate(chunk)
         hist.append(h)
         done += chunk
         r = h.max(axis=1)
-        if r[-1] < tol or (len(hist) > 2 and r.min() >= 0.5 * hist[-2].max(axis=1).min()):
+        if r[-1] < tol or (len(hist) > 2 and r.min() < floor_below and
+                           r.min() >= 0.5 * hist[-2].max(axis=1).min()):
             break
     return np.concatenate(hist)
 
 
-def hex_sphere_converged(max_iter=1500):
-    """The sphere on its hexahedral O-grid, FP64 and mixed precision, each from rest to the paper's criterion
+# The two bodies on their hexahedral O-grids: case, description, implicit-step schedule from rest, iteration cap
+HEX_WORKLOADS = {
+    "sphere_hex": ("sphere Ma 5 Kn 0.1 Tw/Tinf 3 on a hexahedral O-grid (48 384 hexahedra) x 4 140 velocities",
+                   None, 1500),
+    "capsule_hex": ("capsule Ma 10 Kn 0.01 Tw/Tinf 4.18 on the hexahedral O-grid of the tetrahedral capsule "
+                    "(25 272 hexahedra) x 10 568 velocities", "capsule", 3000),
+}
+
+
+def _hex_case(workload):
+    from paper_2303_10846_amd.cases import configs
+    return configs.sphere_hex_case(seed=0) if workload == "sphere_hex" else configs.capsule_hex_case(seed=0)
+
+
+def _hex_schedule(workload):
+    return CAPSULE_CFL_RAMP if HEX_WORKLOADS[workload][1] == "capsule" else None
+
+
+def hex_converged(workload="sphere_hex"):
+    """A body on its hexahedral O-grid, FP64 and mixed precision, each from rest to the paper's criterion
     (FP64 below 1e-10, Sec. 4.1) or to its rounding floor (mixed), and the mixed fields against the FP64 ones."""
     import torch
 
     from paper_2303_10846_amd.binding import Solver
-    from paper_2303_10846_amd.cases import configs
-    case = configs.sphere_hex_case(seed=0)
-    out = {"workload": "sphere Ma 5 Kn 0.1 Tw/Tinf 3 on a hexahedral O-grid (48 384 hexahedra) x 4 140 velocities"}
+    case = _hex_case(workload)
+    desc, _, max_iter = HEX_WORKLOADS[workload]
+    out = {"workload": desc}
+    if _hex_schedule(workload):
+        out["cfl_imp_schedule_from_rest"] = [list(x) for x in _hex_schedule(workload)]
     res = {}
     for prec in ("fp64", "mixed"):
         s = Solver(case, precision=prec, device="cuda:0")
         s.init_equilibrium(case["W0"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h = _converge(s, 1e-12 if prec == "fp64" else 1e-10, max_iter)
+        h = _converge(s, 1e-12 if prec == "fp64" else 1e-10, max_iter, schedule=_hex_schedule(workload))
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         r = h.max(axis=1)
@@ -394,7 +419,7 @@ def hex_sphere_converged(max_iter=1500):
                      "ms_per_iteration": 1e3 * t / len(r),
                      "iterations_to_1e-10": int(np.argmax(r < 1e-10)) + 1 if np.any(r < 1e-10) else None,
                      "Qw": res[prec]["Qw"], "Cd": co["Cd"], "CQ": co["CQ"]}
-        print(f"bench: hex sphere {prec} {len(r)} iterations, residual {r[-1]:.2e}", file=sys.stderr, flush=True)
+        print(f"bench: {workload} {prec} {len(r)} iterations, residual {r[-1]:.2e}", file=sys.stderr, flush=True)
         del s
         torch.cuda.empty_cache()
 
@@ -412,24 +437,26 @@ def hex_sphere_converged(max_iter=1500):
     return out
 
 
-def adjoint_check_hex(fd_rel=1e-6, gmres_iters=600):
-    """Discrete adjoint of the converged hexahedral sphere (FP64, residual below 1e-12) against central
+def adjoint_check_hex(workload="sphere_hex", fd_rel=1e-6, gmres_iters=600):
+    """Discrete adjoint of a converged body on its hexahedral O-grid (FP64, residual below 1e-12) against central
     differences of the converged heat load with step 1e-6 of each parameter, with the limiter differentiated on
-    its branch (limiter 1) and with its values stored at the converged state (limiter 3)."""
+    its branch (limiter 1) and with its values stored at the converged state (limiter 3).  The capsule's GMRES
+    restart is 40: its Krylov basis (4.3 GB per vector) then takes 190 GB."""
     import torch
 
     from paper_2303_10846_amd.binding import Solver
-    from paper_2303_10846_amd.cases import configs
-    case = configs.sphere_hex_case(seed=0)
+    case = _hex_case(workload)
+    restart = 60 if workload == "sphere_hex" else 40
     s = Solver(case, precision="fp64", device="cuda:0")
     s.init_equilibrium(case["W0"])
-    hist = _converge(s, 1e-13, 1500)
-    print(f"bench: hex adjoint check primal residual {hist[-1].max():.3e} after {len(hist)}", file=sys.stderr,
-          flush=True)
+    hist = _converge(s, 1e-13, HEX_WORKLOADS[workload][2], schedule=_hex_schedule(workload))
+    print(f"bench: {workload} adjoint check primal residual {hist[-1].max():.3e} after {len(hist)}",
+          file=sys.stderr, flush=True)
     base = s.get_state()
     p0 = s.params(1, 2)
-    out = {"check": "dQ_w/dp of the converged hexahedral sphere (Ma 5, Kn 0.1), p = (T_w, rho_inf, |U_inf|)",
-           "n_cells": s.nc, "n_vel": s.nv, "primal_iterations": len(hist), "primal_residual": float(hist[-1].max())}
+    out = {"check": f"dQ_w/dp of the converged {HEX_WORKLOADS[workload][0]}, p = (T_w, rho_inf, |U_inf|)",
+           "n_cells": s.nc, "n_vel": s.nv, "primal_iterations": len(hist), "primal_residual": float(hist[-1].max()),
+           "gmres_restart": restart}
     for mode, lim in (("active_limiter", 1), ("stored_limiter", 3)):
         s.set_state(*base)
         s.set_params(p0, 1, 2)
@@ -437,10 +464,10 @@ def adjoint_check_hex(fd_rel=1e-6, gmres_iters=600):
             s.freeze_limiter()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        a = s.adjoint(1, 2, restart=60, max_iter=gmres_iters, rtol=1e-10, precond_pairs=2, macro_pairs=20)
+        a = s.adjoint(1, 2, restart=restart, max_iter=gmres_iters, rtol=1e-10, precond_pairs=2, macro_pairs=20)
         t_adj = time.perf_counter() - t0
-        print(f"bench: hex adjoint {mode} {a['iterations']} iterations, relative residual {a['rel_residual']:.2e}",
-              file=sys.stderr, flush=True)
+        print(f"bench: {workload} adjoint {mode} {a['iterations']} iterations, relative residual "
+              f"{a['rel_residual']:.2e}", file=sys.stderr, flush=True)
         del a["lam"]
         torch.cuda.empty_cache()
         fd = []
@@ -454,8 +481,8 @@ def adjoint_check_hex(fd_rel=1e-6, gmres_iters=600):
                 s.set_state(*base)
                 hk = _converge(s, 1e-13, 800)
                 J.append(s.wall_heat_flux(1))
-                print(f"bench: hex adjoint check {mode} p[{k}] {sgn:+d}h residual {hk[-1].max():.2e}",
-                      file=sys.stderr, flush=True)
+                print(f"bench: {workload} adjoint check {mode} p[{k}] {sgn:+d}h residual {hk[-1].max():.2e} "
+                      f"after {len(hk)}", file=sys.stderr, flush=True)
             fd.append((J[0] - J[1]) / (2 * h))
         s.set_params(p0, 1, 2)
         if lim == 3:
@@ -583,10 +610,12 @@ def main():
                     help="iterations (from rest) after which the two precisions' fields are compared")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["sphere", "capsule", "sphere_hex"], default="sphere",
+    ap.add_argument("--workload", choices=["sphere", "capsule", "sphere_hex", "capsule_hex"], default="sphere",
                     help="sphere (the headline workload), the Ma 10 capsule (303k tets x 10.6k velocities, "
-                         "mixed precision only: its FP64 state does not fit one GPU) or, for --adjoint-check, the "
-                         "sphere on its hexahedral O-grid")
+                         "mixed precision only: its FP64 state does not fit one GPU), or either body on its "
+                         "hexahedral O-grid (timed, and with --adjoint-check the adjoint at its converged state)")
+    ap.add_argument("--no-hex-capsule", action="store_true",
+                    help="leave out the converged hexahedral-capsule block of the default line")
     ap.add_argument("--no-hex", action="store_true",
                     help="leave out the converged hexahedral-sphere block of the default line")
     ap.add_argument("--dvs-study", type=int, default=0, metavar="ITERS",
@@ -617,7 +646,7 @@ def main():
         print(json.dumps(capsule_converge(args.capsule_converge)))
         return
     if args.adjoint_check:
-        print(json.dumps(adjoint_check_hex() if args.workload == "sphere_hex" else adjoint_check()))
+        print(json.dumps(adjoint_check_hex(args.workload) if args.workload in HEX_WORKLOADS else adjoint_check()))
         return
     if args.dvs_study:
         print(json.dumps(dvs_study(args.dvs_study, args.workload)))
@@ -629,10 +658,15 @@ def main():
             sys.exit(2)
         args.precision = "mixed"
         args.converge_iters = 0
-    case = configs.sphere_case(seed=0) if args.workload == "sphere" else configs.capsule_case(seed=0)
+    if args.workload in HEX_WORKLOADS:
+        case = _hex_case(args.workload)
+    else:
+        case = configs.sphere_case(seed=0) if args.workload == "sphere" else configs.capsule_case(seed=0)
     if args.sweeps:
         case["num"] = dict(case["num"], n_macro=args.sweeps[0], n_micro=args.sweeps[1])
-    print(f"bench: {case['name']} tets={len(case['mesh']['tets'])} nv={len(case['u'])}", file=sys.stderr, flush=True)
+    mesh = case["mesh"]
+    print(f"bench: {case['name']} cells={len(mesh['tets'] if 'tets' in mesh else mesh['cells'])} nv={len(case['u'])}",
+          file=sys.stderr, flush=True)
     res = {}
     for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
         print(f"bench: timing {prec}", file=sys.stderr, flush=True)
@@ -647,7 +681,9 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64" if main_key == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": ("sphere Ma 5 Kn 0.1 Tw/Tinf 3, graded tets x unstructured DVS, from rest"
                                 if args.workload == "sphere" else
-                                "capsule Ma 10 Kn 0.01 Tw/Tinf 4.18, graded tets x unstructured DVS, from rest"),
+                                "capsule Ma 10 Kn 0.01 Tw/Tinf 4.18, graded tets x unstructured DVS, from rest"
+                                if args.workload == "capsule" else
+                                HEX_WORKLOADS[args.workload][0] + ", from rest"),
                    "n_cells": r["n_cells"], "n_faces": r["n_faces"], "n_vel": r["n_vel"], "pairs": r["pairs"],
                    "precision": main_key, "n_macro_sweeps": case["num"]["n_macro"],
                    "n_micro_sweeps": case["num"]["n_micro"]},
@@ -677,9 +713,12 @@ def main():
         err = {"rho": float(np.max(np.abs(rm - rd)) / np.max(np.abs(rd))),
                "T": float(np.max(np.abs(Tm - Td)) / np.max(np.abs(Td))),
                "Qw": abs(r["Qw"] - f["Qw"]) / abs(f["Qw"])}
-        line["mixed_vs_fp64"] = dict(err, basis="fields after the same number of iterations from rest, both at the "
-                                     "limiter plateau of the tetrahedral mesh (residuals beside), mixed against the "
-                                     "FP64 GPU run; converged fields: converged_hex_sphere",
+        basis = ("fields after the same number of iterations from rest (residuals beside), mixed against the FP64 "
+                 "GPU run")
+        if args.workload == "sphere":
+            basis += (", both at the limiter plateau of the tetrahedral mesh; converged fields: converged_hex_sphere "
+                      "and converged_hex_capsule")
+        line["mixed_vs_fp64"] = dict(err, basis=basis,
                                      iterations=r["iterations"], residual_mixed=r["residual_last"],
                                      residual_fp64=f["residual_last"], Qw_fp64=f["Qw"],
                                      matched_error=bool(max(err.values()) <= 1e-5),
@@ -687,7 +726,10 @@ def main():
                                      iterations_to_residual_fp64=f["iterations_to"])
     if args.workload == "sphere" and args.converge_iters and not args.no_hex:
         print("bench: hexahedral sphere to convergence", file=sys.stderr, flush=True)
-        line["converged_hex_sphere"] = hex_sphere_converged()
+        line["converged_hex_sphere"] = hex_converged("sphere_hex")
+    if args.workload == "sphere" and args.converge_iters and not args.no_hex_capsule:
+        print("bench: hexahedral capsule to convergence", file=sys.stderr, flush=True)
+        line["converged_hex_capsule"] = hex_converged("capsule_hex")
     if not args.no_cpu and args.workload == "sphere":
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(case)

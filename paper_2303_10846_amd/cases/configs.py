@@ -19,7 +19,7 @@ from . import mesh as _mesh
 
 __all__ = ["gas_n2", "numerics_default", "mu_ref_from_kn", "cavity_case", "sphere_case", "sphere_hex_case",
            "small_sphere_hex_case",
-           "capsule_case",
+           "capsule_case", "capsule_hex_case",
            "freestream_box_case", "open_box_case", "small_sphere_case", "rest_state"]
 
 WALL = 1
@@ -173,4 +173,16 @@ def capsule_case(seed: int = 0, n_ang: int = 18, n_rad: int = 13, nv_target: int
                        3.0, 0.01, 10.0, 0.01, 4.24, 600.0 / 143.5, nv_target, seed, n_iter,
                        smooth_passes=smooth_passes, jitter=0.03)
     c["num"]["cfl_imp"] = 1.0  # Ma 10 from rest: a smaller implicit step keeps the first predictions positive
+    return c
+
+
+def capsule_hex_case(seed: int = 0, n_ang: int = 18, n_rad: int = 13, nv_target: int = 10000, n_iter: int = 50,
+                     smooth_passes: int = 4):
+    """The Ma 10 capsule on the hexahedral O-grid that the tetrahedral capsule splits into 12 tets per cell
+    (6 x 18 x 18 x 13 = 25 272 hexahedra), with the same body, jitter, DVS, gas and boundaries.  The paper's
+    blunted-cone mesh is hexahedral (Sec. 4.3)."""
+    c = _external_case(f"capsule_hex_ma10_kn0.01_{n_ang}x{n_rad}_seed{seed}", _mesh.capsule_body(), n_ang, n_rad,
+                       3.0, 0.01, 10.0, 0.01, 4.24, 600.0 / 143.5, nv_target, seed, n_iter,
+                       smooth_passes=smooth_passes, jitter=0.03, cells="hex")
+    c["num"]["cfl_imp"] = 1.0
     return c
