@@ -275,12 +275,40 @@ __device__ inline float eq_exp(float x) {
   return __builtin_fmaf(r, e * kLn2, r);
 }
 
+// exp(c2 b) for the equilibrium's exponentials, b = -1/(2RT) fixed per cell or face.  FP64: exp(c2 b).  FP32:
+// b log2 e is split once, in FP64, into B_hi + B_lo (B_hi its nearest FP32 value); t = fl(c2 B_hi), and the
+// rounding error of the whole exponent, e = (c2 B_hi - t) + c2 B_lo, follows from two FMAs as in eq_exp, so
+// exp(c2 b) = 2^t (1 + e ln 2).  Folding b into the base-2 constant removes one product and its rounding (the
+// error is then that of c2, of the hardware 2^t and of one rounding).
+template <class C> struct EqExp;
+template <> struct EqExp<double> {
+  double b;
+  __device__ inline void load(double bnat) { b = bnat; }
+  __device__ inline double operator()(double c2) const { return exp(c2 * b); }
+};
+template <> struct EqExp<float> {
+  float hi, lo;
+  __device__ inline void load(double bnat) {
+    const double b2 = bnat * 1.4426950408889634;
+    hi = (float)b2;
+    lo = (float)(b2 - (double)hi);
+  }
+  __device__ inline float operator()(float c2) const {
+    constexpr float kLn2 = 0.693147180559945309f;
+    const float t = c2 * hi;
+    const float e = __builtin_fmaf(c2, lo, __builtin_fmaf(c2, hi, -t));
+    const float r = __builtin_amdgcn_exp2f(t);
+    return __builtin_fmaf(r, e * kLn2, r);
+  }
+};
+
 // G*, R* of Eqs. 17-23 times a constant factor c (c = 1, or c = s/(tau+s) in the face step of Eq. 45), with
 // the constants combined once per cell or face: c (1-1/Z) a_tr and c a_T/Z as the two exponentials'
 // amplitudes, the Shakhov-type factors in the form c^2 k1 - k2 of the peculiar speed, and the R* parts as
-// RT_rot G_tr + RT G_rot + (c.q_rot)(m3 g_tr + m4 g_T).  28 operations and two exponentials per velocity.
+// RT_rot G_tr + RT G_rot + (c.q_rot)(m3 g_tr + m4 g_T).  Two exponentials per velocity.
 template <class C> struct Eq {
-  C Ux, Uy, Uz, qtx, qty, qtz, qrx, qry, qrz, A1, nb1, A2, nb2, k1, k2, k3, k4, m1, m2, m3, m4;
+  C Ux, Uy, Uz, qtx, qty, qtz, qrx, qry, qrz, A1, A2, k1, k2, k3, k4, m1, m2, m3, m4;
+  EqExp<C> x1, x2;
   __device__ inline void load(const double* e, double c = 1.0) {
     Ux = (C)e[1];
     Uy = (C)e[2];
@@ -292,9 +320,9 @@ template <class C> struct Eq {
     qry = (C)e[12];
     qrz = (C)e[13];
     A1 = (C)(c * e[26] * e[14]);
-    nb1 = (C)(-e[15]);
+    x1.load(-e[15]);
     A2 = (C)(c * e[27] * e[16]);
-    nb2 = (C)(-e[17]);
+    x2.load(-e[17]);
     k1 = (C)(e[18] * e[22]);
     k2 = (C)(5.0 * e[18]);
     k3 = (C)(e[19] * e[23]);
@@ -309,8 +337,8 @@ template <class C> struct Eq {
     const C c2 = cx * cx + cy * cy + cz * cz;
     const C cqt = cx * qtx + cy * qty + cz * qtz;
     const C cqr = cx * qrx + cy * qry + cz * qrz;
-    const C g1 = A1 * eq_exp(c2 * nb1);
-    const C g2 = A2 * eq_exp(c2 * nb2);
+    const C g1 = A1 * x1(c2);
+    const C g2 = A2 * x2(c2);
     const C Gt = g1 + g1 * (cqt * (c2 * k1 - k2));
     const C Gr = g2 + g2 * (cqt * (c2 * k3 - k4));
     Gs = Gt + Gr;

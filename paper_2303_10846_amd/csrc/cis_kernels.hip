@@ -171,16 +171,26 @@ __device__ inline void recon_write(T phi, const T* pn, const int32_t* nb, const 
   } else if (limiter) {  // 1, 2, and 4 (the smaller of this value and the stored one, stored back)
     const T scale = vmax(fabs(phi + dmax), fabs(phi + dmin));  // max(|phi_max|, |phi_min|)
     const T eps2 = kh3 * scale * scale;
-    // Venkatakrishnan's function with the common factor d2 divided out of both parts:
-    // psi = (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2), and psi = 1 where d2 = 0 (an unused
-    // slot has zero geometry, so d2 = 0)
+    // Venkatakrishnan's function of face a with the common factor d2_a divided out of both parts:
+    // psi_a = (d1^2 + eps^2 + 2 d1 d2_a) / (d1^2 + 2 d2_a^2 + d1 d2_a + eps^2), d1 = dmax where d2_a > 0 and
+    // dmin where d2_a < 0, and psi_a = 1 where d2_a = 0 (an unused slot has zero geometry, so d2 = 0).
+    // L = min(1, min_a psi_a) needs only the two extreme faces: for d1 >= 0 fixed, min(1, psi) does not grow
+    // with d2 > 0, since psi < 1 exactly where d2 > d1/2 and there dpsi/dd2 has the sign of
+    // (d1^2 + eps^2)(d1 - 4 d2) - 4 d1 d2^2 < 0; the same holds with every sign reversed (d1 = dmin <= 0,
+    // d2 < 0).  So the smallest value over the faces is at the largest positive d2 or at the most negative.
+    T hi = d2[0], lo = d2[0];
 #pragma unroll
-    for (int a = 0; a < NF; ++a) {
-      if (d2[a] != T(0)) {  // skipped by a whole wavefront where the field is locally uniform
-        const T d1 = d2[a] > T(0) ? dmax : dmin;
-        const T dd = d2[a] + d2[a];
-        L = vmin(L, lim_div(d1 * (d1 + dd) + eps2, d1 * (d1 + d2[a]) + (dd * d2[a] + eps2)));
-      }
+    for (int a = 1; a < NF; ++a) {
+      hi = vmax(hi, d2[a]);
+      lo = vmin(lo, d2[a]);
+    }
+    if (hi > T(0)) {  // skipped by a whole wavefront where the field is locally uniform
+      const T dd = hi + hi;
+      L = vmin(L, lim_div(dmax * (dmax + dd) + eps2, dmax * (dmax + hi) + (dd * hi + eps2)));
+    }
+    if (lo < T(0)) {
+      const T dd = lo + lo;
+      L = vmin(L, lim_div(dmin * (dmin + dd) + eps2, dmin * (dmin + lo) + (dd * lo + eps2)));
     }
     if (limiter == 4) L = vmin(L, ld_row(Lin, k));
   }
@@ -565,8 +575,11 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     e.load(sh_ec, sh_ec[29]);
     const T ct = (T)sh_ec[28];
     // pass 2: phi_f (Eq. 45), micro flux and macro flux.  The upwind side (with its tie rule) is the owner's
-    // upwind code, as in the reconstruction, and u.n is the plain FP64 product; |u|^2/2 is formed in registers
-    // (fewer cached DVS loads per velocity).
+    // upwind code, as in the reconstruction, and A u.n is the plain FP64 product with the area-scaled normal;
+    // |u|^2 is formed in registers (fewer cached DVS loads per velocity).  The energy sum runs as
+    // sum w (A u.n) G_f |u|^2 alone; the half and the rotational part sum w (A u.n) R_f are added once after
+    // the reduction.
+    const double an_x = A * nx, an_y = A * ny, an_z = A * nz;
     int slot = 0;
     for (int a = 1; a < NF; ++a)
       if (d.cell_face[NF * own + a] == (int32_t)f) slot = a;
@@ -593,15 +606,15 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       e.eval((T)ux, (T)uy, (T)uz, gs, rs);
       const T gf = ct * gb + gs;
       const T rf = ct * rb + rs;
-      const double un = ((pc[q] >> (2 * slot)) & 3u) == 0u ? 0.0 : ux * nx + uy * ny + uz * nz;
-      rowG[k] = (T)(A * un) * gf;
-      rowR[k] = (T)(A * un) * rf;
-      double wg = vw * un * (double)gf, wr = vw * un * (double)rf;
+      const double aun = ((pc[q] >> (2 * slot)) & 3u) == 0u ? 0.0 : ux * an_x + uy * an_y + uz * an_z;
+      *at_row(rowG, (uint32_t)k) = (T)aun * gf;
+      *at_row(rowR, (uint32_t)k) = (T)aun * rf;
+      double wg = vw * aun * (double)gf, wr = vw * aun * (double)rf;
       acc.add(0, wg);
       acc.add(1, ux * wg);
       acc.add(2, uy * wg);
       acc.add(3, uz * wg);
-      acc.add(4, 0.5 * (ux * ux + uy * uy + uz * uz) * wg + wr);
+      acc.add(4, (ux * ux + uy * uy + uz * uz) * wg);
       acc.add(5, wr);
     };
     if constexpr (Stage == 0) {
@@ -611,6 +624,8 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       k_loop_pf<P>(nv, [&](int k, int q) { load2(std::false_type{}, k, q); }, body2);
     }
     acc.reduce_to_lds(tot, red);
+    if (threadIdx.x < 6)
+      w.face_mac[6 * f + threadIdx.x] = threadIdx.x == 4 ? 0.5 * tot[4] + tot[5] : tot[threadIdx.x];
   } else {
     const double* bc = d.bc + BCW * bcs;
     const bool wall = bc[0] == 1.0;
@@ -662,8 +677,8 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       acc.add(5, wr);
     });
     acc.reduce_to_lds(tot, red);
+    if (threadIdx.x < 6) w.face_mac[6 * f + threadIdx.x] = A * tot[threadIdx.x];
   }
-  if (threadIdx.x < 6) w.face_mac[6 * f + threadIdx.x] = A * tot[threadIdx.x];
 }
 
 // phi_bar of one face is staged in LDS as far as it fits in 38 KB, so that four face workgroups still share a
@@ -1458,7 +1473,8 @@ void launch_micro(const Dev& d, const Bufs& b, const Work& w, const int64_t* col
 // ---------------------------------------------------------------------------
 
 // The 12 moment sums of Eqs. 62-67 of one velocity: phi^{n+1} - phi~* weighted by Phi (conserved moments) and
-// by c |c|^2 / 2, c (heat fluxes), c = u - U~.
+// by c |c|^2 / 2, c (heat fluxes), c = u - U~.  Sums 4 and 6-8 leave out the factor 1/2 (and sum 4 the R part,
+// which is sum 5): update_cell applies them to the totals.
 template <class T, class A>
 __device__ inline void update_moments(A& acc, T g, T r, T gs, T rs, double vx, double vy, double vz, double vw,
                                       double Ux, double Uy, double Uz) {
@@ -1470,9 +1486,9 @@ __device__ inline void update_moments(A& acc, T g, T r, T gs, T rs, double vx, d
   acc.add(1, vx * wg);
   acc.add(2, vy * wg);
   acc.add(3, vz * wg);
-  acc.add(4, 0.5 * (vx * vx + vy * vy + vz * vz) * wg + wr);
+  acc.add(4, (vx * vx + vy * vy + vz * vz) * wg);
   acc.add(5, wr);
-  double hc = 0.5 * c2 * wg;
+  double hc = c2 * wg;
   acc.add(6, cx * hc);
   acc.add(7, cy * hc);
   acc.add(8, cz * hc);
@@ -1493,12 +1509,12 @@ __device__ inline void update_cell(const Dev& d, const Bufs& b, const Work& w, i
   Wn[1] = s[1] + Wt[1];                                                      // Eq. 63
   Wn[2] = s[2] + Wt[2];
   Wn[3] = s[3] + Wt[3];
-  Wn[4] = s[4] + Wt[4];                                                      // Eq. 64
+  Wn[4] = (0.5 * s[4] + s[5]) + Wt[4];                                      // Eq. 64
   Wn[5] = s[5] + ec[0] * gg.R * ((1.0 - 1.0 / gg.Z) * ec[6] + ec[4] / gg.Z);  // Eq. 65
   const double ctr = (1.0 / 3.0) * (1.0 - (1.0 - gg.omega0) / gg.Z);
   const double crot = (1.0 - gg.delta) * (1.0 - (1.0 - gg.omega1) / gg.Z);
   for (int m = 0; m < 3; ++m) {
-    qn[m] = s[6 + m] + q[m] * ctr;          // Eq. 66
+    qn[m] = 0.5 * s[6 + m] + q[m] * ctr;    // Eq. 66
     qn[3 + m] = s[9 + m] + q[3 + m] * crot;  // Eq. 67
   }
   for (int m = 0; m < 6; ++m) {
