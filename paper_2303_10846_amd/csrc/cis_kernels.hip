@@ -338,9 +338,9 @@ template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st
 // collision-coupled face distribution (Eq. 45), micro flux A (u.n) phi_f (written in place over phi_bar)
 // and the face's macro flux A sum_k w (u.n) Phi phi_f (Eq. 37).  Boundary faces: diffuse wall with rho_w
 // from zero net mass flux, or far-field Maxwellian, for incoming velocities.  phi_bar is staged in LDS
-// (Stage = 2: G and R, 1: G only, 0: neither) or re-read from global memory in pass 2; the interior passes issue
-// the loads of Prefetch<T>
-// velocities per thread before their arithmetic, the other velocity loops kUnroll per trip.  The face sums are plain FP64 (each face flux is computed once and applied with opposite signs to its two
+// (Stage = 3: G, R and the upwind codes by LDS-DMA, 2: G and R, 0: the first velocities of G and R) or re-read
+// from global memory in pass 2; the interior passes issue the loads of Prefetch<T> velocities per thread before
+// their arithmetic, the other velocity loops kUnroll per trip.  The face sums are plain FP64 (each face flux is computed once and applied with opposite signs to its two
 // cells, so conservation does not depend on their rounding; compensating them was measured at +40% face time).
 // ---------------------------------------------------------------------------
 
@@ -349,14 +349,14 @@ template <class T> void launch_recon(const Dev& d, const Bufs& b, hipStream_t st
 #endif
 constexpr int kUnroll = CIS_UNROLL;
 
-// Velocity loop of a per-face / per-cell workgroup over all nv velocities, kUnroll independent
+// Velocity loop of a per-face / per-cell workgroup of NT threads over all nv velocities, kUnroll independent
 // velocities per trip.
-template <class F> __device__ inline void k_loop(int64_t nv, F&& body) {
+template <int NT = kBlock, class F> __device__ inline void k_loop(int64_t nv, F&& body) {
   const int n = (int)nv;
-  for (int k0 = threadIdx.x; k0 < n; k0 += kUnroll * kBlock) {
+  for (int k0 = threadIdx.x; k0 < n; k0 += kUnroll * NT) {
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
-      const int k = k0 + q * kBlock;
+      const int k = k0 + q * NT;
       if (k < n) body(k);
     }
   }
@@ -368,25 +368,25 @@ template <class F> __device__ inline void k_loop(int64_t nv, F&& body) {
 // the update kernel loses occupancy with it and is not faster).  P = 4 in FP32 (2 and 8 measured slower on the
 // sphere: face 3.38 and 3.76 ms against 3.22), 2 in FP64 (registers).
 template <class T> struct Prefetch { static constexpr int v = sizeof(T) == 4 ? 4 : 2; };
-// The same over the velocities [begin, end), begin a multiple of kBlock.
-template <int P, class L, class B>
+// The same over the velocities [begin, end), begin a multiple of NT.
+template <int P, int NT = kBlock, class L, class B>
 __device__ inline void k_loop_pf_range(int64_t begin, int64_t end, L&& load, B&& body) {
   const int n = (int)end;
-  for (int k0 = (int)begin + threadIdx.x; k0 < n; k0 += P * kBlock) {
+  for (int k0 = (int)begin + threadIdx.x; k0 < n; k0 += P * NT) {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const int k = k0 + q * kBlock;
+      const int k = k0 + q * NT;
       if (k < n) load(k, q);
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const int k = k0 + q * kBlock;
+      const int k = k0 + q * NT;
       if (k < n) body(k, q);
     }
   }
 }
-template <int P, class L, class B> __device__ inline void k_loop_pf(int64_t nv, L&& load, B&& body) {
-  k_loop_pf_range<P>(0, nv, load, body);
+template <int P, int NT = kBlock, class L, class B> __device__ inline void k_loop_pf(int64_t nv, L&& load, B&& body) {
+  k_loop_pf_range<P, NT>(0, nv, load, body);
 }
 
 // The DVS arrays as uniform row pointers (32-bit velocity offsets)
@@ -442,10 +442,13 @@ __device__ inline void face_state_coeffs(const double* m, const double* U0, doub
   ec[29] = s / (tau + s);
 }
 
-// LDS staging of one face row: at most 38 KB per workgroup (with the kernel's 1.2 KB of static LDS, four face
-// workgroups still share a CU's 160 KB).  Stage 0 stages the first kStagePrefix<T> velocities of G and R (a
-// multiple of the workgroup size) when not even one whole row fits.
+// LDS staging of one face row: at most 38 KB per 256-thread workgroup (with the kernel's 1.2 KB of static LDS,
+// four face workgroups still share a CU's 160 KB), or 77 KB per 512-thread workgroup (two per CU: the same 16
+// wavefronts).  Stage 0 stages the first kStagePrefix<T> velocities of G and R (a multiple of the workgroup
+// size) when not even the wide budget holds both rows.
 constexpr int64_t kLdsStageMax = 38 * 1024;
+constexpr int64_t kLdsStageWide = 77 * 1024;
+constexpr int kFaceWide = 2 * kBlock;
 template <class T> constexpr int64_t kStagePrefix = kLdsStageMax / (2 * (int64_t)sizeof(T)) / kBlock * kBlock;
 
 // Stage 3: G, R and the owner's upwind codes are copied into LDS by LDS-DMA loads (global_load_lds), all
@@ -454,14 +457,14 @@ typedef __attribute__((address_space(1))) const void* GlobalPtr;
 typedef __attribute__((address_space(3))) void* LdsPtr;
 
 // Copy n bytes (n a multiple of 4 * Dw, src and dst aligned to 4 * Dw bytes) from global memory into LDS with
-// LDS-DMA loads of Dw dwords per lane: wavefront w of the block copies 64-lane blocks w, w + 4, ...; a lane
-// past the end is inactive and writes nothing.
-template <int Dw> __device__ inline void lds_dma_copy(const void* src, void* dst, int64_t n) {
+// LDS-DMA loads of Dw dwords per lane: wavefront w of the NT-thread block copies 64-lane blocks w, w + NT/64,
+// ...; a lane past the end is inactive and writes nothing.
+template <int Dw, int NT> __device__ inline void lds_dma_copy(const void* src, void* dst, int64_t n) {
   static_assert(Dw == 1 || Dw == 4, "LDS-DMA loads of 4 or 16 bytes per lane");
   constexpr int kLane = 4 * Dw, kWave = 64 * kLane;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t nblk = (n + kWave - 1) / kWave;
-  for (int64_t blk = wid; blk < nblk; blk += kBlock / 64) {
+  for (int64_t blk = wid; blk < nblk; blk += NT / 64) {
     const int64_t off = blk * kWave + (int64_t)lane * kLane;
     if (off < n) {
       const GlobalPtr g = (GlobalPtr)((const char*)src + off);
@@ -474,8 +477,10 @@ template <int Dw> __device__ inline void lds_dma_copy(const void* src, void* dst
   }
 }
 
-template <class T, int Stage, int NF>
-__global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
+template <class T, int Stage, int NF, int NT>
+__global__ __launch_bounds__(NT) void k_face(Dev d, Bufs b, Work w) {
+  static_assert(Stage == 0 || Stage == 2 || Stage == 3, "staging paths 0, 2, 3");
+  static_assert(Stage != 0 || NT == kBlock, "prefix staging runs 256-thread workgroups");
   using Code = typename Lay<NF>::Code;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sG = reinterpret_cast<T*>(smem_raw);
@@ -484,8 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   // Stage 0: velocities [0, M) of G and R staged at sG and sG + M
   const int64_t M = Stage == 0 ? (d.nv < kStagePrefix<T> ? d.nv : kStagePrefix<T>) : 0;
   T* sR0 = sG + M;
-  __shared__ double red[(kBlock / 64) * 6];
-  __shared__ double red17[(kBlock / 64) * 17];
+  __shared__ double red[(NT / 64) * 6];
+  __shared__ double red17[(NT / 64) * 17];
   const int64_t f = blockIdx.x;
   const int64_t nv = d.nv;
   const double* fg = d.face_geo + FGW * f;
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   const int32_t bcs = d.face_bc[f];
   const GasC& g = d.gas;
   const DvsRows V = dvs_rows(d);
-  Acc<6, false, kBlock> acc;
+  Acc<6, false, NT> acc;
   __shared__ double tot[6];
 
   if (bcs < 0) {
@@ -511,13 +516,13 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     const int64_t own = d.face_cell[2 * f];
     const Code* code = reinterpret_cast<const Code*>(d.upw) + own * nv;
     if constexpr (Stage == 3) {
-      lds_dma_copy<4>(rowG, sG, nv * (int64_t)sizeof(T));
-      lds_dma_copy<4>(rowR, sR, nv * (int64_t)sizeof(T));
-      lds_dma_copy<1>(code, sC, nv * (int64_t)sizeof(Code));
+      lds_dma_copy<4, NT>(rowG, sG, nv * (int64_t)sizeof(T));
+      lds_dma_copy<4, NT>(rowR, sR, nv * (int64_t)sizeof(T));
+      lds_dma_copy<1, NT>(code, sC, nv * (int64_t)sizeof(Code));
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
-    Acc<17, false, kBlock> a17;
+    Acc<17, false, NT> a17;
     a17.zero();
     constexpr int P = Prefetch<T>::v;
     T pg[P], pr[P];
@@ -532,8 +537,10 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     };
     auto body1 = [&](auto prefix, int k, int q) {
       const T gb = pg[q], rb = pr[q];
-      if (Stage == 1 || Stage == 2) sG[k] = gb;
-      if (Stage == 2) sR[k] = rb;
+      if (Stage == 2) {
+        sG[k] = gb;
+        sR[k] = rb;
+      }
       if constexpr (decltype(prefix)::value) {
         sG[k] = gb;
         sR0[k] = rb;
@@ -563,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       k_loop_pf_range<P>(0, M, load1, [&](int k, int q) { body1(std::true_type{}, k, q); });
       k_loop_pf_range<P>(M, nv, load1, [&](int k, int q) { body1(std::false_type{}, k, q); });
     } else {
-      k_loop_pf<P>(nv, load1, [&](int k, int q) { body1(std::false_type{}, k, q); });
+      k_loop_pf<P, NT>(nv, load1, [&](int k, int q) { body1(std::false_type{}, k, q); });
     }
     __shared__ double sh_m[17];
     a17.reduce_to_lds(sh_m, red17);
@@ -590,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
         pg[q] = sG[k];
         pr[q] = sR0[k];
       } else {
-        pg[q] = Stage >= 1 ? sG[k] : rowG[k];
+        pg[q] = Stage >= 2 ? sG[k] : rowG[k];
         pr[q] = Stage >= 2 ? sR[k] : rowR[k];
       }
       px[q] = V.ux[k];
@@ -621,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
       k_loop_pf_range<P>(0, M, [&](int k, int q) { load2(std::true_type{}, k, q); }, body2);
       k_loop_pf_range<P>(M, nv, [&](int k, int q) { load2(std::false_type{}, k, q); }, body2);
     } else {
-      k_loop_pf<P>(nv, [&](int k, int q) { load2(std::false_type{}, k, q); }, body2);
+      k_loop_pf<P, NT>(nv, [&](int k, int q) { load2(std::false_type{}, k, q); }, body2);
     }
     acc.reduce_to_lds(tot, red);
     if (threadIdx.x < 6)
@@ -634,10 +641,10 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     double rho_g = bc[1];
     if (wall) {
       // rho_w from zero net mass flux through the wall
-      Acc<2, false, kBlock> a2;
+      Acc<2, false, NT> a2;
       a2.zero();
       const double anorm = maxwell_norm(RTb);
-      k_loop(nv, [&](int k) {
+      k_loop<NT>(nv, [&](int k) {
         const Vel v = vel(V, k);
         const double un = udotn(v, nx, ny, nz, d.snap);
         if (un > 0.0) {
@@ -654,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
     const T amax = (T)(rho_g * maxwell_norm(RTb));
     const T bmax = (T)(1.0 / (2.0 * RTb));
     acc.zero();
-    k_loop(nv, [&](int k) {
+    k_loop<NT>(nv, [&](int k) {
       const Vel v = vel(V, k);
       const double un = udotn(v, nx, ny, nz, d.snap);
       T gf, rf;
@@ -681,36 +688,47 @@ __global__ __launch_bounds__(kBlock) void k_face(Dev d, Bufs b, Work w) {
   }
 }
 
-// phi_bar of one face is staged in LDS as far as it fits in 38 KB, so that four face workgroups still share a
-// CU (160 KB of LDS): G, R and the codes by LDS-DMA (FP32 rows of the sphere, 37 KB), G and R by ordinary
-// stores, G alone (FP64 rows of the sphere: pass 2 re-reads only R from global memory), else the first
-// kStagePrefix<T> velocities of G and R (the capsule's FP32 rows, 42 KB each).  Measured on the sphere (4140
-// velocities): FP32 rows are faster staged; staging both FP64 rows (66 KB, two workgroups per CU) was slower
-// than re-reading both.
-template <class T, int NF> static int face_stage(const Dev& d, const Bufs& b) {
+// phi_bar of one face is staged in LDS whole where it fits: in 38 KB with 256 threads per face (four face
+// workgroups per CU), else in 77 KB with 512 threads per face (two per CU, the same 16 wavefronts), G, R and
+// the owner's codes by LDS-DMA where the rows allow it, else G and R by ordinary stores; rows too long for both
+// stage the first kStagePrefix<T> velocities of G and R (the capsule's FP32 rows, 42 KB each).  Measured on the
+// sphere (4 140 velocities): FP32 rows (37 KB with the codes) run fastest at 256 threads; FP64 rows (69 KB with
+// the codes) at 512 threads, where staging G alone at 256 threads re-read R from global memory and staging
+// both at 256 threads halved the wavefronts per CU.
+struct FacePlan {
+  int stage, nt;
+  size_t lds;
+};
+template <class T, int NF> static FacePlan face_plan(const Dev& d, const Bufs& b) {
   const int64_t nv = d.nv;
   const int64_t row = nv * (int64_t)sizeof(T);
   // LDS-DMA staging needs 16-byte aligned rows (aligned arrays, nv a multiple of 4), 4-byte aligned code rows
   // and room for the code row
   const int64_t code_row = nv * (int64_t)sizeof(typename Lay<NF>::Code);
-  const bool aligned = (uintptr_t)b.faceG % 16 == 0 && (uintptr_t)b.faceR % 16 == 0 && (uintptr_t)d.upw % 4 == 0;
-  if (aligned && nv % 4 == 0 && 2 * row + code_row <= kLdsStageMax) return 3;
-  return 2 * row <= kLdsStageMax ? 2 : row <= kLdsStageMax ? 1 : 0;
+  const bool dma = (uintptr_t)b.faceG % 16 == 0 && (uintptr_t)b.faceR % 16 == 0 && (uintptr_t)d.upw % 4 == 0 &&
+                   nv % 4 == 0;
+  const int64_t budget[2] = {kLdsStageMax, kLdsStageWide};
+  const int nt[2] = {kBlock, kFaceWide};
+  for (int i = 0; i < 2; ++i) {
+    if (dma && 2 * row + code_row <= budget[i]) return FacePlan{3, nt[i], (size_t)(2 * row + code_row)};
+    if (2 * row <= budget[i]) return FacePlan{2, nt[i], (size_t)(2 * row)};
+  }
+  return FacePlan{0, kBlock, (size_t)std::min<int64_t>(nv, kStagePrefix<T>) * 2 * sizeof(T)};
 }
 
 template <class T, int NF> void launch_face_nf(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {
-  const int stage = face_stage<T, NF>(d, b);
-  const size_t lds = stage == 0 ? (size_t)std::min<int64_t>(d.nv, kStagePrefix<T>) * 2 * sizeof(T)
-                                 : (size_t)d.nv * std::min(stage, 2) * sizeof(T) +
-                                       (stage == 3 ? (size_t)d.nv * sizeof(typename Lay<NF>::Code) : 0);
-  if (stage == 3)
-    hipLaunchKernelGGL((k_face<T, 3, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
-  else if (stage == 2)
-    hipLaunchKernelGGL((k_face<T, 2, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
-  else if (stage == 1)
-    hipLaunchKernelGGL((k_face<T, 1, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
+  const FacePlan p = face_plan<T, NF>(d, b);
+  const dim3 grid((unsigned)d.nf);
+  if (p.stage == 3 && p.nt == kBlock)
+    hipLaunchKernelGGL((k_face<T, 3, NF, kBlock>), grid, dim3(kBlock), p.lds, st, d, b, w);
+  else if (p.stage == 3)
+    hipLaunchKernelGGL((k_face<T, 3, NF, kFaceWide>), grid, dim3(kFaceWide), p.lds, st, d, b, w);
+  else if (p.stage == 2 && p.nt == kBlock)
+    hipLaunchKernelGGL((k_face<T, 2, NF, kBlock>), grid, dim3(kBlock), p.lds, st, d, b, w);
+  else if (p.stage == 2)
+    hipLaunchKernelGGL((k_face<T, 2, NF, kFaceWide>), grid, dim3(kFaceWide), p.lds, st, d, b, w);
   else
-    hipLaunchKernelGGL((k_face<T, 0, NF>), dim3((unsigned)d.nf), dim3(kBlock), lds, st, d, b, w);
+    hipLaunchKernelGGL((k_face<T, 0, NF, kBlock>), grid, dim3(kBlock), p.lds, st, d, b, w);
 }
 
 template <class T> void launch_face(const Dev& d, const Bufs& b, const Work& w, hipStream_t st) {

@@ -257,12 +257,14 @@ def test_small_sphere_from_rest_ten_iterations_fp64():
     assert abs(s.wall_heat_flux(1) - o.wall_heat_flux(1)) < 1e-11 * abs(o.wall_heat_flux(1))
 
 
-def test_large_dvs_takes_the_global_memory_face_path():
-    """nv = 17^3 = 4913: one FP64 row (39 KB) exceeds the face kernel's 38 KB of LDS staging, so it stages the first
-    2 304 velocities of G and R and re-reads the rest from global memory (FP64), as nv = 16 384 does
-    (test_maximum_velocity_count); the full sphere's FP64 rows (33 KB) stage G alone, nv = 343 stages both without
-    LDS-DMA (not a multiple of 4), and the other cases stage both with LDS-DMA."""
-    c = configs.cavity_case(n=2, nv_side=17)
+@pytest.mark.parametrize("nv_side", [17, 18])
+def test_large_dvs_face_staging_paths_fp64(nv_side):
+    """The FP64 face kernel's wide and prefix staging: nv = 17^3 = 4 913 stages both rows (77 KB) in one
+    512-thread workgroup by ordinary loads (nv not a multiple of 4); nv = 18^3 = 5 832 (two rows of 46 KB) stages
+    the first 2 304 velocities of G and R and re-reads the rest from global memory, as nv = 16 384 does
+    (test_maximum_velocity_count).  The full sphere's FP64 rows (33 KB) take LDS-DMA in 512-thread workgroups,
+    nv = 343 stages both rows without LDS-DMA in 256 threads, and the other cases take LDS-DMA in 256 threads."""
+    c = configs.cavity_case(n=2, nv_side=nv_side)
     o, s = _pair(c, warm=2)
     o.iterate(1)
     s.iterate(1)
@@ -271,12 +273,13 @@ def test_large_dvs_takes_the_global_memory_face_path():
     assert nrel(G, Go) < TOL and colrel(W, Wo) < TOL
 
 
-@pytest.mark.parametrize("nv_side", [7, 18, 22])
+@pytest.mark.parametrize("nv_side", [7, 17, 18, 22])
 def test_face_staging_paths_mixed(nv_side):
     """The mixed face kernel's staging paths against the FP64 oracle: nv = 343 stages G and R in LDS by ordinary
-    loads (nv not a multiple of 4, so no LDS-DMA), nv = 5 832 stages G alone (the FP32 pair with its codes is
-    52 KB), nv = 10 648 stages the first 4 864 velocities of G and R (one FP32 row is 42 KB, over the 38 KB
-    budget); the LDS-DMA path is that of every other mixed case.  Both sides start from the same FP32-rounded state three iterations from rest.  The cavity's cell fluxes
+    loads in 256 threads (nv not a multiple of 4, so no LDS-DMA), nv = 4 913 the same in 512 threads (the pair is
+    38.4 KB, over the 38 KB of a 256-thread workgroup), nv = 5 832 stages G, R and the codes by LDS-DMA in 512
+    threads (51 KB), nv = 10 648 stages the first 4 864 velocities of G and R (the pair is 83 KB, over the 77 KB
+    of a 512-thread workgroup); the 256-thread LDS-DMA path is that of every other mixed case.  Both sides start from the same FP32-rounded state three iterations from rest.  The cavity's cell fluxes
     are sums of face fluxes that nearly cancel, and each face's macro flux a velocity sum that nearly cancels,
     so the error is measured against the sums of the absolute terms: sum_f |A (u.n) phi_f| / V per (cell,
     velocity), and sum_f sum_k w |Psi_k| |A (u.n) phi_f,k| / V per cell and macro-flux column (Psi = 1, |u_x|,
