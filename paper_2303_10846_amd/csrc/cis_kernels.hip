@@ -34,8 +34,9 @@ namespace cis {
 // reconstruction takes VptRecon<T>: 3 strided velocities per thread in FP32, 1 in FP64 (measured: FP32 2.42 ms
 // with one, 2.31 with two, 2.25 with three, 2.34 with four; FP64 3.9 ms with one, 5.5 with two).  The scalar
 // micro sweep takes one in both precisions (kVptOne: measured faster in FP32).
-// In the mixed mode the micro sweep and the micro residual have vector forms (k_micro_sweep_vec,
-// k_residual_vec) for an nv that is a multiple of 4 or 2.
+// The micro sweep and the micro residual have vector forms (k_micro_sweep_vec, k_residual_vec) that move
+// 16 bytes per row access (four FP32 or two FP64 velocities) when nv is a multiple of that and the rows are
+// 16-byte aligned, and a two-velocity FP32 form for an even nv.
 template <class T> struct Vpt;
 template <> struct Vpt<double> { static constexpr int v = 1; };
 template <> struct Vpt<float> { static constexpr int v = 2; };
@@ -1023,55 +1024,57 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, Bufs b, Work w, T* o
   }
 }
 
-template <int V> struct alignas(4 * V) VecR { float v[V]; };
+template <class T, int V> struct alignas(sizeof(T) * V) VecR { T v[V]; };
 
-// The mixed-mode micro residual with V adjacent velocities per thread moved as vectors (nv a multiple of V, so
-// that every row offset keeps them aligned), Res stored non-temporally; the arithmetic of k_residual<float>,
-// velocity by velocity.  Measured on the sphere (4140 velocities): 1.68 -> 1.50 ms with V = 4.
-template <int V, int NF>
-__global__ __launch_bounds__(kBlock) void k_residual_vec(Dev d, Bufs b, Work w, float* outG, float* outR) {
+// The micro residual with V adjacent velocities per thread moved as 16-byte vectors (four FP32 or two FP64
+// values; nv a multiple of V and 16-byte aligned rows, so every row offset keeps them aligned), Res stored
+// non-temporally; the arithmetic of k_residual<T>, velocity by velocity.  Measured on the sphere (4140
+// velocities): mixed 1.68 -> 1.50 ms with V = 4; FP64 4.10 -> 2.89 ms with V = 2.
+template <class T, int V, int NF>
+__global__ __launch_bounds__(kBlock) void k_residual_vec(Dev d, Bufs b, Work w, T* outG, T* outR) {
   const CellChunk cc = cell_chunk(d.nc);
   if (cc.cell >= d.nc) return;
   const int64_t i = d.spatial[cc.cell];
   const int64_t nv = d.nv;
   const int k = (int)cc.chunk * (V * kBlock) + V * (int)threadIdx.x;
   if (k >= (int)nv) return;
-  using VF = VecR<V>;
+  using VF = VecR<T, V>;
   const double* geo = d.cell_geo + Lay<NF>::CG * i;
   VF xG[NF], xR[NF];
-  float sg[NF];
+  T sg[NF];
 #pragma unroll
   for (int a = 0; a < NF; ++a) {
     const int32_t fa = d.cell_face[NF * i + a];
     const int64_t f = fa >= 0 ? fa : d.cell_face[NF * i];
-    xG[a] = *reinterpret_cast<const VF*>((const float*)b.faceG + f * nv + k);
-    xR[a] = *reinterpret_cast<const VF*>((const float*)b.faceR + f * nv + k);
-    sg[a] = (float)(geo[CG_FACE + CG_SLOT * a] * geo[1]);
+    xG[a] = *reinterpret_cast<const VF*>((const T*)b.faceG + f * nv + k);
+    xR[a] = *reinterpret_cast<const VF*>((const T*)b.faceR + f * nv + k);
+    sg[a] = (T)(geo[CG_FACE + CG_SLOT * a] * geo[1]);
   }
-  const VF pG = *reinterpret_cast<const VF*>((const float*)b.G + i * nv + k);
-  const VF pR = *reinterpret_cast<const VF*>((const float*)b.R + i * nv + k);
-  const VF ux = *reinterpret_cast<const VF*>(d.dvs_f + k);
-  const VF uy = *reinterpret_cast<const VF*>(d.dvs_f + nv + k);
-  const VF uz = *reinterpret_cast<const VF*>(d.dvs_f + 2 * nv + k);
+  const VF pG = *reinterpret_cast<const VF*>((const T*)b.G + i * nv + k);
+  const VF pR = *reinterpret_cast<const VF*>((const T*)b.R + i * nv + k);
+  const T* dvs = std::is_same<T, float>::value ? (const T*)d.dvs_f : (const T*)d.dvs;
+  const VF ux = *reinterpret_cast<const VF*>(dvs + k);
+  const VF uy = *reinterpret_cast<const VF*>(dvs + nv + k);
+  const VF uz = *reinterpret_cast<const VF*>(dvs + 2 * nv + k);
   const double* ec = w.eq + ER * i;
-  Eq<float> e;
+  Eq<T> e;
   e.load(ec);
-  const float itau = (float)(1.0 / ec[7]);
+  const T itau = (T)(1.0 / ec[7]);
   VF oG, oR;
 #pragma unroll
   for (int q = 0; q < V; ++q) {
-    float FG = sg[0] * xG[0].v[q], FR = sg[0] * xR[0].v[q];
+    T FG = sg[0] * xG[0].v[q], FR = sg[0] * xR[0].v[q];
 #pragma unroll
     for (int a = 1; a < NF; ++a) {
       FG += sg[a] * xG[a].v[q];
       FR += sg[a] * xR[a].v[q];
     }
-    float gs, rs;
+    T gs, rs;
     e.eval(ux.v[q], uy.v[q], uz.v[q], gs, rs);
     oG.v[q] = (gs - pG.v[q]) * itau - FG;
     oR.v[q] = (rs - pR.v[q]) * itau - FR;
   }
-  typedef float ev __attribute__((ext_vector_type(V)));
+  typedef T ev __attribute__((ext_vector_type(V)));
   ev sG, sR;
 #pragma unroll
   for (int q = 0; q < V; ++q) {
@@ -1082,17 +1085,27 @@ __global__ __launch_bounds__(kBlock) void k_residual_vec(Dev d, Bufs b, Work w, 
   __builtin_nontemporal_store(sR, reinterpret_cast<ev*>(outR + i * nv + k));
 }
 
+// Whether the rows of the distribution, right-hand side and face arrays keep V-element vectors of T 16-byte
+// aligned (vector kernels of the micro residual and sweep); otherwise the scalar kernels run.
+template <class T> static bool rows_aligned16(const Dev& d, const Bufs& b, int V) {
+  const void* p[8] = {b.G, b.R, b.dG, b.dR, b.resG, b.resR, b.faceG, b.faceR};
+  bool ok = (int)sizeof(T) * V == 16 && d.nv % V == 0;
+  for (const void* x : p) ok = ok && (uintptr_t)x % 16 == 0;
+  return ok;
+}
+
 template <class T, int NF>
 void launch_residual_nf(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR, int flux_only,
                         hipStream_t st) {
-  if (std::is_same<T, float>::value && !flux_only && d.nv % 4 == 0) {
-    hipLaunchKernelGGL((k_residual_vec<4, NF>), cell_chunk_grid_u<4>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w,
-                       (float*)outG, (float*)outR);
+  constexpr int V = 16 / sizeof(T);
+  if (!flux_only && rows_aligned16<T>(d, b, V) && (uintptr_t)outG % 16 == 0 && (uintptr_t)outR % 16 == 0) {
+    hipLaunchKernelGGL((k_residual_vec<T, V, NF>), cell_chunk_grid_u<V>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w,
+                       (T*)outG, (T*)outR);
     return;
   }
   if (std::is_same<T, float>::value && !flux_only && d.nv % 2 == 0) {
-    hipLaunchKernelGGL((k_residual_vec<2, NF>), cell_chunk_grid_u<2>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w,
-                       (float*)outG, (float*)outR);
+    hipLaunchKernelGGL((k_residual_vec<float, 2, NF>), cell_chunk_grid_u<2>(d.nc, d.nv), dim3(kBlock), 0, st, d, b,
+                       w, (float*)outG, (float*)outR);
     return;
   }
   hipLaunchKernelGGL((k_residual<T, NF>), cell_chunk_grid<T>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w, (T*)outG,
@@ -1236,30 +1249,30 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep(Dev d, Bufs b, Work w, i
   micro_store<T, U, NF>(c, in, code, k, nvi);
 }
 
-// The mixed-mode sweep moves V adjacent velocities per thread as one vector per row (one load or store of
-// 4V bytes instead of V), when nv is a multiple of V so that every row offset keeps the vectors aligned.  The
-// arithmetic is that of k_micro_sweep<float>, velocity by velocity; a neighbour's vector is loaded when any of
+// The vector sweep moves V adjacent velocities per thread as one vector per row (one load or store of
+// V sizeof(T) bytes instead of V), when nv is a multiple of V so that every row offset keeps the vectors aligned.
+// The arithmetic is that of k_micro_sweep<T>, velocity by velocity; a neighbour's vector is loaded when any of
 // the V velocities takes it as its upstream value.  The right-hand sides are read and the increments written
 // non-temporally (in every precision): the increments are next read by other colours' launches and the update,
 // after the caches have turned over.  Measured on the sphere (4140 velocities): micro sweep 3.79 -> 3.45 ms
 // with V = 4 (90 VGPRs, 5 waves per SIMD), 3.52 ms with V = 2; non-temporal 3.44 -> 3.14 ms (FP64 6.89 ->
-// 6.58 ms).
-template <int V> struct alignas(4 * V) VecF { float v[V]; };
-template <int V> struct ExtV;
-template <> struct ExtV<2> { typedef float type __attribute__((ext_vector_type(2))); };
-template <> struct ExtV<4> { typedef float type __attribute__((ext_vector_type(4))); };
-template <int V> __device__ inline VecF<V> ld_nt(const float* p) {
-  const typename ExtV<V>::type x = __builtin_nontemporal_load(reinterpret_cast<const typename ExtV<V>::type*>(p));
-  VecF<V> r;
+// 6.58 ms); FP64 with V = 2: 6.35 -> 6.13 ms.
+template <class T, int V> struct alignas(sizeof(T) * V) VecF { T v[V]; };
+template <class T, int V> struct ExtV { typedef T type __attribute__((ext_vector_type(V))); };
+template <class T, int V> __device__ inline VecF<T, V> ld_nt(const T* p) {
+  using E = typename ExtV<T, V>::type;
+  const E x = __builtin_nontemporal_load(reinterpret_cast<const E*>(p));
+  VecF<T, V> r;
 #pragma unroll
   for (int q = 0; q < V; ++q) r.v[q] = x[q];
   return r;
 }
-template <int V> __device__ inline void st_nt(float* p, const VecF<V>& v) {
-  typename ExtV<V>::type x;
+template <class T, int V> __device__ inline void st_nt(T* p, const VecF<T, V>& v) {
+  using E = typename ExtV<T, V>::type;
+  E x;
 #pragma unroll
   for (int q = 0; q < V; ++q) x[q] = v.v[q];
-  __builtin_nontemporal_store(x, reinterpret_cast<typename ExtV<V>::type*>(p));
+  __builtin_nontemporal_store(x, reinterpret_cast<E*>(p));
 }
 // The codes of V adjacent velocities as one word: V bytes (4 face slots) or V 16-bit codes (6 slots)
 template <int V, int NF> struct CodeT;
@@ -1268,7 +1281,7 @@ template <> struct CodeT<4, 4> { using type = uint32_t; };
 template <> struct CodeT<2, kMaxFaces> { using type = uint32_t; };
 template <> struct CodeT<4, kMaxFaces> { using type = uint64_t; };
 
-template <int V, int NF>
+template <class T, int V, int NF>
 __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work w, int64_t c0, int64_t cnext,
                                                             int first) {
   using Code = typename Lay<NF>::Code;
@@ -1279,20 +1292,21 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work 
   const int64_t i = c0 + cc.cell;
   const int k = (int)cc.chunk * (V * kBlock) + V * (int)threadIdx.x;
   if (k >= (int)nv) return;
-  using VF = VecF<V>;
+  using VF = VecF<T, V>;
   const uint64_t cw = *reinterpret_cast<const typename CodeT<V, NF>::type*>(reinterpret_cast<const Code*>(d.upw) +
                                                                              i * nv + k);
-  const VF vx = *reinterpret_cast<const VF*>(d.dvs_f + k);
-  const VF vy = *reinterpret_cast<const VF*>(d.dvs_f + nv + k);
-  const VF vz = *reinterpret_cast<const VF*>(d.dvs_f + 2 * nv + k);
-  MicroCell<float, NF> c;
-  micro_setup<float, NF>(d, b, w, i, cnext, first, c);
-  const VF xG = ld_nt<V>(c.rG + k);
-  const VF xR = ld_nt<V>(c.rR + k);
+  const T* dvs = std::is_same<T, float>::value ? (const T*)d.dvs_f : (const T*)d.dvs;
+  const VF vx = *reinterpret_cast<const VF*>(dvs + k);
+  const VF vy = *reinterpret_cast<const VF*>(dvs + nv + k);
+  const VF vz = *reinterpret_cast<const VF*>(dvs + 2 * nv + k);
+  MicroCell<T, NF> c;
+  micro_setup<T, NF>(d, b, w, i, cnext, first, c);
+  const VF xG = ld_nt<T, V>(c.rG + k);
+  const VF xR = ld_nt<T, V>(c.rR + k);
   unsigned code[V];
 #pragma unroll
   for (int q = 0; q < V; ++q) code[q] = (unsigned)((cw >> (bits * q)) & ((1ull << bits) - 1));
-  float pos[V][NF], neg[V][NF];
+  T pos[V][NF], neg[V][NF];
   VF yG[NF], yR[NF];
 #pragma unroll
   for (int a = 0; a < NF; ++a) {
@@ -1300,13 +1314,13 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work 
 #pragma unroll
     for (int q = 0; q < V; ++q) {
       const unsigned cd = (code[q] >> (2 * a)) & 3u;
-      const float t = vx.v[q] * c.nx[a] + vy.v[q] * c.ny[a] + vz.v[q] * c.nz[a];
-      pos[q][a] = cd == 1u ? fmaxf(t, 0.0f) : 0.0f;
-      neg[q][a] = cd == 2u ? fminf(t, 0.0f) : 0.0f;
+      const T t = vx.v[q] * c.nx[a] + vy.v[q] * c.ny[a] + vz.v[q] * c.nz[a];
+      pos[q][a] = cd == 1u ? vmax(t, T(0)) : T(0);
+      neg[q][a] = cd == 2u ? vmin(t, T(0)) : T(0);
       need = need || cd == 2u;
     }
 #pragma unroll
-    for (int q = 0; q < V; ++q) yG[a].v[q] = yR[a].v[q] = 0.0f;
+    for (int q = 0; q < V; ++q) yG[a].v[q] = yR[a].v[q] = T(0);
     if (c.use[a] && need) {
       yG[a] = *reinterpret_cast<const VF*>(c.nG[a] + k);
       yR[a] = *reinterpret_cast<const VF*>(c.nR[a] + k);
@@ -1316,7 +1330,7 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work 
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     double D = c.dbase;
-    float aG = xG.v[q], aR = xR.v[q];
+    T aG = xG.v[q], aR = xR.v[q];
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
       D += (double)(c.av[a] * pos[q][a]);
@@ -1326,11 +1340,11 @@ __global__ __launch_bounds__(kBlock) void k_micro_sweep_vec(Dev d, Bufs b, Work 
       }
     }
     const double iD = 1.0 / D;
-    oG.v[q] = (float)((double)aG * iD);
-    oR.v[q] = (float)((double)aR * iD);
+    oG.v[q] = (T)((double)aG * iD);
+    oR.v[q] = (T)((double)aR * iD);
   }
-  st_nt<V>(c.oG + k, oG);
-  st_nt<V>(c.oR + k, oR);
+  st_nt<T, V>(c.oG + k, oG);
+  st_nt<T, V>(c.oR + k, oR);
 }
 
 // Preconditioner of the discrete adjoint (FP64): point relaxation over one colour of
@@ -1461,15 +1475,17 @@ void launch_micro_nf(const Dev& d, const Bufs& b, const Work& w, const int64_t* 
   }
   int64_t nonempty = 0;
   for (int64_t c = 0; c < n_colors; ++c) nonempty += color_off[c + 1] > color_off[c];
+  constexpr int V = 16 / sizeof(T);  // 16-byte vectors: four FP32 or two FP64 velocities
+  const bool vec = rows_aligned16<T>(d, b, V);
   for (size_t p = 0; p < seq.size(); ++p) {
     const int64_t c = seq[p];
     const int64_t n = color_off[c + 1] - color_off[c];
-    if (std::is_same<T, float>::value && d.nv % 4 == 0)
-      hipLaunchKernelGGL((k_micro_sweep_vec<4, NF>), cell_chunk_grid_u<4>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
+    if (vec)
+      hipLaunchKernelGGL((k_micro_sweep_vec<T, V, NF>), cell_chunk_grid_u<V>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
                          color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
     else if (std::is_same<T, float>::value && d.nv % 2 == 0)
-      hipLaunchKernelGGL((k_micro_sweep_vec<2, NF>), cell_chunk_grid_u<2>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
-                         color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
+      hipLaunchKernelGGL((k_micro_sweep_vec<float, 2, NF>), cell_chunk_grid_u<2>(n, d.nv), dim3(kBlock), 0, st, d,
+                         b, w, color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
     else
       hipLaunchKernelGGL((k_micro_sweep<T, NF>), cell_chunk_grid_u<kVptOne>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
                          color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
