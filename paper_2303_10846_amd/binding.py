@@ -269,10 +269,13 @@ class Dvs:
 
 
 class Solver:
-    """One state of the scheme on the current GPU (device memory owned by torch tensors)."""
+    """One state of the scheme on the current GPU (device memory owned by torch tensors).
+    row_offset > 0 starts every distribution and face array that many elements past the start of its allocation,
+    so that the rows are element-aligned only (the library then runs its scalar kernels instead of the vector
+    ones; used to test those paths)."""
 
     def __init__(self, case: dict, precision: str = "fp64", device: str = "cuda:0", num: dict = None,
-                 gas: dict = None, bcs=None, stream=None):
+                 gas: dict = None, bcs=None, stream=None, row_offset: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("paper_2303_10846_amd needs a ROCm GPU; none is visible")
@@ -295,7 +298,12 @@ class Solver:
         _check(lib.cis_state_required_bytes(self.mesh.h, self.dvs.h, self.precision, C.byref(sizes)))
         self.sizes = sizes
         with torch.cuda.device(self.device):
-            mk = lambda n: torch.empty(n, self.nv, dtype=self.dtype, device=self.device)  # noqa: E731
+            def mk(n):
+                if not row_offset:
+                    return torch.empty(n, self.nv, dtype=self.dtype, device=self.device)
+                flat = torch.empty(n * self.nv + int(row_offset), dtype=self.dtype, device=self.device)
+                return flat[int(row_offset):].view(n, self.nv)
+
             self.G, self.R = mk(self.nc), mk(self.nc)
             self.dG, self.dR = mk(self.nc), mk(self.nc)
             self.resG, self.resR = mk(self.nc), mk(self.nc)

@@ -1085,12 +1085,14 @@ __global__ __launch_bounds__(kBlock) void k_residual_vec(Dev d, Bufs b, Work w, 
   __builtin_nontemporal_store(sR, reinterpret_cast<ev*>(outR + i * nv + k));
 }
 
-// Whether the rows of the distribution, right-hand side and face arrays keep V-element vectors of T 16-byte
-// aligned (vector kernels of the micro residual and sweep); otherwise the scalar kernels run.
-template <class T> static bool rows_aligned16(const Dev& d, const Bufs& b, int V) {
+// Whether every row of the distribution, right-hand side and face arrays keeps V-element vectors of T aligned
+// to their size (nv a multiple of V, arrays aligned to V sizeof(T) bytes): the condition of the vector kernels
+// of the micro residual and sweep; otherwise the scalar kernels run.
+template <class T> static bool rows_aligned(const Dev& d, const Bufs& b, int V) {
   const void* p[8] = {b.G, b.R, b.dG, b.dR, b.resG, b.resR, b.faceG, b.faceR};
-  bool ok = (int)sizeof(T) * V == 16 && d.nv % V == 0;
-  for (const void* x : p) ok = ok && (uintptr_t)x % 16 == 0;
+  const uintptr_t bytes = sizeof(T) * (uintptr_t)V;
+  bool ok = d.nv % V == 0;
+  for (const void* x : p) ok = ok && (uintptr_t)x % bytes == 0;
   return ok;
 }
 
@@ -1098,12 +1100,13 @@ template <class T, int NF>
 void launch_residual_nf(const Dev& d, const Bufs& b, const Work& w, void* outG, void* outR, int flux_only,
                         hipStream_t st) {
   constexpr int V = 16 / sizeof(T);
-  if (!flux_only && rows_aligned16<T>(d, b, V) && (uintptr_t)outG % 16 == 0 && (uintptr_t)outR % 16 == 0) {
+  if (!flux_only && rows_aligned<T>(d, b, V) && (uintptr_t)outG % 16 == 0 && (uintptr_t)outR % 16 == 0) {
     hipLaunchKernelGGL((k_residual_vec<T, V, NF>), cell_chunk_grid_u<V>(d.nc, d.nv), dim3(kBlock), 0, st, d, b, w,
                        (T*)outG, (T*)outR);
     return;
   }
-  if (std::is_same<T, float>::value && !flux_only && d.nv % 2 == 0) {
+  if (std::is_same<T, float>::value && !flux_only && rows_aligned<T>(d, b, 2) && (uintptr_t)outG % 8 == 0 &&
+      (uintptr_t)outR % 8 == 0) {
     hipLaunchKernelGGL((k_residual_vec<float, 2, NF>), cell_chunk_grid_u<2>(d.nc, d.nv), dim3(kBlock), 0, st, d, b,
                        w, (float*)outG, (float*)outR);
     return;
@@ -1476,14 +1479,15 @@ void launch_micro_nf(const Dev& d, const Bufs& b, const Work& w, const int64_t* 
   int64_t nonempty = 0;
   for (int64_t c = 0; c < n_colors; ++c) nonempty += color_off[c + 1] > color_off[c];
   constexpr int V = 16 / sizeof(T);  // 16-byte vectors: four FP32 or two FP64 velocities
-  const bool vec = rows_aligned16<T>(d, b, V);
+  const bool vec = rows_aligned<T>(d, b, V);
+  const bool vec2 = std::is_same<T, float>::value && rows_aligned<T>(d, b, 2);
   for (size_t p = 0; p < seq.size(); ++p) {
     const int64_t c = seq[p];
     const int64_t n = color_off[c + 1] - color_off[c];
     if (vec)
       hipLaunchKernelGGL((k_micro_sweep_vec<T, V, NF>), cell_chunk_grid_u<V>(n, d.nv), dim3(kBlock), 0, st, d, b, w,
                          color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
-    else if (std::is_same<T, float>::value && d.nv % 2 == 0)
+    else if (vec2)
       hipLaunchKernelGGL((k_micro_sweep_vec<float, 2, NF>), cell_chunk_grid_u<2>(n, d.nv), dim3(kBlock), 0, st, d,
                          b, w, color_off[c], color_off[c + 1], (int64_t)p < nonempty ? 1 : 0);
     else
