@@ -366,9 +366,10 @@ template <int NT = kBlock, class F> __device__ inline void k_loop(int64_t nv, F&
 // The same loop with the loads of P velocities per thread issued before any of their arithmetic:
 // load(k, q) fills the registers of slot q (loads only), body(k, q) consumes them.  A face workgroup that
 // loops over a whole row is otherwise bound by one memory round trip per trip (measured: face kernel -12%;
-// the update kernel loses occupancy with it and is not faster).  P = 4 in FP32 (2 and 8 measured slower on the
-// sphere: face 3.38 and 3.76 ms against 3.22), 2 in FP64 (registers).
-template <class T> struct Prefetch { static constexpr int v = sizeof(T) == 4 ? 4 : 2; };
+// the update kernel loses occupancy with it and is not faster).  P = 3 in FP32 (on the sphere, with the rows
+// staged by LDS-DMA: face 2.79 ms against 2.86 with P = 4; before the staging 2 and 8 were slower than 4) and
+// 1 in FP64 (512-thread workgroups over staged rows: 4.08 ms against 4.09 with P = 2).
+template <class T> struct Prefetch { static constexpr int v = sizeof(T) == 4 ? 3 : 1; };
 // The same over the velocities [begin, end), begin a multiple of NT.
 template <int P, int NT = kBlock, class L, class B>
 __device__ inline void k_loop_pf_range(int64_t begin, int64_t end, L&& load, B&& body) {
