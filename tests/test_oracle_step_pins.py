@@ -3,7 +3,8 @@
 Each test rebuilds one step of the oracle from its definition in the paper, with plain numpy on the oracle's
 geometry, and compares:
 
-* Venkatakrishnan's function (the limiter Eq. 46 cites) against its published closed-form values;
+* Venkatakrishnan's function (the limiter Eq. 46 cites) against its published closed-form values, and the
+  minimum over a cell's faces against its value at the two extreme faces;
 * the limiter of every cell against the minimum of that function over the cell's faces, evaluated by hand;
 * the face value of Eq. 46 (the point x_f - u s, the upwind cell, the u.n = 0 tie) against a least-squares
   gradient taken with numpy's lstsq, on one face for every velocity;
@@ -55,6 +56,48 @@ def test_venkatakrishnan_function_published_values():
     for y, d2, eps2 in ((0.3, 0.2, 0.01), (1.7, -0.5, 0.3), (-0.4, 1.1, 2.0), (0.05, 3.0, 0.0)):
         assert abs(psi(y * d2, d2, eps2) - venkat_ratio_form(y, eps2 / d2 ** 2)) < 1e-14
     assert abs(psi(0.0, 1.0, 1e12) - 1.0) < 1e-11
+
+
+def test_limiter_minimum_over_faces_is_at_the_two_extreme_faces():
+    """min(1, min_f psi(d1_f, d2_f)) with d1_f = d_max (>= 0) where d2_f > 0 and d_min (<= 0) where d2_f < 0
+    equals min(1, psi(d_max, max_f d2_f), psi(d_min, min_f d2_f)), each term taken only for a positive maximum or a
+    negative minimum: for fixed d1 >= 0, min(1, psi) does not grow with d2 > 0 (psi < 1 exactly for d2 > d1/2,
+    where it decreases), and the same with every sign reversed.  The reconstruction kernels evaluate the
+    limiter at those two faces only; this checks the identity on the oracle's function, over random stencils
+    with 1 to 6 faces, zero increments and eps = 0 included."""
+    psi = oracle.venkat_psi
+    rng = np.random.default_rng(11)
+
+    def lim_all(dmax, dmin, d2, eps2):
+        L = 1.0
+        for x in d2:
+            if x != 0.0:
+                L = min(L, psi(dmax if x > 0 else dmin, x, eps2))
+        return L
+
+    def lim_two(dmax, dmin, d2, eps2):
+        L = 1.0
+        if max(d2) > 0:
+            L = min(L, psi(dmax, max(d2), eps2))
+        if min(d2) < 0:
+            L = min(L, psi(dmin, min(d2), eps2))
+        return L
+
+    n_active = 0
+    for t in range(4000):
+        nf = int(rng.integers(1, 7))
+        scale = 10.0 ** rng.uniform(-3, 1)
+        d2 = list(scale * rng.normal(size=nf))
+        for a in range(nf):
+            if rng.uniform() < 0.15:
+                d2[a] = 0.0
+        dmax = 0.0 if rng.uniform() < 0.1 else abs(scale * rng.normal())
+        dmin = 0.0 if rng.uniform() < 0.1 else -abs(scale * rng.normal())
+        eps2 = 0.0 if rng.uniform() < 0.3 else (scale * 10.0 ** rng.uniform(-3, 0)) ** 2
+        la, lt = lim_all(dmax, dmin, d2, eps2), lim_two(dmax, dmin, d2, eps2)
+        assert abs(la - lt) <= 1e-15 * max(la, 1e-300), (dmax, dmin, d2, eps2, la, lt)
+        n_active += la < 0.999
+    assert n_active > 1000  # the limiter acts in many of the samples
 
 
 def _lsq_gradients(geo, phi):
