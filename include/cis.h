@@ -110,9 +110,10 @@ typedef struct {
 } cis_buffer_sizes;
 
 /* Caller-owned device memory of a state (sizes from cis_state_required_bytes).  Alignment: element alignment is
-   required; faceG and faceR aligned to 16 bytes and upwind to 4 bytes (torch and hipMalloc give 256) let the face
-   pass copy each face row into LDS with LDS-DMA loads when n_vel is a multiple of 4 (a faster path with the same
-   results). */
+   required.  Faster paths with the same results need more (torch and hipMalloc give 256): faceG and faceR aligned
+   to 16 bytes and upwind to 4 bytes let the face pass copy each face row into LDS with LDS-DMA loads when n_vel
+   is a multiple of 4; G, R, dG, dR, resG, resR, faceG and faceR aligned to 16 bytes let the micro residual and
+   sweep move 16-byte vectors of velocities when n_vel is a multiple of 4 (mixed) or 2 (FP64). */
 typedef struct {
   void* G;      /* phi^n, [n_cells][n_vel] */
   void* R;
