@@ -72,3 +72,49 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert p.returncode == 2
     assert "one GPU" in p.stderr
     assert p.stdout.strip() == ""
+
+
+class _FakeSolver:
+    """Stands in for a Solver in the convergence loop: the residual history follows a given function of the
+    iteration count, and every implicit-step change is recorded."""
+
+    def __init__(self, residual_of):
+        self.residual_of = residual_of
+        self.done = 0
+        self.cfl = []
+
+    def set_numerics(self, **kw):
+        self.cfl.append((self.done, kw["cfl_imp"]))
+
+    def iterate(self, n):
+        import numpy as np
+        r = np.array([self.residual_of(self.done + k + 1) for k in range(n)])
+        self.done += n
+        return np.repeat(r[:, None], 6, axis=1)
+
+
+def test_converge_stops_at_tol_and_applies_the_schedule():
+    s = _FakeSolver(lambda it: 10.0 ** (-it / 100.0))
+    h = bench._converge(s, 1e-8, 3000, schedule=((0, 1.0), (300, 3.0), (900, 10.0)))
+    # below 1e-8 first at iteration 801, checked at the end of each 100-iteration chunk
+    assert len(h) == 900 and h[-1].max() < 1e-8
+    assert s.cfl == [(0, 1.0), (300, 3.0)]
+
+
+def test_converge_stops_at_a_rounding_floor_only_below_floor_below():
+    # a slow transient above 1e-5 (falls by less than half per chunk) must not stop the loop; a floor at 2e-6 does
+    def res(it):
+        if it <= 500:
+            return 0.1 * 0.9 ** (it / 100.0)
+        return max(2e-6, 0.1 * 0.9 ** 5 * 10.0 ** (-(it - 500) / 100.0))
+    s = _FakeSolver(res)
+    h = bench._converge(s, 1e-10, 5000)
+    r = h.max(axis=1)
+    assert r[-1] == 2e-6 and len(h) < 5000
+    assert len(h) > 500
+
+
+def test_hex_workloads_take_the_capsule_schedule():
+    assert bench._hex_schedule("capsule_hex") == bench.CAPSULE_CFL_RAMP
+    assert bench._hex_schedule("sphere_hex") is None
+    assert set(bench.HEX_WORKLOADS) == {"sphere_hex", "capsule_hex"}
