@@ -734,13 +734,13 @@ def main():
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(case)
     elif not args.no_cpu:
-        # the capsule's FP64 oracle state does not fit the host's memory: its per-pair rate on the sphere workload,
-        # labelled as an extrapolation to the capsule
+        # the other workloads take the oracle's per-pair rate on the sphere workload, labelled as an extrapolation
+        # (the capsule's FP64 oracle state does not fit the host's memory)
         print("bench: cpu baseline (oracle on the sphere workload, extrapolated)", file=sys.stderr, flush=True)
         cb = cpu_baseline(configs.sphere_case(seed=0))
         cb["kind"] = "oracle, extrapolated"
-        cb["extrapolation"] = (f"the oracle's per-pair rate on the sphere workload applied to the capsule's "
-                               f"{r['pairs']:.3g} pairs: {r['pairs'] / cb['value']:.0f} s per iteration")
+        cb["extrapolation"] = (f"the oracle's per-pair rate on the sphere workload applied to this workload's "
+                               f"{r['pairs']:.3g} pairs: {r['pairs'] / cb['value']:.1f} s per iteration")
         line["cpu_baseline"] = cb
     print(json.dumps(line))
 
