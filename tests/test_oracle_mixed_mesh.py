@@ -160,3 +160,35 @@ def test_closed_box_at_wall_temperature_is_steady(kind):
     hist = o.iterate(1)
     assert np.max(hist) < 1e-14
     assert np.max(np.abs(o.stage("ResG"))) < 1e-12 * np.max(G0)
+
+
+@pytest.mark.parametrize("body", ["sphere", "capsule"])
+def test_hexahedral_shell_meshes_are_valid(body):
+    """The hexahedral O-grid shells of the sphere and capsule workloads (small versions, 6 x 4 x 4 x 4 = 384
+    cells): every cell has positive sub-volumes, the wall and far-field faces are the 6 n_ang^2 quads of the inner
+    and outer layers (inner ones at the body radius, outer ones at r_far = 3), the shell's volume is that between
+    the two surfaces as the cells' faces enclose it (the divergence theorem over the boundary faces), and no two
+    cells that share a face have the same colour."""
+    n_ang, n_rad = 4, 4
+    b = mesh.sphere_body(0.5) if body == "sphere" else mesh.capsule_body()
+    m = mesh.shell_mesh(b, n_ang=n_ang, n_rad=n_rad, r_far=3.0, first_layer=0.03, seed=0, cells="hex",
+                        smooth_passes=0 if body == "sphere" else 4, jitter=0.1 if body == "sphere" else 0.03)
+    cells, kinds = m["cells"], m["kinds"]
+    assert len(cells) == 6 * n_ang * n_ang * n_rad and np.all(kinds == 8)
+    assert mesh._cells_valid(m["xyz"], cells, kinds)
+    tags = np.asarray(m["btag"])
+    assert np.sum(tags == 1) == 6 * n_ang ** 2 and np.sum(tags == 2) == 6 * n_ang ** 2
+    o, _ = _geometry(m)
+    g = o.geometry()
+    bnd = np.nonzero(g["fn"] < 0)[0]
+    r = np.linalg.norm(g["xf"][bnd] - np.asarray(m["centre"]), axis=1)
+    outer = r > 2.0
+    assert outer.sum() == 6 * n_ang ** 2 and np.all(r[~outer] < 1.0)
+    # volume by the divergence theorem over the boundary faces (x . n A / 3) against the cells' volume sum
+    vol_b = float(np.sum(np.einsum("ij,ij->i", g["xf"][bnd], g["n"][bnd]) * g["A"][bnd]) / 3.0)
+    assert abs(vol_b - g["V"].sum()) < 1e-10 * g["V"].sum() and g["V"].min() > 0
+    # colouring: the colour offsets split the (colour-major) cells, and no face joins two cells of one colour
+    off = np.asarray(m["color_offsets"])
+    colour = np.searchsorted(off, np.arange(len(cells)), side="right") - 1
+    interior = np.nonzero(g["fn"] >= 0)[0]
+    assert np.all(colour[g["fo"][interior]] != colour[g["fn"][interior]])
